@@ -1,0 +1,185 @@
+/*
+ * odmd.h -- online dynamic mode decomposition on one MI355X (gfx950).
+ *
+ * The library keeps, per snapshot stream, the online DMD of Sec. 2.3 of
+ * "Accelerating Flow Simulations using Online Dynamic Mode Decomposition"
+ * (arXiv 2311.18715): the truncated SVD U- = L S R^* of the input snapshot
+ * matrix, updated by one rank-1 column append per time step (Brand's
+ * incremental SVD, the paper's reference [brand2006fast]); the reduced
+ * operator A~ = L^* U+ R S^-1; its eigendecomposition A~ = V Lambda V^-1;
+ * and the prediction u(t) = Phi Lambda^(t/dt) Phi^+ u(0) with Phi = L V.
+ *
+ * Symbols used below: n is the state dimension (the paper's N), r the
+ * current rank, r_max its cap, U the n x r left basis (the paper's L),
+ * sigma the singular values, A~ the r x r reduced operator.
+ *
+ * Conventions for every call:
+ *   - Every call returns an odmd_status; nothing aborts the process.
+ *   - Arguments are checked on the host before any device work; a bad
+ *     argument returns ODMD_EINVAL and leaves the handle untouched.
+ *   - Pointers marked "device" must point to device memory of the GPU the
+ *     handle was created on; "host" pointers to ordinary host memory.
+ *   - Work is queued on the handle's HIP stream and returns before the GPU
+ *     finishes, unless the call is marked (synchronising).  Errors that the
+ *     GPU detects (non-finite input, unchained pair, no convergence) are
+ *     latched in the handle and returned, then cleared, by the next
+ *     synchronising call.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef ODMD_H
+#define ODMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct odmd_s* odmd_t;
+
+/* Element types.  ODMD_F64 / ODMD_F32 may be used for the basis and for
+ * snapshots; ODMD_BF16 only for the basis. */
+typedef enum { ODMD_F64 = 0, ODMD_F32 = 1, ODMD_BF16 = 2 } odmd_dtype;
+
+typedef enum {
+  ODMD_OK = 0,
+  ODMD_EINVAL = 1,     /* bad argument (checked on the host)              */
+  ODMD_ENOMEM = 2,     /* device allocation failed / workspace too small  */
+  ODMD_EEMPTY = 3,     /* eigs or predict on a rank-0 model               */
+  ODMD_ENONFINITE = 4, /* a snapshot held NaN/Inf; that update was skipped */
+  ODMD_ENOCONV = 5,    /* small SVD or eigen-iteration hit its sweep cap   */
+  ODMD_ESEQ = 6,       /* x_k was not the previous x_k+1; update skipped   */
+  ODMD_EDEVICE = 7     /* HIP runtime error or no usable device            */
+} odmd_status;
+
+/* Largest supported rank cap (the small FP64 problems live in one
+ * workgroup's LDS). */
+#define ODMD_RMAX 64
+
+/*
+ * Create a stream model with an FP64 basis and FP64 snapshots on the
+ * current device's null stream; the library allocates its own device
+ * memory.  n >= 1, 1 <= r_max <= min(n, ODMD_RMAX), 0 <= tol < 1.
+ * tol is relative and serves both tests of the method's rank choice
+ * (Sec. 2.3 leaves it open): a new direction is kept only if its residual
+ * norm exceeds tol * ||x_k||, and after each update only singular values
+ * above tol * sigma_1 are kept (at most r_max of them).
+ * On success *h receives the handle (host pointer to a host handle).
+ */
+odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
+
+/*
+ * As odmd_create, with the basis storage type, the snapshot (and
+ * prediction output) type, the HIP stream (hipStream_t, NULL = null
+ * stream) and optionally caller-owned device memory.
+ *   basis: ODMD_F64, ODMD_F32 (ODMD_BF16 returns ODMD_EINVAL until
+ *          supported).  For an FP32 basis the effective tolerance is
+ *          max(tol, 16 * 2^-24): FP32 storage cannot hold a direction
+ *          weaker than that.
+ *   io:    ODMD_F64 or ODMD_F32; must equal basis for F64/F32 bases.
+ *   workspace / workspace_bytes: NULL/0 to let the library allocate, else
+ *          a device buffer of at least odmd_state_bytes(...) bytes, 256-byte
+ *          aligned, owned by the caller and kept alive until odmd_destroy.
+ */
+odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
+                           odmd_dtype io, void* hip_stream, void* workspace,
+                           size_t workspace_bytes, odmd_t* h);
+
+/* Device bytes one handle needs (0 for invalid arguments). */
+size_t odmd_state_bytes(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io);
+
+/*
+ * Append one snapshot pair: x_k (a new column of U-) and x_k+1 (a new
+ * column of U+), Sec. 2.3, "only a single snapshot is appended to the
+ * snapshot matrix every iteration".  x_k, x_k1: device, n elements of the
+ * io type, contiguous; they must stay valid until the stream has run the
+ * update.  The first call initialises the model from x_k (Sec. 2.1).
+ * Later pairs must chain: x_k must equal, element for element, the x_k1 of
+ * the previous accepted update; otherwise the update is skipped and
+ * ODMD_ESEQ is latched.  Asynchronous.
+ */
+odmd_status odmd_update(odmd_t h, const void* x_k, const void* x_k1);
+
+/*
+ * Append one pair to each of `count` handles in one fused launch.  All
+ * handles must share one device and one HIP stream (that of hs[0]);
+ * duplicates are not allowed.  hs, xs, ys: host arrays of length count;
+ * xs[i], ys[i] are device pointers as in odmd_update.  Results are
+ * identical, bit for bit, to calling odmd_update on each handle.
+ * Asynchronous.
+ */
+odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* const* ys,
+                              int32_t count);
+
+/*
+ * Eigenpairs of A~ (synchronising).  cap: capacity of the output arrays
+ * (eigenvalue count; V arrays hold cap*cap doubles).  Outputs (host):
+ *   *r        current rank;
+ *   lam_re/im eigenvalues, |lambda| descending, then Im descending;
+ *   v_re/v_im nullable; column j (r doubles, leading dimension r) is the
+ *             eigenvector of lambda_j with unit 2-norm, scaled so that its
+ *             largest-modulus entry is real and positive.
+ * Returns ODMD_EEMPTY at rank 0, ODMD_EINVAL if cap < r.
+ */
+odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double* lam_im,
+                      double* v_re, double* v_im);
+
+/*
+ * Predicted states x_{a+1} .. x_{a+steps} where a is the time index of the
+ * last x_k1 (Sec. 2.3, u(t) = Phi Lambda^(t/dt) Phi^+ u(0), anchored at the
+ * last snapshot: Phi^+ u(0) = V^-1 U^T x_a).  out: device, steps x n, row
+ * k-1 holds state a+k, io type, row-major (row stride n).  steps >= 1.
+ * Asynchronous (the eigendecomposition it may need runs on the device).
+ */
+odmd_status odmd_predict(odmd_t h, int32_t steps, void* out);
+
+/* Wait for the handle's stream; return and clear a latched error. */
+odmd_status odmd_sync(odmd_t h);
+
+/* Free the handle and (unless caller-owned) its device memory. */
+odmd_status odmd_destroy(odmd_t h);
+
+const char* odmd_status_str(odmd_status s);
+
+/* ---- introspection (synchronising; for tests, diagnostics, benchmarks) ---- */
+
+typedef struct {
+  int32_t r;          /* current rank                                   */
+  int32_t r_max;
+  int64_t n;
+  int64_t m;          /* accepted pairs                                 */
+  double tol_eff;     /* tolerance in use (after the FP32 clamp)        */
+  double last_rho;    /* residual norm of the last accepted update      */
+  int32_t last_sweeps;/* Jacobi sweeps of the last small SVD            */
+  int32_t nblocks;    /* workgroups of the streaming pass               */
+} odmd_info;
+
+odmd_status odmd_get_info(odmd_t h, odmd_info* info);
+
+/*
+ * Copy the small state to host arrays (any may be NULL): sigma (r),
+ * A~ (r x r, column-major, leading dimension r), p_y = U^T x_a (r),
+ * C (r x r, column-major) and w (r), the shifted product of the right
+ * singular vectors and their last row.
+ */
+odmd_status odmd_get_state(odmd_t h, int32_t cap, double* sigma, double* atilde, double* p_y,
+                           double* C, double* w);
+
+/* The current basis U as FP64, device out: n x r column-major with
+ * leading dimension n (needs n * r_max doubles).  Asynchronous. */
+odmd_status odmd_get_basis(odmd_t h, double* out);
+
+/*
+ * Kernel timing.  odmd_profile(h, 1) makes every later update record HIP
+ * events on the handle's stream around its streaming pass and around its
+ * small-SVD phase; odmd_profile_read (synchronising) returns the summed
+ * durations in milliseconds and the number of timed updates, then resets.
+ */
+odmd_status odmd_profile(odmd_t h, int32_t enable);
+odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ODMD_H */

@@ -1,0 +1,431 @@
+// Host runtime behind the C ABI declared in include/odmd.h.
+//
+// Every entry point validates its arguments on the host before touching the
+// device, queues its kernels on the handle's HIP stream, and reports HIP
+// runtime failures as ODMD_EDEVICE.  Errors that only the GPU can see are
+// latched in DevState::status and surface at the next synchronising call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "odmd.h"
+#include "odmd_internal.h"
+#include "pass.h"
+
+using namespace odmd;
+
+struct odmd_s {
+  int64_t n = 0, ld = 0;
+  int r_max = 0, rb = 0;
+  double tol = 0.0, tol_eff = 0.0;
+  odmd_dtype basis = ODMD_F64, io = ODMD_F64;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* mem = nullptr;
+  size_t bytes = 0;
+  bool own = false;
+  DevState* st = nullptr;
+  double* partials = nullptr;
+  void* Us = nullptr;
+  void* Es = nullptr;
+  int nblk = 0, tiles = 0;
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // triples: before pass, after pass, after core
+  size_t ev_used = 0;
+};
+
+namespace {
+
+struct Layout {
+  size_t st = 0, partials = 0, Us = 0, Es = 0, total = 0;
+  int64_t ld = 0;
+  int nblk = 0, tiles = 0;
+};
+
+int elem_bytes(odmd_dtype t) { return t == ODMD_F64 ? 8 : (t == ODMD_F32 ? 4 : 2); }
+
+bool valid_types(odmd_dtype basis, odmd_dtype io) {
+  if (basis != ODMD_F64 && basis != ODMD_F32) return false;   // BF16 storage not yet offered
+  return io == basis;
+}
+
+bool valid_args(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dtype io) {
+  if (n < 1 || n > (int64_t(1) << 40)) return false;
+  if (r_max < 1 || r_max > RMAX || (int64_t)r_max > n) return false;
+  if (!std::isfinite(tol) || tol < 0.0 || tol >= 1.0) return false;
+  return valid_types(basis, io);
+}
+
+Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis) {
+  Layout L;
+  L.ld = round_up(n, 64);
+  L.tiles = (int)((n + PASS_THREADS - 1) / PASS_THREADS);
+  L.nblk = std::min(L.tiles, PASS_MAX_BLOCKS);
+  size_t off = 0;
+  L.st = off;
+  off += round_up(sizeof(DevState), 256);
+  L.partials = off;
+  off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
+  L.Us = off;
+  off += round_up((int64_t)r_max * L.ld * elem_bytes(basis), 256);
+  L.Es = off;
+  off += round_up(L.ld * elem_bytes(basis), 256);
+  L.total = off;
+  return L;
+}
+
+int rank_bucket(int r_max) { return (r_max + 7) / 8 * 8; }
+
+odmd_status map_status(int bits) {
+  if (bits & ST_NONFINITE) return ODMD_ENONFINITE;
+  if (bits & ST_SEQ) return ODMD_ESEQ;
+  if (bits & ST_NOCONV) return ODMD_ENOCONV;
+  if (bits & ST_EMPTY) return ODMD_EEMPTY;
+  return ODMD_OK;
+}
+
+#define HIP_OK(expr)                        \
+  do {                                      \
+    if ((expr) != hipSuccess) {             \
+      (void)hipGetLastError();              \
+      return ODMD_EDEVICE;                  \
+    }                                       \
+  } while (0)
+
+// Wait for the stream, then fetch and clear the latched device status.
+odmd_status sync_and_status(odmd_t h) {
+  HIP_OK(hipStreamSynchronize(h->stream));
+  int bits = 0;
+  HIP_OK(hipMemcpy(&bits, &h->st->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (bits) {
+    const int zero = 0;
+    HIP_OK(hipMemcpy(&h->st->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+  }
+  return map_status(bits);
+}
+
+template <typename T>
+odmd_status copy_field(odmd_t h, T* dst, const T* src_dev, size_t count) {
+  HIP_OK(hipMemcpyAsync(dst, src_dev, count * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+  return ODMD_OK;
+}
+
+odmd_status launch_update(odmd_t h, const void* x, const void* y) {
+  hipEvent_t* ev = nullptr;
+  if (h->prof) {
+    if (h->ev_used + 3 > h->ev.size()) {
+      for (int k = 0; k < 3; ++k) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        h->ev.push_back(e);
+      }
+    }
+    ev = &h->ev[h->ev_used];
+    h->ev_used += 3;
+    HIP_OK(hipEventRecord(ev[0], h->stream));
+  }
+  PassArgs p;
+  p.Us = h->Us;
+  p.Es = h->Es;
+  p.x = x;
+  p.y = y;
+  p.partials = h->partials;
+  p.st = h->st;
+  p.n = h->n;
+  p.ld = h->ld;
+  p.nblk = h->nblk;
+  p.tiles = h->tiles;
+  HIP_OK(launch_pass(p, h->basis == ODMD_F64, h->rb, h->stream));
+  if (ev) HIP_OK(hipEventRecord(ev[1], h->stream));
+  CoreArgs c;
+  c.st = h->st;
+  c.partials = h->partials;
+  c.nblk = h->nblk;
+  c.r_max = h->r_max;
+  c.basis_f32 = h->basis == ODMD_F32;
+  HIP_OK(launch_core(c, h->stream));
+  if (ev) HIP_OK(hipEventRecord(ev[2], h->stream));
+  return ODMD_OK;
+}
+
+odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool out_f32) {
+  CombineArgs c;
+  c.st = h->st;
+  c.Us = h->Us;
+  c.Es = h->Es;
+  c.out = out;
+  c.n = h->n;
+  c.ld = h->ld;
+  c.ldo = ldo;
+  c.K = K;
+  const int64_t xb = (h->n + 255) / 256;
+  int ysplit = (int)std::max<int64_t>(1, (1024 + xb - 1) / xb);
+  ysplit = std::min(ysplit, std::max(1, (K + 7) / 8));
+  c.kb = (K + ysplit - 1) / ysplit;
+  HIP_OK(launch_combine(c, h->basis == ODMD_F64, out_f32, h->rb, h->stream));
+  return ODMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* odmd_status_str(odmd_status s) {
+  switch (s) {
+    case ODMD_OK: return "ok";
+    case ODMD_EINVAL: return "invalid argument";
+    case ODMD_ENOMEM: return "out of device memory or workspace too small";
+    case ODMD_EEMPTY: return "model has rank 0";
+    case ODMD_ENONFINITE: return "non-finite snapshot (update skipped)";
+    case ODMD_ENOCONV: return "iteration cap reached";
+    case ODMD_ESEQ: return "snapshot pair does not chain (update skipped)";
+    case ODMD_EDEVICE: return "HIP device error";
+  }
+  return "unknown status";
+}
+
+size_t odmd_state_bytes(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io) {
+  if (!valid_args(n, r_max, 0.0, basis, io)) return 0;
+  return make_layout(n, r_max, basis).total;
+}
+
+odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dtype io,
+                           void* hip_stream, void* workspace, size_t workspace_bytes, odmd_t* h) {
+  if (!h) return ODMD_EINVAL;
+  *h = nullptr;
+  if (!valid_args(n, r_max, tol, basis, io)) return ODMD_EINVAL;
+  const Layout L = make_layout(n, r_max, basis);
+  if (workspace) {
+    if (workspace_bytes < L.total) return ODMD_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return ODMD_EINVAL;
+  } else if (workspace_bytes != 0) {
+    return ODMD_EINVAL;
+  }
+  odmd_s* s = new (std::nothrow) odmd_s;
+  if (!s) return ODMD_ENOMEM;
+  s->n = n;
+  s->ld = L.ld;
+  s->r_max = r_max;
+  s->rb = rank_bucket(r_max);
+  s->tol = tol;
+  s->tol_eff = basis == ODMD_F32 ? std::max(tol, 16.0 * 5.9604644775390625e-08) : tol;
+  s->basis = basis;
+  s->io = io;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->nblk = L.nblk;
+  s->tiles = L.tiles;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return ODMD_EDEVICE;
+  }
+  if (workspace) {
+    s->mem = static_cast<char*>(workspace);
+  } else {
+    if (hipMalloc(&s->mem, L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete s;
+      return ODMD_ENOMEM;
+    }
+    s->own = true;
+  }
+  s->bytes = L.total;
+  s->st = reinterpret_cast<DevState*>(s->mem + L.st);
+  s->partials = reinterpret_cast<double*>(s->mem + L.partials);
+  s->Us = s->mem + L.Us;
+  s->Es = s->mem + L.Es;
+  const double tol_eff = s->tol_eff;
+  if (hipMemsetAsync(s->mem, 0, L.total, s->stream) != hipSuccess ||
+      hipMemcpyAsync(&s->st->tol, &tol_eff, sizeof(double), hipMemcpyHostToDevice, s->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (s->own) (void)hipFree(s->mem);
+    delete s;
+    return ODMD_EDEVICE;
+  }
+  *h = s;
+  return ODMD_OK;
+}
+
+odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h) {
+  return odmd_create_ex(n, r_max, tol, ODMD_F64, ODMD_F64, nullptr, nullptr, 0, h);
+}
+
+odmd_status odmd_update(odmd_t h, const void* x_k, const void* x_k1) {
+  if (!h || !x_k || !x_k1) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  return launch_update(h, x_k, x_k1);
+}
+
+odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* const* ys,
+                              int32_t count) {
+  if (!hs || !xs || !ys || count < 0) return ODMD_EINVAL;
+  if (count == 0) return ODMD_OK;
+  std::unordered_set<odmd_t> seen;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i] || !xs[i] || !ys[i]) return ODMD_EINVAL;
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return ODMD_EINVAL;
+    if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
+  }
+  HIP_OK(hipSetDevice(hs[0]->device));
+  for (int32_t i = 0; i < count; ++i) {
+    const odmd_status s = launch_update(hs[i], xs[i], ys[i]);
+    if (s != ODMD_OK) return s;
+  }
+  return ODMD_OK;
+}
+
+odmd_status odmd_sync(odmd_t h) {
+  if (!h) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  return sync_and_status(h);
+}
+
+odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double* lam_im,
+                      double* v_re, double* v_im) {
+  if (!h || !r || !lam_re || !lam_im || cap < 0) return ODMD_EINVAL;
+  if ((v_re == nullptr) != (v_im == nullptr)) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(launch_eig(h->st, h->stream));
+  int rr = 0;
+  std::vector<double> lr(RMAX), li(RMAX), vr, vi;
+  odmd_status s;
+  if ((s = copy_field(h, &rr, &h->st->r, 1)) != ODMD_OK) return s;
+  if ((s = copy_field(h, lr.data(), h->st->lam_re, RMAX)) != ODMD_OK) return s;
+  if ((s = copy_field(h, li.data(), h->st->lam_im, RMAX)) != ODMD_OK) return s;
+  if (v_re) {
+    vr.resize(RMAX * RMAX);
+    vi.resize(RMAX * RMAX);
+    if ((s = copy_field(h, vr.data(), h->st->V_re, RMAX * RMAX)) != ODMD_OK) return s;
+    if ((s = copy_field(h, vi.data(), h->st->V_im, RMAX * RMAX)) != ODMD_OK) return s;
+  }
+  s = sync_and_status(h);
+  *r = rr;
+  if (s != ODMD_OK) return s;
+  if (rr == 0) return ODMD_EEMPTY;
+  if (cap < rr) return ODMD_EINVAL;
+  for (int k = 0; k < rr; ++k) {
+    lam_re[k] = lr[k];
+    lam_im[k] = li[k];
+  }
+  if (v_re) {
+    for (int j = 0; j < rr; ++j)
+      for (int i = 0; i < rr; ++i) {
+        v_re[j * rr + i] = vr[j * RMAX + i];
+        v_im[j * rr + i] = vi[j * RMAX + i];
+      }
+  }
+  return ODMD_OK;
+}
+
+odmd_status odmd_predict(odmd_t h, int32_t steps, void* out) {
+  if (!h || !out || steps < 1) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(launch_eig(h->st, h->stream));
+  const int es = elem_bytes(h->io);
+  for (int k0 = 0; k0 < steps; k0 += COEF_CHUNK) {
+    const int K = std::min(COEF_CHUNK, steps - k0);
+    HIP_OK(launch_predict_coef(h->st, k0, K, h->stream));
+    char* o = static_cast<char*>(out) + (int64_t)k0 * h->n * es;
+    const odmd_status s = launch_combine_cols(h, o, h->n, K, h->io == ODMD_F32);
+    if (s != ODMD_OK) return s;
+  }
+  return ODMD_OK;
+}
+
+odmd_status odmd_get_basis(odmd_t h, double* out) {
+  if (!h || !out) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(launch_basis_coef(h->st, h->stream));
+  return launch_combine_cols(h, out, h->n, h->r_max, false);
+}
+
+odmd_status odmd_get_info(odmd_t h, odmd_info* info) {
+  if (!h || !info) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  DevState hdr;
+  const size_t nbytes = offsetof(DevState, pad_);
+  HIP_OK(hipMemcpyAsync(&hdr, h->st, nbytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  info->r = hdr.r;
+  info->r_max = h->r_max;
+  info->n = h->n;
+  info->m = hdr.m;
+  info->tol_eff = h->tol_eff;
+  info->last_rho = hdr.last_rho;
+  info->last_sweeps = hdr.sweeps;
+  info->nblocks = h->nblk;
+  return ODMD_OK;
+}
+
+odmd_status odmd_get_state(odmd_t h, int32_t cap, double* sigma, double* atilde, double* p_y,
+                           double* C, double* w) {
+  if (!h || cap < 0) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  int rr = 0;
+  std::vector<double> sg(RMAX), py(RMAX), ww(RMAX), at(RMAX * RMAX), cc(RMAX * RMAX);
+  odmd_status s;
+  if ((s = copy_field(h, &rr, &h->st->r, 1)) != ODMD_OK) return s;
+  if ((s = copy_field(h, sg.data(), h->st->sigma, RMAX)) != ODMD_OK) return s;
+  if ((s = copy_field(h, py.data(), h->st->py, RMAX)) != ODMD_OK) return s;
+  if ((s = copy_field(h, ww.data(), h->st->w, RMAX)) != ODMD_OK) return s;
+  if ((s = copy_field(h, at.data(), h->st->At, RMAX * RMAX)) != ODMD_OK) return s;
+  if ((s = copy_field(h, cc.data(), h->st->C, RMAX * RMAX)) != ODMD_OK) return s;
+  HIP_OK(hipStreamSynchronize(h->stream));
+  if (cap < rr) return ODMD_EINVAL;
+  for (int i = 0; i < rr; ++i) {
+    if (sigma) sigma[i] = sg[i];
+    if (p_y) p_y[i] = py[i];
+    if (w) w[i] = ww[i];
+    for (int j = 0; j < rr; ++j) {
+      if (atilde) atilde[j * rr + i] = at[j * RMAX + i];
+      if (C) C[j * rr + i] = cc[j * RMAX + i];
+    }
+  }
+  return ODMD_OK;
+}
+
+odmd_status odmd_profile(odmd_t h, int32_t enable) {
+  if (!h) return ODMD_EINVAL;
+  h->prof = enable != 0;
+  return ODMD_OK;
+}
+
+odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_t* count) {
+  if (!h || !pass_ms || !core_ms || !count) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  double a = 0.0, b = 0.0;
+  for (size_t k = 0; k + 3 <= h->ev_used; k += 3) {
+    float t1 = 0.f, t2 = 0.f;
+    HIP_OK(hipEventElapsedTime(&t1, h->ev[k], h->ev[k + 1]));
+    HIP_OK(hipEventElapsedTime(&t2, h->ev[k + 1], h->ev[k + 2]));
+    a += t1;
+    b += t2;
+  }
+  *pass_ms = a;
+  *core_ms = b;
+  *count = (int64_t)(h->ev_used / 3);
+  h->ev_used = 0;
+  return ODMD_OK;
+}
+
+odmd_status odmd_destroy(odmd_t h) {
+  if (!h) return ODMD_EINVAL;
+  odmd_status s = ODMD_OK;
+  if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+    s = ODMD_EDEVICE;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->own && hipFree(h->mem) != hipSuccess) s = ODMD_EDEVICE;
+  (void)hipGetLastError();
+  delete h;
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""Python binding of the C ABI in include/odmd.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libodmd.so``; this module
+only converts torch tensors to device pointers and host arrays to ctypes
+buffers.  If the library is not built, importing the binding's functions
+raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libodmd.so")
+RMAX = 64
+
+F64, F32, BF16 = 0, 1, 2
+STATUS = {
+    0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EEMPTY", 4: "ENONFINITE",
+    5: "ENOCONV", 6: "ESEQ", 7: "EDEVICE",
+}
+EXPORTS = [
+    "odmd_create", "odmd_create_ex", "odmd_state_bytes", "odmd_update", "odmd_update_batch",
+    "odmd_eigs", "odmd_predict", "odmd_sync", "odmd_destroy", "odmd_status_str",
+    "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
+]
+
+
+class OdmdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{where}: {self.name} ({lib().odmd_status_str(code).decode()})")
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("r", ctypes.c_int32), ("r_max", ctypes.c_int32), ("n", ctypes.c_int64),
+        ("m", ctypes.c_int64), ("tol_eff", ctypes.c_double), ("last_rho", ctypes.c_double),
+        ("last_sweeps", ctypes.c_int32), ("nblocks", ctypes.c_int32),
+    ]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libodmd.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2311_18715_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        pd = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "odmd_create": ([i64, i32, dbl, ctypes.POINTER(vp)], ctypes.c_int),
+            "odmd_create_ex": ([i64, i32, dbl, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_size_t,
+                                ctypes.POINTER(vp)], ctypes.c_int),
+            "odmd_state_bytes": ([i64, i32, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+            "odmd_update": ([vp, vp, vp], ctypes.c_int),
+            "odmd_update_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32],
+                                  ctypes.c_int),
+            "odmd_eigs": ([vp, i32, ctypes.POINTER(i32), pd, pd, pd, pd], ctypes.c_int),
+            "odmd_predict": ([vp, i32, vp], ctypes.c_int),
+            "odmd_sync": ([vp], ctypes.c_int),
+            "odmd_destroy": ([vp], ctypes.c_int),
+            "odmd_status_str": ([ctypes.c_int], ctypes.c_char_p),
+            "odmd_get_info": ([vp, ctypes.POINTER(Info)], ctypes.c_int),
+            "odmd_get_state": ([vp, i32, pd, pd, pd, pd, pd], ctypes.c_int),
+            "odmd_get_basis": ([vp, vp], ctypes.c_int),
+            "odmd_profile": ([vp, i32], ctypes.c_int),
+            "odmd_profile_read": ([vp, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise OdmdError(code, where)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    """Device pointer of a contiguous CUDA (HIP) tensor."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dbl(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class ODMD:
+    """One online-DMD stream on the GPU (a handle of the C library).
+
+    Parameters mirror ``odmd_create_ex``: state size n, rank cap r_max,
+    relative tolerance tol, basis storage ('f64' | 'f32'), snapshot type
+    (defaults to the basis type), torch stream (defaults to the current
+    one) and an optional caller-owned uint8 device workspace.
+    """
+
+    def __init__(self, n: int, r_max: int, tol: float, basis: str = "f64", io: str | None = None,
+                 stream=None, workspace=None):
+        import torch
+        self._torch = torch
+        bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
+        it = {"f64": F64, "f32": F32}[io or basis]
+        self.n, self.r_max, self.basis, self.io = int(n), int(r_max), basis, io or basis
+        self.dtype = torch.float64 if self.io == "f64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        ws, wsb = None, 0
+        if workspace is not None:
+            ws, wsb = _dptr(workspace), workspace.numel() * workspace.element_size()
+        _check(lib().odmd_create_ex(self.n, self.r_max, float(tol), bt, it,
+                                    ctypes.c_void_p(stream.cuda_stream), ws, wsb,
+                                    ctypes.byref(h)), "odmd_create_ex")
+        self._h = h
+        self._workspace = workspace
+
+    @staticmethod
+    def state_bytes(n: int, r_max: int, basis: str = "f64", io: str | None = None) -> int:
+        bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
+        it = {"f64": F64, "f32": F32}[io or basis]
+        return int(lib().odmd_state_bytes(int(n), int(r_max), bt, it))
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def update(self, x, y) -> None:
+        _check(lib().odmd_update(self._h, _dptr(x), _dptr(y)), "odmd_update")
+
+    def sync(self) -> None:
+        _check(lib().odmd_sync(self._h), "odmd_sync")
+
+    def eigs(self, vectors: bool = True):
+        """(lam, V): complex eigenvalues (r,) and eigenvectors (r, r) of A~."""
+        r = ctypes.c_int32()
+        lr, li = np.zeros(RMAX), np.zeros(RMAX)
+        vr = np.zeros(RMAX * RMAX) if vectors else None
+        vi = np.zeros(RMAX * RMAX) if vectors else None
+        _check(lib().odmd_eigs(self._h, RMAX, ctypes.byref(r), _dbl(lr), _dbl(li),
+                               _dbl(vr) if vectors else None, _dbl(vi) if vectors else None),
+               "odmd_eigs")
+        k = r.value
+        lam = lr[:k] + 1j * li[:k]
+        if not vectors:
+            return lam, None
+        V = (vr[:k * k] + 1j * vi[:k * k]).reshape(k, k).T     # column j = vector j
+        return lam, V
+
+    def predict(self, steps: int, out=None):
+        """Predicted states a+1..a+steps as a (steps, n) device tensor."""
+        if out is None:
+            out = self._torch.empty((steps, self.n), dtype=self.dtype, device="cuda")
+        _check(lib().odmd_predict(self._h, int(steps), _dptr(out)), "odmd_predict")
+        return out
+
+    def info(self) -> Info:
+        i = Info()
+        _check(lib().odmd_get_info(self._h, ctypes.byref(i)), "odmd_get_info")
+        return i
+
+    def state(self) -> dict:
+        """Small FP64 state copied to the host: sigma, atilde, p_y, C, w."""
+        k = self.info().r
+        s, a, p = np.zeros(RMAX), np.zeros(RMAX * RMAX), np.zeros(RMAX)
+        c, w = np.zeros(RMAX * RMAX), np.zeros(RMAX)
+        _check(lib().odmd_get_state(self._h, RMAX, _dbl(s), _dbl(a), _dbl(p), _dbl(c), _dbl(w)),
+               "odmd_get_state")
+        return {
+            "r": k, "sigma": s[:k].copy(), "p_y": p[:k].copy(), "w": w[:k].copy(),
+            "atilde": a[:k * k].reshape(k, k).T.copy(), "C": c[:k * k].reshape(k, k).T.copy(),
+        }
+
+    def basis_matrix(self):
+        """The current basis U as an (n, r) FP64 device tensor."""
+        out = self._torch.empty((self.r_max, self.n), dtype=self._torch.float64, device="cuda")
+        _check(lib().odmd_get_basis(self._h, _dptr(out)), "odmd_get_basis")
+        k = self.info().r
+        return out[:k].T
+
+    def profile(self, enable: bool = True) -> None:
+        _check(lib().odmd_profile(self._h, int(enable)), "odmd_profile")
+
+    def profile_read(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().odmd_profile_read(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "odmd_profile_read")
+        return a.value, b.value, c.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            code = lib().odmd_destroy(self._h)
+            self._h = None
+            _check(code, "odmd_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def update_batch(models, xs, ys) -> None:
+    """One fused update of several streams (odmd_update_batch)."""
+    n = len(models)
+    H = (ctypes.c_void_p * n)(*[m.handle for m in models])
+    X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
+    Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
+    _check(lib().odmd_update_batch(H, X, Y, n), "odmd_update_batch")

@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function include/odmd.h declares, and
+reject bad arguments on the host before any device call.  The product
+package must never reach the CPU oracle.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2311_18715_amd import odmd as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "odmd.h")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="libodmd.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(odmd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for core in ["odmd_create", "odmd_update", "odmd_eigs", "odmd_predict", "odmd_destroy"]:
+        assert core in names
+    assert set(names) == set(B.EXPORTS)
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+@needs_lib
+def test_state_bytes_is_host_only():
+    L = B.lib()
+    n64 = L.odmd_state_bytes(160000, 40, B.F64, B.F64)
+    n32 = L.odmd_state_bytes(160000, 40, B.F32, B.F32)
+    assert n64 > 160000 * 40 * 8 and n32 > 160000 * 40 * 4
+    assert n64 - n32 >= 160000 * 41 * 4 - 4096
+    assert L.odmd_state_bytes(0, 4, B.F64, B.F64) == 0
+    assert L.odmd_state_bytes(100, 65, B.F64, B.F64) == 0       # above the rank cap
+    assert L.odmd_state_bytes(10, 11, B.F64, B.F64) == 0        # r_max > n
+    assert L.odmd_state_bytes(100, 8, B.F64, B.F32) == 0        # io must match basis
+    assert L.odmd_state_bytes(100, 8, B.BF16, B.F32) == 0       # not offered
+
+
+@needs_lib
+@pytest.mark.parametrize("n,r_max,tol", [
+    (0, 4, 1e-8), (-5, 4, 1e-8), (100, 0, 1e-8), (100, 65, 1e-8), (5, 6, 1e-8),
+    (100, 4, -1e-3), (100, 4, 1.0), (100, 4, float("nan")), (100, 4, float("inf")),
+])
+def test_create_rejects_bad_arguments(n, r_max, tol):
+    h = ctypes.c_void_p(12345)
+    assert B.lib().odmd_create(n, r_max, tol, ctypes.byref(h)) == 1     # ODMD_EINVAL
+    assert h.value is None                                              # *h cleared
+
+
+@needs_lib
+def test_null_arguments_are_rejected():
+    L = B.lib()
+    assert L.odmd_create(100, 4, 1e-8, None) == 1
+    assert L.odmd_update(None, None, None) == 1
+    assert L.odmd_sync(None) == 1
+    assert L.odmd_destroy(None) == 1
+    assert L.odmd_predict(None, 5, None) == 1
+    assert L.odmd_update_batch(None, None, None, 1) == 1
+    r = ctypes.c_int32()
+    assert L.odmd_eigs(None, 4, ctypes.byref(r), None, None, None, None) == 1
+    assert L.odmd_get_info(None, None) == 1
+    assert L.odmd_profile(None, 1) == 1
+
+
+@needs_lib
+def test_workspace_checks_happen_before_device_use():
+    L = B.lib()
+    h = ctypes.c_void_p()
+    need = L.odmd_state_bytes(1000, 8, B.F64, B.F64)
+    # too small a workspace, misaligned workspace, bytes without a buffer
+    assert L.odmd_create_ex(1000, 8, 1e-8, B.F64, B.F64, None, ctypes.c_void_p(4096), need - 1,
+                            ctypes.byref(h)) == 2
+    assert L.odmd_create_ex(1000, 8, 1e-8, B.F64, B.F64, None, ctypes.c_void_p(4096 + 8), need,
+                            ctypes.byref(h)) == 1
+    assert L.odmd_create_ex(1000, 8, 1e-8, B.F64, B.F64, None, None, 64, ctypes.byref(h)) == 1
+
+
+@needs_lib
+def test_status_strings():
+    L = B.lib()
+    for code in range(8):
+        assert len(L.odmd_status_str(code)) > 0
+    assert L.odmd_status_str(99) == b"unknown status"
+
+
+def test_product_never_reaches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2311_18715_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), f
+                assert "odmd_oracle" not in text, f

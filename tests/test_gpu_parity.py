@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Inputs come from the seeded generators in paper_2311_18715_amd.synth and
+feed both sides.  Tolerances (FP64 path): eigenvalues 1e-10 relative
+(eigenvalues with |lambda| >= 1e-2 max|lambda|), singular values 1e-11
+relative, orthogonality ||U^T U - I||_F <= 1e-12, rollouts 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import odmd_oracle as O
+from paper_2311_18715_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2311_18715_amd.odmd import ODMD, OdmdError
+
+
+def dev(X, dtype=None):
+    """Snapshots as rows of a device tensor: row k is x_k."""
+    return torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda", dtype or torch.float64)
+
+
+def run_both(X, r_max, tol, steps=None, basis="f64", check_every=0):
+    m = X.shape[1] - 1 if steps is None else steps
+    g = ODMD(X.shape[0], r_max, tol, basis=basis)
+    o = O.OnlineDMD(X.shape[0], r_max, g.info().tol_eff)
+    Xd = dev(X, torch.float64 if basis == "f64" else torch.float32)
+    Xo = X if basis == "f64" else Xd.double().cpu().numpy().T
+    for k in range(m):
+        g.update(Xd[k], Xd[k + 1])
+        o.update(Xo[:, k], Xo[:, k + 1])
+        if check_every and (k % check_every == 0 or k == m - 1):
+            s = g.state()
+            assert s["r"] == o.r, f"rank differs at step {k}"
+            np.testing.assert_allclose(s["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
+    g.sync()
+    return g, o
+
+
+def rel_eig_err(ref, got, floor=1e-2):
+    big = np.abs(ref) >= floor * np.abs(ref).max()
+    m = O.match_eigs(ref[big], got)
+    return np.max(np.abs(m - ref[big]) / np.abs(ref[big]))
+
+
+def orth_err(g):
+    U = g.basis_matrix()
+    return torch.linalg.norm(U.T @ U - torch.eye(U.shape[1], dtype=U.dtype, device=U.device)).item()
+
+
+def test_planted_small_every_step():
+    """n=4096, rank 6, r_max 20, tol 1e-8, 399 pairs: rank and sigma each step."""
+    s = synth.planted_small()
+    X = s.snapshots(0, 400)
+    g, o = run_both(X, 20, 1e-8, check_every=1)
+    assert g.info().r == 6
+    lam, V = g.eigs()
+    lo, Vo = o.eigs()
+    assert rel_eig_err(lo, lam) < 1e-10
+    assert rel_eig_err(s.planted_eigs(), lam) < 1e-10
+    # eigenvectors: unit norm, A~ V = V Lambda with the GPU's own A~
+    st = g.state()
+    np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, rtol=1e-12)
+    assert np.max(np.abs(st["atilde"] @ V - V * lam[None, :])) < 1e-10
+    assert orth_err(g) < 1e-12
+    # U A~ U^T is basis-independent: compare on random probes
+    U = g.basis_matrix().cpu().numpy()
+    P = np.random.default_rng(0).standard_normal((X.shape[0], 4))
+    Pg = U @ (st["atilde"] @ (U.T @ P))
+    Po = o.U @ (o.atilde() @ (o.U.T @ P))
+    assert np.max(np.abs(Pg - Po)) < 1e-10 * np.max(np.abs(Po))
+
+
+def test_planted_small_rollout():
+    s = synth.planted_small()
+    X = s.snapshots(0, 400)
+    g, o = run_both(X, 20, 1e-8)
+    pred = g.predict(500)
+    g.sync()
+    pg = pred.cpu().numpy()
+    po = o.predict(500)
+    fut = s.clean(400, 900).T
+    err_o = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)
+    err_f = np.linalg.norm(pg - fut, axis=1) / np.linalg.norm(fut, axis=1)
+    assert err_o.max() < 1e-9
+    assert err_f.max() < 1e-9
+
+
+@pytest.mark.parametrize("nx,ny,r_max", [(60, 40, 40), (173, 97, 32), (7, 5, 24)])
+def test_wake_ragged_sizes(nx, ny, r_max):
+    """Noisy wake stream, n not a multiple of the tile size, truncation active."""
+    s = synth.wake(nx=nx, ny=ny, noise=1e-6)
+    X = s.snapshots(0, 200)
+    g, o = run_both(X, r_max, 1e-8, check_every=25)
+    lam, _ = g.eigs()
+    lo, _ = o.eigs()
+    # planted (mean flow and shedding harmonics) eigenvalues agree to 1e-10
+    pl = s.planted_eigs()[:11]
+    mg, mo = O.match_eigs(pl, lam), O.match_eigs(pl, lo)
+    assert np.max(np.abs(mg - mo) / np.abs(mo)) < 1e-10
+    assert orth_err(g) < 1e-12
+
+
+def test_determinism_bitwise():
+    s = synth.wake(nx=50, ny=30, noise=1e-6)
+    X = s.snapshots(0, 80)
+    Xd = dev(X)
+    runs = []
+    for _ in range(2):
+        g = ODMD(X.shape[0], 24, 1e-8)
+        for k in range(79):
+            g.update(Xd[k], Xd[k + 1])
+        st = g.state()
+        runs.append((st["sigma"], st["atilde"], g.basis_matrix().cpu().numpy()))
+        g.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_scalar_and_tiny_streams():
+    g = np.random.default_rng(7)
+    X = g.standard_normal((1, 40))
+    gp, o = run_both(X, 1, 1e-12)
+    st = gp.state()
+    x, y = X[0, :-1], X[0, 1:]
+    np.testing.assert_allclose(st["atilde"][0, 0], x @ y / (x @ x), rtol=1e-13)
+    # n below one tile, rank cap = n
+    X = g.standard_normal((9, 30))
+    gp, o = run_both(X, 9, 1e-12, check_every=3)
+    assert gp.info().r == 9
+    A = X[:, 1:] @ np.linalg.pinv(X[:, :-1])
+    U = gp.basis_matrix().cpu().numpy()
+    assert np.max(np.abs(U @ gp.state()["atilde"] @ U.T - A)) < 1e-10 * np.max(np.abs(A))
+
+
+def test_rank_cap_64():
+    g = np.random.default_rng(8)
+    X = g.standard_normal((3000, 90))
+    gp, o = run_both(X, 64, 1e-12, check_every=10)
+    assert gp.info().r == 64
+    assert orth_err(gp) < 1e-12
+    lam, _ = gp.eigs()
+    assert rel_eig_err(np.linalg.eigvals(o.atilde()), lam, floor=0.1) < 1e-9
+
+
+def test_zero_snapshots_and_empty_model():
+    n = 700
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    x = torch.randn(n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    g = ODMD(n, 8, 1e-8)
+    g.update(z, z)                      # zero first snapshot: stays empty
+    g.sync()
+    assert g.info().r == 0
+    with pytest.raises(OdmdError) as e:
+        g.eigs()
+    assert e.value.name == "EEMPTY"
+    g.predict(3)
+    with pytest.raises(OdmdError):
+        g.sync()                        # latched EEMPTY from the prediction
+    g.update(z, x)                      # chained (x_k = previous x_k+1 = 0)
+    g.update(x, 2 * x)
+    g.sync()
+    assert g.info().r == 1
+    g.update(2 * x, z)                  # in span: rank unchanged
+    g.update(z, z)                      # zero pair: rank unchanged, w -> 0
+    g.sync()
+    st = g.state()
+    assert st["r"] == 1 and st["w"][0] == 0.0
+
+
+def test_nonfinite_and_unchained_are_skipped():
+    s = synth.planted_small(n=1000)
+    X = s.snapshots(0, 30)
+    Xd = dev(X)
+    g = ODMD(1000, 10, 1e-8)
+    for k in range(20):
+        g.update(Xd[k], Xd[k + 1])
+    g.sync()
+    before = g.state()
+    bad = Xd[21].clone()
+    bad[17] = float("nan")
+    g.update(Xd[20], bad)
+    with pytest.raises(OdmdError) as e:
+        g.sync()
+    assert e.value.name == "ENONFINITE"
+    after = g.state()
+    np.testing.assert_array_equal(before["sigma"], after["sigma"])
+    g.update(Xd[5], Xd[6])              # does not chain to the last accepted pair
+    with pytest.raises(OdmdError) as e:
+        g.sync()
+    assert e.value.name == "ESEQ"
+    # the stream resumes where it was and matches an oracle that skipped both
+    o = O.OnlineDMD(1000, 10, 1e-8)
+    for k in range(25):
+        o.update(X[:, k], X[:, k + 1])
+    for k in range(20, 25):
+        g.update(Xd[k], Xd[k + 1])
+    g.sync()
+    np.testing.assert_allclose(g.state()["sigma"], o.sigma, rtol=1e-12)
+
+
+def test_full_size_wake_prefix():
+    """n = 160,000 (400 x 200 grid), r_max 40, the launch the benchmark times:
+    the first 120 updates element by element against the oracle, then
+    properties that hold at any length."""
+    s = synth.wake(nx=400, ny=200, noise=1e-6)
+    X = s.snapshots(0, 121)
+    g, o = run_both(X, 40, 1e-8, check_every=20)
+    st = g.state()
+    assert st["r"] == o.r
+    lam, _ = g.eigs()
+    lo, _ = o.eigs()
+    pl = s.planted_eigs()[:11]
+    assert np.max(np.abs(O.match_eigs(pl, lam) - O.match_eigs(pl, lo))) < 1e-10
+    assert orth_err(g) < 1e-12
+    pg = g.predict(5).cpu().numpy()
+    po = o.predict(5)
+    assert np.max(np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)) < 1e-9
