@@ -78,6 +78,9 @@ odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
  *          max(tol, 16 * 2^-24): FP32 storage cannot hold a direction
  *          weaker than that.
  *   io:    ODMD_F64 or ODMD_F32; must equal basis for F64/F32 bases.
+ *   The small SVD of each update is solved through its secular equation,
+ *   with one-sided Jacobi as the fallback; the environment variable
+ *   ODMD_CORE_SVD=jacobi, read here, selects Jacobi only (diagnostics).
  *   workspace / workspace_bytes: NULL/0 to let the library allocate, else
  *          a device buffer of at least odmd_state_bytes(...) bytes, 256-byte
  *          aligned, owned by the caller and kept alive until odmd_destroy.
@@ -171,13 +174,23 @@ odmd_status odmd_get_state(odmd_t h, int32_t cap, double* sigma, double* atilde,
 odmd_status odmd_get_basis(odmd_t h, double* out);
 
 /*
- * Kernel timing.  odmd_profile(h, 1) makes every later update record HIP
- * events on the handle's stream around its streaming pass and around its
- * small-SVD phase; odmd_profile_read (synchronising) returns the summed
- * durations in milliseconds and the number of timed updates, then resets.
+ * Kernel timing.  odmd_profile(h, capacity) with capacity > 0 creates HIP
+ * events for at least `capacity` updates (up front, so that timing adds no
+ * allocation later) and makes every later update record events on the
+ * handle's stream around its streaming pass and around its small-SVD phase;
+ * capacity 0 stops recording.  odmd_profile_read (synchronising) returns the
+ * summed durations in milliseconds and the number of timed updates, then
+ * resets.
  */
-odmd_status odmd_profile(odmd_t h, int32_t enable);
+odmd_status odmd_profile(odmd_t h, int32_t capacity);
 odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_t* count);
+
+/* Per-update samples instead of sums (synchronising): pass_ms[k], core_ms[k]
+ * for the first min(cap, timed updates) updates (host arrays of length cap);
+ * *count receives the number of timed updates.  Resets like
+ * odmd_profile_read. */
+odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double* core_ms,
+                                 int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -108,6 +108,265 @@ __device__ int jacobi_sweeps(double* A, double* V, double* d, int M, int* flag) 
   return sweep + 1;
 }
 
+// SVD of the core by its secular equation (used first; Jacobi is the fallback).
+//
+// K K^T = D^2 + z z^T with D = diag(sigma_1..sigma_r, 0) and z = [p; rho], so
+// the squared singular values of K are the roots lambda of
+//     f(lambda) = 1 + sum_j z_j^2 / (d_j^2 - lambda) = 0,
+// one in each gap between consecutive d_j^2 and one above d_1^2.  With the
+// roots known, left and right singular vectors have closed forms,
+//     u_i[j] = z_j / (d_j^2 - lambda_i),   v_i[j] = d_j z_j / (d_j^2 - lambda_i),
+// v_i[r] = -1 (then normalised).  Numerical orthogonality needs z replaced by
+// the z~ for which the computed roots are exact (Loewner's formula, the
+// Gu-Eisenstat construction), and every difference d_j^2 - lambda_i formed
+// as (d_j - d_K)(d_j + d_K) - mu_i with lambda_i = d_K^2 + mu_i stored relative
+// to its nearer pole d_K.  Entries of z below 8 eps max(|d|, |z|) are deflated
+// (the pair (d_j, e_j) is already singular), as are poles closer than that
+// (a Givens rotation moves their z weight onto one of them); the zero pole
+// is never deflated: a zero rho is raised to that tolerance.  Each root is
+// found by one 32-lane half-wavefront: bracketed iteration on the two-pole
+// rational model of f (Li's "middle way"), falling back to bisection.
+constexpr int SEC_MAXIT = 64;
+constexpr double SEC_EPS = 2.220446049250313e-16;
+
+struct SecShared {
+  double dj[MMAX], zz[MMAX], zs[MMAX], mu[MMAX], zh[MMAX], nrm[2 * MMAX];
+  double gc[MMAX], gs[MMAX], d[MMAX], z[MMAX];
+  int J[MMAX], K[MMAX], gi[MMAX], gj[MMAX], dflist[MMAX], live[MMAX];
+  int nd, ndef, ngiv, fail;
+};
+
+__device__ __forceinline__ double lam_minus(const SecShared& S, int i, int jj) {
+  // lambda_i - d_jj^2 = (d_K^2 - d_jj^2) + mu_i
+  const double dK = S.dj[S.K[i]], dj = S.dj[jj];
+  return (dK - dj) * (dK + dj) + S.mu[i];
+}
+
+// Returns true on success; fills A (columns U_k * sigma'), V (V_k), column
+// order arbitrary (the caller sorts by column norm).
+__device__ bool secular_svd(double* A, double* V, const double* sig, const double* pv, double rho,
+                            int r, SecShared& S) {
+  const int tid = threadIdx.x, hw = tid >> 5, hl = tid & 31;
+  const int n = r + 1;
+  if (tid == 0) {
+    double dmax = 0.0;
+    for (int j = 0; j < r; ++j) dmax = fmax(dmax, fmax(fabs(sig[j]), fabs(pv[j])));
+    dmax = fmax(dmax, fabs(rho));
+    const double tol = 8.0 * SEC_EPS * dmax;
+    double* d = S.d;
+    double* z = S.z;
+    int* live = S.live;
+    for (int j = 0; j < r; ++j) {
+      d[j] = sig[j];
+      z[j] = pv[j];
+    }
+    d[r] = 0.0;
+    z[r] = fabs(rho) <= tol ? tol : rho;
+    int nl = 0, ndef = 0, ngiv = 0;
+    for (int j = 0; j < r; ++j) {
+      if (fabs(z[j]) <= tol) S.dflist[ndef++] = j;
+      else live[nl++] = j;
+    }
+    live[nl++] = r;
+    // close poles: consecutive live entries (the zero pole excluded)
+    int k = 0;
+    while (k + 1 < nl) {
+      const int i = live[k], j = live[k + 1];
+      if (j != r && d[i] - d[j] <= tol) {
+        const double h = hypot(z[i], z[j]);
+        S.gc[ngiv] = z[i] / h;
+        S.gs[ngiv] = z[j] / h;
+        S.gi[ngiv] = i;
+        S.gj[ngiv] = j;
+        ++ngiv;
+        z[i] = h;
+        S.dflist[ndef++] = j;
+        for (int t = k + 1; t + 1 < nl; ++t) live[t] = live[t + 1];
+        --nl;
+      } else {
+        ++k;
+      }
+    }
+    for (int t = 0; t < nl; ++t) {
+      S.J[t] = live[t];
+      S.dj[t] = d[live[t]];
+      S.zz[t] = z[live[t]] * z[live[t]];
+      S.zs[t] = z[live[t]] < 0.0 ? -1.0 : 1.0;
+    }
+    S.nd = nl;
+    S.ndef = ndef;
+    S.ngiv = ngiv;
+    S.fail = 0;
+  }
+  __syncthreads();
+  const int nd = S.nd;
+
+  // roots, one half-wavefront each
+  for (int i = hw; i < nd; i += CORE_THREADS / 32) {
+    if (nd == 1) {
+      if (hl == 0) {
+        S.K[0] = 0;
+        S.mu[0] = S.zz[0];
+      }
+      continue;
+    }
+    int K = 0;
+    if (i > 0) {
+      const double dI = S.dj[i];
+      const double half = 0.5 * (S.dj[i - 1] - dI) * (S.dj[i - 1] + dI);
+      double fm = 0.0;
+      for (int k = hl; k < nd; k += 32) fm += S.zz[k] / ((S.dj[k] - dI) * (S.dj[k] + dI) - half);
+      fm = 1.0 + halfwave_sum(fm);
+      K = fm > 0.0 ? i : i - 1;
+    }
+    const double dK = S.dj[K];
+    double lo, hi;
+    if (i == 0) {
+      double zs = 0.0;
+      for (int k = hl; k < nd; k += 32) zs += S.zz[k];
+      lo = 0.0;
+      hi = halfwave_sum(zs);
+    } else {
+      lo = (S.dj[i] - dK) * (S.dj[i] + dK);
+      hi = (S.dj[i - 1] - dK) * (S.dj[i - 1] + dK);
+      if (K == i) hi *= 0.5;
+      else lo *= 0.5;
+    }
+    const int ilo = i == 0 ? 1 : i, ihi = i == 0 ? 0 : i - 1;
+    const double dlo = (S.dj[ilo] - dK) * (S.dj[ilo] + dK);
+    const double dhi = (S.dj[ihi] - dK) * (S.dj[ihi] + dK);
+    double mu = 0.5 * (lo + hi);
+    int it = 0;
+    for (; it < SEC_MAXIT; ++it) {
+      double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
+      for (int k = hl; k < nd; k += 32) {
+        const double den = (S.dj[k] - dK) * (S.dj[k] + dK) - mu;
+        const double t = S.zz[k] / den;
+        if (k >= ilo) {
+          psi += t;
+          dpsi += t / den;
+        } else {
+          phi += t;
+          dphi += t / den;
+        }
+      }
+      psi = halfwave_sum(psi);
+      phi = halfwave_sum(phi);
+      dpsi = halfwave_sum(dpsi);
+      dphi = halfwave_sum(dphi);
+      const double w = 1.0 + psi + phi;
+      if (w > 0.0) hi = mu;
+      else lo = mu;
+      if (fabs(w) <= 8.0 * SEC_EPS * (1.0 + fabs(psi) + fabs(phi)) ||
+          hi - lo <= 4.0 * SEC_EPS * fmax(fabs(lo), fabs(hi)))
+        break;
+      const double Dlo = dlo - mu, Dhi = dhi - mu, dw = dpsi + dphi;
+      const double cq = w - Dlo * dpsi - Dhi * dphi;
+      const double aq = (Dlo + Dhi) * w - Dlo * Dhi * dw;
+      const double bq = Dlo * Dhi * w;
+      double r1 = NAN, r2 = NAN;
+      if (cq == 0.0) {
+        if (aq != 0.0) r1 = bq / aq;
+      } else {
+        const double disc = sqrt(fabs(aq * aq - 4.0 * bq * cq));
+        const double q = 0.5 * (aq + (aq >= 0.0 ? disc : -disc));
+        r1 = q / cq;
+        if (q != 0.0) r2 = bq / q;
+      }
+      double eta;
+      if (i == 0) {
+        eta = (r1 > Dhi) ? r1 : ((r2 > Dhi) ? r2 : NAN);
+      } else {
+        eta = (r1 > Dlo && r1 < Dhi) ? r1 : ((r2 > Dlo && r2 < Dhi) ? r2 : NAN);
+      }
+      if (!(eta == eta) || w * eta >= 0.0) eta = -w / dw;
+      double nw = mu + eta;
+      if (!(nw > lo && nw < hi)) nw = 0.5 * (lo + hi);
+      mu = nw;
+    }
+    if (hl == 0) {
+      S.K[i] = K;
+      S.mu[i] = mu;
+      if (it >= SEC_MAXIT || !isfinite(mu)) S.fail = 1;
+    }
+  }
+  __syncthreads();
+  if (S.fail) return false;
+
+  // z~ from the computed roots (Loewner's formula)
+  if (tid < nd) {
+    const int jj = tid;
+    double prod = lam_minus(S, jj, jj);
+    const double dj = S.dj[jj];
+    for (int i = 0; i < nd; ++i) {
+      if (i == jj) continue;
+      prod *= lam_minus(S, i, jj) / ((S.dj[i] - dj) * (S.dj[i] + dj));
+    }
+    S.zh[jj] = S.zs[jj] * sqrt(fmax(prod, 0.0));
+  }
+  // clear the outputs
+  for (int idx = tid; idx < n * n; idx += CORE_THREADS) {
+    const int row = idx % n, col = idx / n;
+    A[col * LDK + row] = 0.0;
+    V[col * LDK + row] = 0.0;
+  }
+  __syncthreads();
+  // unnormalised vectors of the roots: column i, live rows J[jj]
+  for (int idx = tid; idx < nd * nd; idx += CORE_THREADS) {
+    const int jj = idx % nd, i = idx / nd;
+    const double den = -lam_minus(S, i, jj);      // d_jj^2 - lambda_i
+    const int row = S.J[jj];
+    A[i * LDK + row] = S.zh[jj] / den;
+    V[i * LDK + row] = (row == r) ? -1.0 : S.dj[jj] * S.zh[jj] / den;
+  }
+  __syncthreads();
+  // column norms (one half-wavefront per column and matrix)
+  for (int q = hw; q < 2 * nd; q += CORE_THREADS / 32) {
+    const int i = q % nd;
+    const double* M = q < nd ? A : V;
+    double s = 0.0;
+    for (int jj = hl; jj < nd; jj += 32) {
+      const double v = M[i * LDK + S.J[jj]];
+      s += v * v;
+    }
+    s = halfwave_sum(s);
+    if (hl == 0) S.nrm[q] = s;
+  }
+  __syncthreads();
+  // scale: U columns to length sigma', V columns to length 1
+  for (int idx = tid; idx < nd * nd; idx += CORE_THREADS) {
+    const int jj = idx % nd, i = idx / nd;
+    const int row = S.J[jj];
+    const double om = sqrt(S.dj[S.K[i]] * S.dj[S.K[i]] + S.mu[i]);
+    A[i * LDK + row] *= om / sqrt(S.nrm[i]);
+    V[i * LDK + row] /= sqrt(S.nrm[nd + i]);
+  }
+  // deflated pairs: (d_j, e_j, e_j)
+  for (int t = tid; t < S.ndef; t += CORE_THREADS) {
+    const int j = S.dflist[t], col = nd + t;
+    A[col * LDK + j] = sig[j];
+    V[col * LDK + j] = 1.0;
+  }
+  __syncthreads();
+  // undo the close-pole rotations on the rows of U_k and V_k
+  if (tid < 2 * n) {
+    double* M = tid < n ? A : V;
+    const int col = tid % n;
+    for (int g = S.ngiv - 1; g >= 0; --g) {
+      const int i = S.gi[g], j = S.gj[g];
+      const double c = S.gc[g], sn = S.gs[g];
+      const double ri = M[col * LDK + i], rj = M[col * LDK + j];
+      M[col * LDK + i] = c * ri - sn * rj;
+      M[col * LDK + j] = sn * ri + c * rj;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += CORE_THREADS)
+    if (!isfinite(A[idx / n * LDK + idx % n]) || !isfinite(V[idx / n * LDK + idx % n])) S.fail = 1;
+  __syncthreads();
+  return !S.fail;
+}
+
 __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
   DevState* __restrict__ st = c.st;
   __shared__ double sA[MMAX * LDK];
@@ -115,7 +374,9 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
   __shared__ double red[CORE_THREADS];
   __shared__ double tot[PW];
   __shared__ double sd[MMAX + 1];
-  __shared__ double p2[RMAX], pyr[RMAX], pyn[RMAX], wn[RMAX], sgn[RMAX];
+  __shared__ double p2[RMAX], pyr[RMAX], pyn[RMAX], wn[RMAX], sgn[RMAX], ssig[RMAX], pvec[RMAX];
+  __shared__ SecShared sec;
+  __shared__ double sC[RMAX * RMAX];
   __shared__ int perm[MMAX + 1];
   __shared__ int flag;
   __shared__ double sc[8];
@@ -124,11 +385,20 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
   const int tid = threadIdx.x;
   const int r = st->r, rs = st->rs, pending = st->pending;
 
+  // 0. stage the previous rotation (in sA, free until the SVD) and the
+  //    shifted product C in LDS with one coalesced pass each
+  for (int idx = tid; idx < RMAX * RMAX; idx += CORE_THREADS) {
+    const int j = idx % RMAX, k = idx / RMAX;
+    sA[idx] = (pending && j < rs && k < r) ? st->G[idx] : 0.0;
+    sC[idx] = (j < r && k < r) ? st->C[idx] : 0.0;
+  }
+
   // 1. fixed-order reduction of the per-workgroup partial sums
   constexpr int NSPLIT = CORE_THREADS / PW;
   if (tid < NSPLIT * PW) {
     const int v = tid % PW, s = tid / PW;
     double acc = 0.0;
+#pragma unroll 8
     for (int b = s; b < c.nblk; b += NSPLIT) acc += c.partials[(int64_t)b * PW + v];
     red[s * PW + v] = acc;
   }
@@ -147,8 +417,8 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
       a2 = st->g[tid] * tot[P_SEE];
       b2 = st->g[tid] * tot[P_SEY];
       for (int j = 0; j < rs; ++j) {
-        a2 += st->G[tid * RMAX + j] * tot[P_SUE + j];
-        b2 += st->G[tid * RMAX + j] * tot[P_SUY + j];
+        a2 += sA[tid * RMAX + j] * tot[P_SUE + j];
+        b2 += sA[tid * RMAX + j] * tot[P_SUY + j];
       }
     } else {
       a2 = tot[P_SUE + tid];
@@ -202,18 +472,26 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
 
   // 4. core K = [[diag(sigma), p], [0, rho]], p = p1 + p2 with p1 = cached p_y
   const int M = r + 1;
-  for (int idx = tid; idx < M * M; idx += CORE_THREADS) {
-    const int i = idx % M, j = idx / M;
-    double v;
-    if (j < r) v = (i == j) ? st->sigma[j] : 0.0;
-    else v = (i < r) ? st->py[i] + p2[i] : rho;
-    sA[j * LDK + i] = v;
-    sV[j * LDK + i] = (i == j) ? 1.0 : 0.0;
+  if (tid < r) {
+    ssig[tid] = st->sigma[tid];
+    pvec[tid] = st->py[tid] + p2[tid];
   }
   __syncthreads();
 
-  // 5. SVD of the core
-  const int sweeps = jacobi_sweeps(sA, sV, sd, M, &flag);
+  // 5. SVD of the core: secular equation, one-sided Jacobi if that fails
+  int sweeps = 0;
+  if (c.jacobi_only || !secular_svd(sA, sV, ssig, pvec, rho, r, sec)) {
+    for (int idx = tid; idx < M * M; idx += CORE_THREADS) {
+      const int i = idx % M, j = idx / M;
+      double v;
+      if (j < r) v = (i == j) ? ssig[j] : 0.0;
+      else v = (i < r) ? pvec[i] : rho;
+      sA[j * LDK + i] = v;
+      sV[j * LDK + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    sweeps = jacobi_sweeps(sA, sV, sd, M, &flag);
+  }
 
   // 6. singular values (exact column norms), descending order, truncation
   if (tid < M) {
@@ -314,7 +592,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     const int pb = perm[bcol];
     double s = 0.0;
     if (i < r) {
-      for (int j = 0; j < r; ++j) s += st->C[j * RMAX + i] * sV[pb * LDK + j];
+      for (int j = 0; j < r; ++j) s += sC[j * RMAX + i] * sV[pb * LDK + j];
     } else {
       for (int j = 0; j < r; ++j) s += st->w[j] * sV[pb * LDK + j];
     }

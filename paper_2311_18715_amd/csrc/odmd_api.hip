@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <unordered_set>
@@ -36,6 +37,7 @@ struct odmd_s {
   void* Es = nullptr;
   int nblk = 0, tiles = 0;
   bool prof = false;
+  bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
   std::vector<hipEvent_t> ev;   // triples: before pass, after pass, after core
   size_t ev_used = 0;
 };
@@ -149,6 +151,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.nblk = h->nblk;
   c.r_max = h->r_max;
   c.basis_f32 = h->basis == ODMD_F32;
+  c.jacobi_only = h->jacobi_only;
   HIP_OK(launch_core(c, h->stream));
   if (ev) HIP_OK(hipEventRecord(ev[2], h->stream));
   return ODMD_OK;
@@ -220,6 +223,10 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->nblk = L.nblk;
   s->tiles = L.tiles;
+  {
+    const char* alg = std::getenv("ODMD_CORE_SVD");
+    s->jacobi_only = alg && std::strcmp(alg, "jacobi") == 0;
+  }
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return ODMD_EDEVICE;
@@ -391,9 +398,15 @@ odmd_status odmd_get_state(odmd_t h, int32_t cap, double* sigma, double* atilde,
   return ODMD_OK;
 }
 
-odmd_status odmd_profile(odmd_t h, int32_t enable) {
-  if (!h) return ODMD_EINVAL;
-  h->prof = enable != 0;
+odmd_status odmd_profile(odmd_t h, int32_t capacity) {
+  if (!h || capacity < 0) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  while (h->ev.size() < 3 * (size_t)capacity) {
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    h->ev.push_back(e);
+  }
+  h->prof = capacity > 0;
   return ODMD_OK;
 }
 
@@ -412,6 +425,24 @@ odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_
   *pass_ms = a;
   *core_ms = b;
   *count = (int64_t)(h->ev_used / 3);
+  h->ev_used = 0;
+  return ODMD_OK;
+}
+
+odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double* core_ms,
+                                 int64_t* count) {
+  if (!h || !pass_ms || !core_ms || !count || cap < 0) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  const int64_t n = (int64_t)(h->ev_used / 3);
+  for (int64_t k = 0; k < n && k < cap; ++k) {
+    float t1 = 0.f, t2 = 0.f;
+    HIP_OK(hipEventElapsedTime(&t1, h->ev[3 * k], h->ev[3 * k + 1]));
+    HIP_OK(hipEventElapsedTime(&t2, h->ev[3 * k + 1], h->ev[3 * k + 2]));
+    pass_ms[k] = t1;
+    core_ms[k] = t2;
+  }
+  *count = n;
   h->ev_used = 0;
   return ODMD_OK;
 }

@@ -26,6 +26,7 @@ struct CoreArgs {
   int nblk;
   int r_max;
   int basis_f32;        // also keep an FP32 copy of the rotation
+  int jacobi_only;      // skip the secular solver (diagnostics)
 };
 hipError_t launch_core(const CoreArgs& c, hipStream_t s);
 

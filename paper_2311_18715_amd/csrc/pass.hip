@@ -45,14 +45,20 @@ __device__ __forceinline__ void wave_reduce_scatter(double* v, int lane) {
   rs_step<N / 32, 1>(v, lane);
 }
 
+// Coefficients that stay constant for a whole launch (written only by the
+// small-state kernel) are read through the constant address space, so that
+// wave-uniform reads become scalar loads broadcast to all lanes.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
 template <typename T> struct Rot;
 template <> struct Rot<double> {
-  __device__ static const double* G(const DevState* s) { return s->G; }
-  __device__ static const double* g(const DevState* s) { return s->g; }
+  __device__ static cptr<double> G(const DevState* s) { return (cptr<double>)s->G; }
+  __device__ static cptr<double> g(const DevState* s) { return (cptr<double>)s->g; }
 };
 template <> struct Rot<float> {
-  __device__ static const float* G(const DevState* s) { return s->G32; }
-  __device__ static const float* g(const DevState* s) { return s->g32; }
+  __device__ static cptr<float> G(const DevState* s) { return (cptr<float>)s->G32; }
+  __device__ static cptr<float> g(const DevState* s) { return (cptr<float>)s->g32; }
 };
 
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -80,9 +86,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const DevState* __r
   TS* __restrict__ Es = static_cast<TS*>(p.Es);
   const TIO* __restrict__ X = static_cast<const TIO*>(p.x);
   const TIO* __restrict__ Y = static_cast<const TIO*>(p.y);
-  const double* a = st->a;
-  const TS* G = Rot<TS>::G(st);
-  const TS* gv = Rot<TS>::g(st);
+  cptr<double> a = (cptr<double>)st->a;
+  cptr<TS> G = Rot<TS>::G(st);
+  cptr<TS> gv = Rot<TS>::g(st);
   const double beta = st->beta;
   const int64_t ld = p.ld;
   const int lane = threadIdx.x & 63;

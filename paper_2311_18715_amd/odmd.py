@@ -24,6 +24,7 @@ EXPORTS = [
     "odmd_create", "odmd_create_ex", "odmd_state_bytes", "odmd_update", "odmd_update_batch",
     "odmd_eigs", "odmd_predict", "odmd_sync", "odmd_destroy", "odmd_status_str",
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
+    "odmd_profile_samples",
 ]
 
 
@@ -72,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "odmd_get_basis": ([vp, vp], ctypes.c_int),
             "odmd_profile": ([vp, i32], ctypes.c_int),
             "odmd_profile_read": ([vp, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
+            "odmd_profile_samples": ([vp, i64, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -190,14 +192,23 @@ class ODMD:
         k = self.info().r
         return out[:k].T
 
-    def profile(self, enable: bool = True) -> None:
-        _check(lib().odmd_profile(self._h, int(enable)), "odmd_profile")
+    def profile(self, capacity: int) -> None:
+        """Record per-update events (capacity > 0 reserves them now); 0 stops."""
+        _check(lib().odmd_profile(self._h, int(capacity)), "odmd_profile")
 
     def profile_read(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
         _check(lib().odmd_profile_read(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "odmd_profile_read")
         return a.value, b.value, c.value
+
+    def profile_samples(self, cap: int = 1 << 16):
+        """Per-update (pass_ms, core_ms) arrays of the timed updates."""
+        a, b, c = np.zeros(cap), np.zeros(cap), ctypes.c_int64()
+        _check(lib().odmd_profile_samples(self._h, cap, _dbl(a), _dbl(b), ctypes.byref(c)),
+               "odmd_profile_samples")
+        k = min(cap, c.value)
+        return a[:k].copy(), b[:k].copy()
 
     def close(self) -> None:
         if getattr(self, "_h", None):

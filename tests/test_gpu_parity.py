@@ -51,7 +51,17 @@ def orth_err(g):
     return torch.linalg.norm(U.T @ U - torch.eye(U.shape[1], dtype=U.dtype, device=U.device)).item()
 
 
-def test_planted_small_every_step():
+@pytest.fixture(params=["secular", "jacobi"])
+def core_svd(request, monkeypatch):
+    """Run a test with each small-SVD solver of the core."""
+    if request.param == "jacobi":
+        monkeypatch.setenv("ODMD_CORE_SVD", "jacobi")
+    else:
+        monkeypatch.delenv("ODMD_CORE_SVD", raising=False)
+    return request.param
+
+
+def test_planted_small_every_step(core_svd):
     """n=4096, rank 6, r_max 20, tol 1e-8, 399 pairs: rank and sigma each step."""
     s = synth.planted_small()
     X = s.snapshots(0, 400)
@@ -90,7 +100,7 @@ def test_planted_small_rollout():
 
 
 @pytest.mark.parametrize("nx,ny,r_max", [(60, 40, 40), (173, 97, 32), (7, 5, 24)])
-def test_wake_ragged_sizes(nx, ny, r_max):
+def test_wake_ragged_sizes(nx, ny, r_max, core_svd):
     """Noisy wake stream, n not a multiple of the tile size, truncation active."""
     s = synth.wake(nx=nx, ny=ny, noise=1e-6)
     X = s.snapshots(0, 200)
@@ -136,7 +146,7 @@ def test_scalar_and_tiny_streams():
     assert np.max(np.abs(U @ gp.state()["atilde"] @ U.T - A)) < 1e-10 * np.max(np.abs(A))
 
 
-def test_rank_cap_64():
+def test_rank_cap_64(core_svd):
     g = np.random.default_rng(8)
     X = g.standard_normal((3000, 90))
     gp, o = run_both(X, 64, 1e-12, check_every=10)
@@ -146,7 +156,7 @@ def test_rank_cap_64():
     assert rel_eig_err(np.linalg.eigvals(o.atilde()), lam, floor=0.1) < 1e-9
 
 
-def test_zero_snapshots_and_empty_model():
+def test_zero_snapshots_and_empty_model(core_svd):
     n = 700
     z = torch.zeros(n, dtype=torch.float64, device="cuda")
     x = torch.randn(n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
