@@ -1,7 +1,8 @@
 // Rollout / basis read-out: out[k] = U c_k for a block of coefficient
 // columns, with U the logical basis (Us G + Es g^T when a rotation is
 // pending, folded into the coefficients by the caller's coefficient kernel):
-//     out[k*ldo + i] = sum_j Us[j*ld + i] * coefA[k*RMAX + j] + Es[i] * coefB[k].
+//     out[k*ldo + i] = sum_j Us(i, j) * coefA[k*RMAX + j] + Es[i] * coefB[k],
+// Us(i, j) stored at ((i/64)*ct + j)*64 + i%64 (64-row tiles).
 // This is the O(N r) prediction of Sec. 2.3 (one read of the basis, one
 // write per predicted state).  Each thread keeps one row of Us in registers
 // and streams the output rows; coefficient columns are wave-uniform and come
@@ -25,13 +26,17 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs c) {
   const TS* __restrict__ Es = static_cast<const TS*>(c.Es);
   TO* __restrict__ out = static_cast<TO*>(c.out);
   double u[RB];
+  const TS* __restrict__ T = Us + (i >> 6) * (int64_t)c.ct * 64 + (i & 63);
 #pragma unroll
-  for (int j = 0; j < RB; ++j) u[j] = j < ncols ? (double)Us[j * c.ld + i] : 0.0;
+  for (int j = 0; j < RB; ++j) u[j] = j < ncols ? (double)T[j * 64] : 0.0;
   const double e = ue ? (double)Es[i] : 0.0;
   const int k0 = blockIdx.y * c.kb;
   const int k1 = min(c.K, k0 + c.kb);
-  const double* A = st->coefA;
-  const double* B = st->coefB;
+  // coefficients are read-only for the launch: scalar loads via the
+  // constant address space
+  typedef const __attribute__((address_space(4))) double* cdp;
+  cdp A = (cdp)st->coefA;
+  cdp B = (cdp)st->coefB;
   for (int k = k0; k < k1; ++k) {
     asm volatile("" : "+s"(A), "+s"(B));
     double acc = e * B[k];

@@ -128,17 +128,27 @@ __device__ int jacobi_sweeps(double* A, double* V, double* d, int M, int* flag) 
 // rational model of f (Li's "middle way"), falling back to bisection.
 constexpr int SEC_MAXIT = 64;
 constexpr double SEC_EPS = 2.220446049250313e-16;
+constexpr int SEC_TERMS = (MMAX + 15) / 16;   // secular terms per lane of a quarter-wave
 
 struct SecShared {
-  double dj[MMAX], zz[MMAX], zs[MMAX], mu[MMAX], zh[MMAX], nrm[2 * MMAX];
+  double dj[MMAX], zz[MMAX], zs[MMAX];   // live poles (descending), z^2, sign of z
+  double rK[MMAX], mu[MMAX];             // root i: lambda_i = rK[i]^2 + mu[i]
+  double zh[MMAX], nrm[2 * MMAX];
   double gc[MMAX], gs[MMAX], d[MMAX], z[MMAX];
-  int J[MMAX], K[MMAX], gi[MMAX], gj[MMAX], dflist[MMAX], live[MMAX];
-  int nd, ndef, ngiv, fail;
+  int J[MMAX], gi[MMAX], gj[MMAX], dflist[MMAX], live[MMAX];
+  int nd, ndef, ngiv, fail, close;
+  double tol;
 };
 
-__device__ __forceinline__ double lam_minus(const SecShared& S, int i, int jj) {
-  // lambda_i - d_jj^2 = (d_K^2 - d_jj^2) + mu_i
-  const double dK = S.dj[S.K[i]], dj = S.dj[jj];
+__device__ __forceinline__ double quarter_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+// lambda_i - d_j^2 = (d_K^2 - d_j^2) + mu_i, with d_K the pole root i is stored against
+__device__ __forceinline__ double lam_minus_d(const SecShared& S, int i, double dj) {
+  const double dK = S.rK[i];
   return (dK - dj) * (dK + dj) + S.mu[i];
 }
 
@@ -146,66 +156,107 @@ __device__ __forceinline__ double lam_minus(const SecShared& S, int i, int jj) {
 // order arbitrary (the caller sorts by column norm).
 __device__ bool secular_svd(double* A, double* V, const double* sig, const double* pv, double rho,
                             int r, SecShared& S) {
-  const int tid = threadIdx.x, hw = tid >> 5, hl = tid & 31;
+  const int tid = threadIdx.x;
   const int n = r + 1;
-  if (tid == 0) {
-    double dmax = 0.0;
-    for (int j = 0; j < r; ++j) dmax = fmax(dmax, fmax(fabs(sig[j]), fabs(pv[j])));
-    dmax = fmax(dmax, fabs(rho));
-    const double tol = 8.0 * SEC_EPS * dmax;
-    double* d = S.d;
-    double* z = S.z;
-    int* live = S.live;
-    for (int j = 0; j < r; ++j) {
-      d[j] = sig[j];
-      z[j] = pv[j];
+
+  // tolerance 8 eps max(|d|, |z|)
+  if (tid < 64) {
+    double m = 0.0;
+    for (int j = tid; j < r; j += 64) m = fmax(m, fmax(fabs(sig[j]), fabs(pv[j])));
+    if (tid == 0) m = fmax(m, fabs(rho));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (tid == 0) {
+      S.tol = 8.0 * SEC_EPS * m;
+      S.close = 0;
+      S.fail = 0;
+      S.ngiv = 0;
     }
-    d[r] = 0.0;
-    z[r] = fabs(rho) <= tol ? tol : rho;
-    int nl = 0, ndef = 0, ngiv = 0;
-    for (int j = 0; j < r; ++j) {
-      if (fabs(z[j]) <= tol) S.dflist[ndef++] = j;
-      else live[nl++] = j;
+  }
+  __syncthreads();
+  const double tol = S.tol;
+  if (tid < n) {
+    S.d[tid] = tid < r ? sig[tid] : 0.0;
+    S.z[tid] = tid < r ? pv[tid] : (fabs(rho) <= tol ? tol : rho);
+  }
+  __syncthreads();
+  // deflate tiny z (never the zero pole), keeping descending order (wave 0)
+  if (tid < 64) {
+    const int j0 = tid, j1 = tid + 64;
+    const bool l0 = j0 < n && !(j0 < r && fabs(S.z[j0]) <= tol);
+    const bool l1 = j1 < n && !(j1 < r && fabs(S.z[j1]) <= tol);
+    const unsigned long long m0 = __ballot(l0), m1 = __ballot(l1);
+    const unsigned long long lt = (tid == 0) ? 0ull : (~0ull >> (64 - tid));
+    const int p0 = __popcll(m0 & lt), p1 = __popcll(m1 & lt);
+    const int nl0 = __popcll(m0), nd0 = min(n, 64) - nl0;
+    if (j0 < n) {
+      if (l0) S.live[p0] = j0;
+      else S.dflist[j0 - p0] = j0;
     }
-    live[nl++] = r;
-    // close poles: consecutive live entries (the zero pole excluded)
-    int k = 0;
+    if (j1 < n) {
+      if (l1) S.live[nl0 + p1] = j1;
+      else S.dflist[nd0 + (j1 - 64 - p1)] = j1;
+    }
+    if (tid == 0) {
+      S.nd = nl0 + __popcll(m1);
+      S.ndef = n - S.nd;
+    }
+  }
+  __syncthreads();
+  // tied poles (rare): detect in parallel, merge serially
+  if (tid + 1 < S.nd) {
+    const int i = S.live[tid], j = S.live[tid + 1];
+    if (j != r && S.d[i] - S.d[j] <= tol) S.close = 1;
+  }
+  __syncthreads();
+  if (S.close && tid == 0) {
+    int nl = S.nd, ndef = S.ndef, ngiv = 0, k = 0;
     while (k + 1 < nl) {
-      const int i = live[k], j = live[k + 1];
-      if (j != r && d[i] - d[j] <= tol) {
-        const double h = hypot(z[i], z[j]);
-        S.gc[ngiv] = z[i] / h;
-        S.gs[ngiv] = z[j] / h;
+      const int i = S.live[k], j = S.live[k + 1];
+      if (j != r && S.d[i] - S.d[j] <= tol) {
+        const double h = hypot(S.z[i], S.z[j]);
+        S.gc[ngiv] = S.z[i] / h;
+        S.gs[ngiv] = S.z[j] / h;
         S.gi[ngiv] = i;
         S.gj[ngiv] = j;
         ++ngiv;
-        z[i] = h;
+        S.z[i] = h;
         S.dflist[ndef++] = j;
-        for (int t = k + 1; t + 1 < nl; ++t) live[t] = live[t + 1];
+        for (int t = k + 1; t + 1 < nl; ++t) S.live[t] = S.live[t + 1];
         --nl;
       } else {
         ++k;
       }
     }
-    for (int t = 0; t < nl; ++t) {
-      S.J[t] = live[t];
-      S.dj[t] = d[live[t]];
-      S.zz[t] = z[live[t]] * z[live[t]];
-      S.zs[t] = z[live[t]] < 0.0 ? -1.0 : 1.0;
-    }
     S.nd = nl;
     S.ndef = ndef;
     S.ngiv = ngiv;
-    S.fail = 0;
   }
   __syncthreads();
   const int nd = S.nd;
+  if (tid < nd) {
+    const int j = S.live[tid];
+    const double zj = S.z[j];
+    S.J[tid] = j;
+    S.dj[tid] = S.d[j];
+    S.zz[tid] = zj * zj;
+    S.zs[tid] = zj < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
 
-  // roots, one half-wavefront each
-  for (int i = hw; i < nd; i += CORE_THREADS / 32) {
+  // roots: one 16-lane quarter-wave each, the lane's terms kept in registers
+  const int qw = tid >> 4, ql = tid & 15;
+  double tdj[SEC_TERMS], tzz[SEC_TERMS];
+#pragma unroll
+  for (int m = 0; m < SEC_TERMS; ++m) {
+    const int k = ql + 16 * m;
+    tdj[m] = k < nd ? S.dj[k] : 0.0;
+    tzz[m] = k < nd ? S.zz[k] : 0.0;
+  }
+  for (int i = qw; i < nd; i += CORE_THREADS / 16) {
     if (nd == 1) {
-      if (hl == 0) {
-        S.K[0] = 0;
+      if (ql == 0) {
+        S.rK[0] = S.dj[0];
         S.mu[0] = S.zz[0];
       }
       continue;
@@ -215,17 +266,20 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
       const double dI = S.dj[i];
       const double half = 0.5 * (S.dj[i - 1] - dI) * (S.dj[i - 1] + dI);
       double fm = 0.0;
-      for (int k = hl; k < nd; k += 32) fm += S.zz[k] / ((S.dj[k] - dI) * (S.dj[k] + dI) - half);
-      fm = 1.0 + halfwave_sum(fm);
+#pragma unroll
+      for (int m = 0; m < SEC_TERMS; ++m)
+        if (ql + 16 * m < nd) fm += tzz[m] / ((tdj[m] - dI) * (tdj[m] + dI) - half);
+      fm = 1.0 + quarter_sum(fm);
       K = fm > 0.0 ? i : i - 1;
     }
     const double dK = S.dj[K];
     double lo, hi;
     if (i == 0) {
-      double zs = 0.0;
-      for (int k = hl; k < nd; k += 32) zs += S.zz[k];
+      double zsum = 0.0;
+#pragma unroll
+      for (int m = 0; m < SEC_TERMS; ++m) zsum += tzz[m];
       lo = 0.0;
-      hi = halfwave_sum(zs);
+      hi = quarter_sum(zsum);
     } else {
       lo = (S.dj[i] - dK) * (S.dj[i] + dK);
       hi = (S.dj[i - 1] - dK) * (S.dj[i - 1] + dK);
@@ -235,25 +289,32 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
     const int ilo = i == 0 ? 1 : i, ihi = i == 0 ? 0 : i - 1;
     const double dlo = (S.dj[ilo] - dK) * (S.dj[ilo] + dK);
     const double dhi = (S.dj[ihi] - dK) * (S.dj[ihi] + dK);
+    double dsh[SEC_TERMS];   // d_k^2 - d_K^2
+#pragma unroll
+    for (int m = 0; m < SEC_TERMS; ++m) dsh[m] = (tdj[m] - dK) * (tdj[m] + dK);
     double mu = 0.5 * (lo + hi);
     int it = 0;
     for (; it < SEC_MAXIT; ++it) {
       double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
-      for (int k = hl; k < nd; k += 32) {
-        const double den = (S.dj[k] - dK) * (S.dj[k] + dK) - mu;
-        const double t = S.zz[k] / den;
-        if (k >= ilo) {
-          psi += t;
-          dpsi += t / den;
-        } else {
-          phi += t;
-          dphi += t / den;
+#pragma unroll
+      for (int m = 0; m < SEC_TERMS; ++m) {
+        const int k = ql + 16 * m;
+        if (k < nd) {
+          const double rinv = 1.0 / (dsh[m] - mu);
+          const double t = tzz[m] * rinv;
+          if (k >= ilo) {
+            psi += t;
+            dpsi += t * rinv;
+          } else {
+            phi += t;
+            dphi += t * rinv;
+          }
         }
       }
-      psi = halfwave_sum(psi);
-      phi = halfwave_sum(phi);
-      dpsi = halfwave_sum(dpsi);
-      dphi = halfwave_sum(dphi);
+      psi = quarter_sum(psi);
+      phi = quarter_sum(phi);
+      dpsi = quarter_sum(dpsi);
+      dphi = quarter_sum(dphi);
       const double w = 1.0 + psi + phi;
       if (w > 0.0) hi = mu;
       else lo = mu;
@@ -269,23 +330,20 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
         if (aq != 0.0) r1 = bq / aq;
       } else {
         const double disc = sqrt(fabs(aq * aq - 4.0 * bq * cq));
-        const double q = 0.5 * (aq + (aq >= 0.0 ? disc : -disc));
-        r1 = q / cq;
-        if (q != 0.0) r2 = bq / q;
+        const double qv = 0.5 * (aq + (aq >= 0.0 ? disc : -disc));
+        r1 = qv / cq;
+        if (qv != 0.0) r2 = bq / qv;
       }
       double eta;
-      if (i == 0) {
-        eta = (r1 > Dhi) ? r1 : ((r2 > Dhi) ? r2 : NAN);
-      } else {
-        eta = (r1 > Dlo && r1 < Dhi) ? r1 : ((r2 > Dlo && r2 < Dhi) ? r2 : NAN);
-      }
+      if (i == 0) eta = (r1 > Dhi) ? r1 : ((r2 > Dhi) ? r2 : NAN);
+      else eta = (r1 > Dlo && r1 < Dhi) ? r1 : ((r2 > Dlo && r2 < Dhi) ? r2 : NAN);
       if (!(eta == eta) || w * eta >= 0.0) eta = -w / dw;
       double nw = mu + eta;
       if (!(nw > lo && nw < hi)) nw = 0.5 * (lo + hi);
       mu = nw;
     }
-    if (hl == 0) {
-      S.K[i] = K;
+    if (ql == 0) {
+      S.rK[i] = dK;
       S.mu[i] = mu;
       if (it >= SEC_MAXIT || !isfinite(mu)) S.fail = 1;
     }
@@ -296,11 +354,13 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
   // z~ from the computed roots (Loewner's formula)
   if (tid < nd) {
     const int jj = tid;
-    double prod = lam_minus(S, jj, jj);
     const double dj = S.dj[jj];
+    double prod = lam_minus_d(S, jj, dj);
+#pragma unroll 4
     for (int i = 0; i < nd; ++i) {
       if (i == jj) continue;
-      prod *= lam_minus(S, i, jj) / ((S.dj[i] - dj) * (S.dj[i] + dj));
+      const double di = S.dj[i];
+      prod *= lam_minus_d(S, i, dj) / ((di - dj) * (di + dj));
     }
     S.zh[jj] = S.zs[jj] * sqrt(fmax(prod, 0.0));
   }
@@ -314,30 +374,34 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
   // unnormalised vectors of the roots: column i, live rows J[jj]
   for (int idx = tid; idx < nd * nd; idx += CORE_THREADS) {
     const int jj = idx % nd, i = idx / nd;
-    const double den = -lam_minus(S, i, jj);      // d_jj^2 - lambda_i
+    const double dj = S.dj[jj];
+    const double den = -lam_minus_d(S, i, dj);      // d_jj^2 - lambda_i
     const int row = S.J[jj];
     A[i * LDK + row] = S.zh[jj] / den;
-    V[i * LDK + row] = (row == r) ? -1.0 : S.dj[jj] * S.zh[jj] / den;
+    V[i * LDK + row] = (row == r) ? -1.0 : dj * S.zh[jj] / den;
   }
   __syncthreads();
   // column norms (one half-wavefront per column and matrix)
-  for (int q = hw; q < 2 * nd; q += CORE_THREADS / 32) {
-    const int i = q % nd;
-    const double* M = q < nd ? A : V;
-    double s = 0.0;
-    for (int jj = hl; jj < nd; jj += 32) {
-      const double v = M[i * LDK + S.J[jj]];
-      s += v * v;
+  {
+    const int hw = tid >> 5, hl = tid & 31;
+    for (int q = hw; q < 2 * nd; q += CORE_THREADS / 32) {
+      const int i = q % nd;
+      const double* M = q < nd ? A : V;
+      double sm = 0.0;
+      for (int jj = hl; jj < nd; jj += 32) {
+        const double v = M[i * LDK + S.J[jj]];
+        sm += v * v;
+      }
+      sm = halfwave_sum(sm);
+      if (hl == 0) S.nrm[q] = sm;
     }
-    s = halfwave_sum(s);
-    if (hl == 0) S.nrm[q] = s;
   }
   __syncthreads();
   // scale: U columns to length sigma', V columns to length 1
   for (int idx = tid; idx < nd * nd; idx += CORE_THREADS) {
     const int jj = idx % nd, i = idx / nd;
     const int row = S.J[jj];
-    const double om = sqrt(S.dj[S.K[i]] * S.dj[S.K[i]] + S.mu[i]);
+    const double om = sqrt(S.rK[i] * S.rK[i] + S.mu[i]);
     A[i * LDK + row] *= om / sqrt(S.nrm[i]);
     V[i * LDK + row] /= sqrt(S.nrm[nd + i]);
   }
@@ -348,16 +412,16 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
     V[col * LDK + j] = 1.0;
   }
   __syncthreads();
-  // undo the close-pole rotations on the rows of U_k and V_k
-  if (tid < 2 * n) {
+  // undo the tied-pole rotations on the rows of U_k and V_k
+  if (S.ngiv > 0 && tid < 2 * n) {
     double* M = tid < n ? A : V;
     const int col = tid % n;
     for (int g = S.ngiv - 1; g >= 0; --g) {
       const int i = S.gi[g], j = S.gj[g];
-      const double c = S.gc[g], sn = S.gs[g];
+      const double cg = S.gc[g], sn = S.gs[g];
       const double ri = M[col * LDK + i], rj = M[col * LDK + j];
-      M[col * LDK + i] = c * ri - sn * rj;
-      M[col * LDK + j] = sn * ri + c * rj;
+      M[col * LDK + i] = cg * ri - sn * rj;
+      M[col * LDK + j] = sn * ri + cg * rj;
     }
   }
   __syncthreads();
@@ -377,6 +441,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
   __shared__ double p2[RMAX], pyr[RMAX], pyn[RMAX], wn[RMAX], sgn[RMAX], ssig[RMAX], pvec[RMAX];
   __shared__ SecShared sec;
   __shared__ double sC[RMAX * RMAX];
+  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX];
   __shared__ int perm[MMAX + 1];
   __shared__ int flag;
   __shared__ double sc[8];
@@ -392,23 +457,40 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     sA[idx] = (pending && j < rs && k < r) ? st->G[idx] : 0.0;
     sC[idx] = (j < r && k < r) ? st->C[idx] : 0.0;
   }
+  if (tid < RMAX) sw[tid] = tid < r ? st->w[tid] : 0.0;
 
-  // 1. fixed-order reduction of the per-workgroup partial sums
-  constexpr int NSPLIT = CORE_THREADS / PW;
-  if (tid < NSPLIT * PW) {
-    const int v = tid % PW, s = tid / PW;
-    double acc = 0.0;
+  // 1. fixed-order reduction of the per-workgroup partial sums (compact
+  //    records of pwc values, read as 16-byte pairs; sV is scratch here)
+  {
+    const int pwc = 2 * (c.rb + 1) + 4, pw2 = pwc / 2;
+    const int nslot = CORE_THREADS / pw2;
+    if (tid < nslot * pw2) {
+      const int g = tid % pw2, sl = tid / pw2;
+      double ax = 0.0, ay = 0.0;
 #pragma unroll 8
-    for (int b = s; b < c.nblk; b += NSPLIT) acc += c.partials[(int64_t)b * PW + v];
-    red[s * PW + v] = acc;
+      for (int b = sl; b < c.nblk; b += nslot) {
+        const double2 v = reinterpret_cast<const double2*>(c.partials + (int64_t)b * PW)[g];
+        ax += v.x;
+        ay += v.y;
+      }
+      sV[sl * pwc + 2 * g] = ax;
+      sV[sl * pwc + 2 * g + 1] = ay;
+    }
+    __syncthreads();
+    if (tid < pwc) {
+      double t = 0.0;
+      for (int sl = 0; sl < nslot; ++sl) t += sV[sl * pwc + tid];
+      const int rb = c.rb;
+      int slot;
+      if (tid < rb) slot = P_SUE + tid;
+      else if (tid == rb) slot = P_SEE;
+      else if (tid <= 2 * rb) slot = P_SUY + (tid - rb - 1);
+      else if (tid == 2 * rb + 1) slot = P_SEY;
+      else slot = tid == 2 * rb + 2 ? P_EE : (tid == 2 * rb + 3 ? P_EY : (tid == 2 * rb + 4 ? P_XX : P_YY));
+      tot[slot] = t;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (tid < PW) {
-    double t = 0.0;
-    for (int s = 0; s < NSPLIT; ++s) t += red[s * PW + tid];
-    tot[tid] = t;
-  }
-  __syncthreads();
 
   // 2. second projection p2 = U^T e and U^T y in the basis the pass used
   if (tid < r) {
@@ -416,6 +498,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     if (pending) {
       a2 = st->g[tid] * tot[P_SEE];
       b2 = st->g[tid] * tot[P_SEY];
+#pragma unroll 8
       for (int j = 0; j < rs; ++j) {
         a2 += sA[tid * RMAX + j] * tot[P_SUE + j];
         b2 += sA[tid * RMAX + j] * tot[P_SUY + j];
@@ -496,6 +579,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
   // 6. singular values (exact column norms), descending order, truncation
   if (tid < M) {
     double s = 0.0;
+#pragma unroll 8
     for (int i = 0; i < M; ++i) s += sA[tid * LDK + i] * sA[tid * LDK + i];
     sd[tid] = sqrt(s);
   }
@@ -503,21 +587,14 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
   if (tid < M) {
     const double me = sd[tid];
     int rank = 0;
+#pragma unroll 8
     for (int k = 0; k < M; ++k) rank += (sd[k] > me) || (sd[k] == me && k < tid);
     perm[rank] = tid;
   }
   __syncthreads();
-  if (tid == 0) {
-    const double smax = sd[perm[0]];
-    int rn = 0;
-    if (smax > 0.0) {
-      for (int k = 0; k < M; ++k) rn += sd[k] > st->tol * smax;
-      rn = min(rn, c.r_max);
-    }
-    si[2] = rn;
-  }
-  __syncthreads();
-  const int rn = si[2];
+  const double smax = sd[perm[0]];
+  const int above = __syncthreads_count(tid < M && smax > 0.0 && sd[tid] > st->tol * smax);
+  const int rn = min(above, c.r_max);
   if (rn == 0) {   // nothing kept (zero snapshots so far)
     if (tid == 0) {
       st->r = 0;
@@ -540,10 +617,13 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     const int pj = perm[tid];
     const double inv = 1.0 / sd[pj];
     double s = sA[pj * LDK + r] * qy;
+#pragma unroll 8
     for (int i = 0; i < r; ++i) s += sA[pj * LDK + i] * pyr[i];
     pyn[tid] = s * inv;
     wn[tid] = sV[pj * LDK + r];
     sgn[tid] = sd[pj];
+    wk[tid] = s * inv * inv;                  // p_y,k / sigma'_k
+    urk[tid] = sA[pj * LDK + r] * inv;        // U_k(r, k)
   }
   __syncthreads();
 
@@ -569,20 +649,23 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     }
     st->g[tid] = gk;
     if (c.basis_f32) st->g32[tid] = (float)gk;
-    // a = G p1 with p1 = new p_y (the next x equals this y)
-    double av = 0.0;
+    // a = G p1 with p1 = new p_y (the next x equals this y):
+    // a_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
+    double av = 0.0, bsum = 0.0;
     if (tid < r) {
+#pragma unroll 8
       for (int k = 0; k < rn; ++k) {
-        const int pk = perm[k];
-        av += (sA[pk * LDK + tid] - p2[tid] * irho * sA[pk * LDK + r]) / sd[pk] * pyn[k];
+        av += sA[perm[k] * LDK + tid] * wk[k];
+        bsum += urk[k] * pyn[k];
       }
+      av -= p2[tid] * irho * bsum;
     }
     st->a[tid] = av;
-  }
-  if (tid == 0) {
-    double b = 0.0;
-    for (int k = 0; k < rn; ++k) b += sA[perm[k] * LDK + r] * irho / sd[perm[k]] * pyn[k];
-    st->beta = b;
+    if (tid == 0) {
+      double b = 0.0;
+      for (int k = 0; k < rn; ++k) b += urk[k] * pyn[k];
+      st->beta = b * irho;
+    }
   }
   __syncthreads();
 
@@ -592,9 +675,11 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     const int pb = perm[bcol];
     double s = 0.0;
     if (i < r) {
+#pragma unroll 8
       for (int j = 0; j < r; ++j) s += sC[j * RMAX + i] * sV[pb * LDK + j];
     } else {
-      for (int j = 0; j < r; ++j) s += st->w[j] * sV[pb * LDK + j];
+#pragma unroll 8
+      for (int j = 0; j < r; ++j) s += sw[j] * sV[pb * LDK + j];
     }
     sA[bcol * LDK + i] = s;   // U_k is no longer read (synced above)
   }
@@ -605,6 +690,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     const int i = idx % rn, j = idx / rn;
     const int pi = perm[i];
     double s = 0.0;
+#pragma unroll 8
     for (int k = 0; k < M; ++k) s += sV[pi * LDK + k] * sA[j * LDK + k];
     st->C[j * RMAX + i] = s;
     st->At[j * RMAX + i] = (sgn[i] * s + pyn[i] * wn[j]) / sgn[j];

@@ -22,7 +22,7 @@
 using namespace odmd;
 
 struct odmd_s {
-  int64_t n = 0, ld = 0;
+  int64_t n = 0;
   int r_max = 0, rb = 0;
   double tol = 0.0, tol_eff = 0.0;
   odmd_dtype basis = ODMD_F64, io = ODMD_F64;
@@ -35,7 +35,8 @@ struct odmd_s {
   double* partials = nullptr;
   void* Us = nullptr;
   void* Es = nullptr;
-  int nblk = 0, tiles = 0;
+  int nblk = 0;
+  int64_t units = 0;
   bool prof = false;
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
   std::vector<hipEvent_t> ev;   // triples: before pass, after pass, after core
@@ -46,8 +47,8 @@ namespace {
 
 struct Layout {
   size_t st = 0, partials = 0, Us = 0, Es = 0, total = 0;
-  int64_t ld = 0;
-  int nblk = 0, tiles = 0;
+  int64_t ntiles = 0, units = 0;
+  int nblk = 0, ct = 0;
 };
 
 int elem_bytes(odmd_dtype t) { return t == ODMD_F64 ? 8 : (t == ODMD_F32 ? 4 : 2); }
@@ -64,25 +65,28 @@ bool valid_args(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dty
   return valid_types(basis, io);
 }
 
+int rank_bucket(int r_max) { return (r_max + 7) / 8 * 8; }
+
+// Basis: 64-row tiles, column-major inside a tile, rank_bucket(r_max) columns
+// per tile; the residual Es holds the same padded row count.
 Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis) {
   Layout L;
-  L.ld = round_up(n, 64);
-  L.tiles = (int)((n + PASS_THREADS - 1) / PASS_THREADS);
-  L.nblk = std::min(L.tiles, PASS_MAX_BLOCKS);
+  L.ct = rank_bucket(r_max);
+  L.ntiles = (n + 63) / 64;
+  L.units = (n + 31) / 32;
+  L.nblk = (int)std::min<int64_t>((L.units + 3) / 4, PASS_MAX_BLOCKS);
   size_t off = 0;
   L.st = off;
   off += round_up(sizeof(DevState), 256);
   L.partials = off;
   off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
   L.Us = off;
-  off += round_up((int64_t)r_max * L.ld * elem_bytes(basis), 256);
+  off += round_up(L.ntiles * L.ct * 64 * elem_bytes(basis), 256);
   L.Es = off;
-  off += round_up(L.ld * elem_bytes(basis), 256);
+  off += round_up(L.ntiles * 64 * elem_bytes(basis), 256);
   L.total = off;
   return L;
 }
-
-int rank_bucket(int r_max) { return (r_max + 7) / 8 * 8; }
 
 odmd_status map_status(int bits) {
   if (bits & ST_NONFINITE) return ODMD_ENONFINITE;
@@ -140,9 +144,8 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.partials = h->partials;
   p.st = h->st;
   p.n = h->n;
-  p.ld = h->ld;
+  p.units = h->units;
   p.nblk = h->nblk;
-  p.tiles = h->tiles;
   HIP_OK(launch_pass(p, h->basis == ODMD_F64, h->rb, h->stream));
   if (ev) HIP_OK(hipEventRecord(ev[1], h->stream));
   CoreArgs c;
@@ -152,6 +155,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.r_max = h->r_max;
   c.basis_f32 = h->basis == ODMD_F32;
   c.jacobi_only = h->jacobi_only;
+  c.rb = h->rb;
   HIP_OK(launch_core(c, h->stream));
   if (ev) HIP_OK(hipEventRecord(ev[2], h->stream));
   return ODMD_OK;
@@ -164,7 +168,7 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   c.Es = h->Es;
   c.out = out;
   c.n = h->n;
-  c.ld = h->ld;
+  c.ct = h->rb;
   c.ldo = ldo;
   c.K = K;
   const int64_t xb = (h->n + 255) / 256;
@@ -213,7 +217,6 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   odmd_s* s = new (std::nothrow) odmd_s;
   if (!s) return ODMD_ENOMEM;
   s->n = n;
-  s->ld = L.ld;
   s->r_max = r_max;
   s->rb = rank_bucket(r_max);
   s->tol = tol;
@@ -222,7 +225,7 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   s->io = io;
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->nblk = L.nblk;
-  s->tiles = L.tiles;
+  s->units = L.units;
   {
     const char* alg = std::getenv("ODMD_CORE_SVD");
     s->jacobi_only = alg && std::strcmp(alg, "jacobi") == 0;

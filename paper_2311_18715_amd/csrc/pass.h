@@ -7,14 +7,15 @@
 namespace odmd {
 
 struct PassArgs {
-  void* Us;             // stored basis, column-major, leading dim ld
-  void* Es;             // stored residual
+  void* Us;             // stored basis: 64-row tiles, column-major inside a tile
+  void* Es;             // stored residual (n rounded up to 64 entries)
   const void* x;        // snapshot x_k (io type)
   const void* y;        // snapshot x_k+1 (io type)
-  double* partials;     // nblk x PW
+  double* partials;     // nblk records (stride PW) of 2 (rb + 1) + 4 values
   const DevState* st;
-  int64_t n, ld;
-  int nblk, tiles;      // workgroups, 256-row tiles
+  int64_t n;
+  int64_t units;        // 32-row units, ceil(n / 32)
+  int nblk;             // workgroups
 };
 
 // rb: rank bucket (multiple of 8, >= r_max of the stream)
@@ -27,15 +28,17 @@ struct CoreArgs {
   int r_max;
   int basis_f32;        // also keep an FP32 copy of the rotation
   int jacobi_only;      // skip the secular solver (diagnostics)
+  int rb;               // rank bucket of the pass (compact partial records)
 };
 hipError_t launch_core(const CoreArgs& c, hipStream_t s);
 
 struct CombineArgs {
   const DevState* st;   // coefficients coefA / coefB and the basis layout
-  const void* Us;       // stored basis
+  const void* Us;       // stored basis (64-row tiles, column capacity ct)
   const void* Es;       // stored residual
   void* out;            // out[k*ldo + i], k < K
-  int64_t n, ld, ldo;
+  int64_t n, ldo;
+  int ct;               // column capacity of a basis tile
   int K, kb;            // columns, columns per workgroup row of the grid
 };
 // out type: 0 = FP64, 1 = FP32; basis_f64 selects the stored type

@@ -1,19 +1,29 @@
-// Streaming pass of the online DMD update (HBM-bound, one read of the basis).
+// Streaming pass of the online DMD update (HBM-bound, one read and one write
+// of the basis per update).
 //
 // One update appends the pair (x, y) to the snapshot matrices (Sec. 2.3).
 // Brand's column append needs the projection of x onto the basis and the
 // residual direction; this pass computes, in one sweep over the rows:
-//   * the pending rotation of the previous update, U = Us G + Es g^T,
-//     written back to Us (so the basis is read once and written once);
-//   * the first Gram-Schmidt residual e = x - U p1 with the cached
-//     projection p1 = U^T x (equal to the previous step's U^T y for chained
-//     pairs), stored to Es;
+//   * the pending rotation of the previous update, U = [Us Es] G' with
+//     G' = [G; g^T], written back to Us;
+//   * the first Gram-Schmidt residual e = x - U p1 = x - Us a - Es beta (a = G
+//     p1, beta = g . p1, p1 the cached projection U^T x, equal to the
+//     previous step's U^T y for chained pairs), stored to Es;
 //   * per-workgroup partial sums of Us^T e, Es.e, e.e, x.x and of Us^T y,
-//     Es.y, e.y, y.y.  The small-state kernel turns them into the second
-//     Gram-Schmidt projection p2 = U^T e = G^T (Us^T e) + g (Es.e) and into
-//     U^T y the same way, which completes the CGS2 step.
-// Partial sums are reduced in a fixed order (wave reduce-scatter, then the
-// workgroup's waves in index order) so results do not depend on timing.
+//     Es.y, e.y, y.y, from which the small-state kernel forms the second
+//     Gram-Schmidt projection p2 = U^T e = G'^T [Us Es]^T e and U^T y (CGS2).
+//
+// Layout and mapping (CDNA4): the basis is stored in tiles of 64 rows, each
+// tile column-major (element (i, c) at ((i/64)*CT + c)*64 + i%64, CT the
+// column capacity), so one column of a tile is 64 contiguous elements.  A
+// wavefront processes 32 rows at a time in the operand layout of the 16x16x4
+// matrix-core instruction: lane l holds rows 16*mt + l%16 (mt = 0, 1) of
+// columns 4*kk + l/16, so that
+//   * the rotation [Us Es] G' is a chain of MFMAs (G' staged in LDS in the
+//     operand layout), overlapped with the loads of the next unit;
+//   * e needs only an in-lane dot product plus two cross-lane additions;
+//   * the projections accumulate in-lane across all rows a lane sees and are
+//     reduced once per workgroup, in a fixed order (bitwise reproducible).
 #include <hip/hip_runtime.h>
 
 #include "odmd_internal.h"
@@ -21,165 +31,259 @@
 
 namespace odmd {
 
-template <int N, int O>
-__device__ __forceinline__ void rs_step(double* v, int lane) {
-  const bool up = (lane & O) != 0;
-#pragma unroll
-  for (int t = 0; t < N / 2; ++t) {
-    const double keep = up ? v[t + N / 2] : v[t];
-    const double send = up ? v[t] : v[t + N / 2];
-    v[t] = keep + __shfl_xor(send, O, 64);
-  }
-}
-
-// Recursive-halving reduce-scatter over a 64-wide wavefront: afterwards lane
-// l holds in v[0 .. N/64) the wave sums of the entries [l*N/64, (l+1)*N/64).
-template <int N>
-__device__ __forceinline__ void wave_reduce_scatter(double* v, int lane) {
-  static_assert(N % 64 == 0, "N must be a multiple of 64");
-  rs_step<N, 32>(v, lane);
-  rs_step<N / 2, 16>(v, lane);
-  rs_step<N / 4, 8>(v, lane);
-  rs_step<N / 8, 4>(v, lane);
-  rs_step<N / 16, 2>(v, lane);
-  rs_step<N / 32, 1>(v, lane);
-}
-
 // Coefficients that stay constant for a whole launch (written only by the
-// small-state kernel) are read through the constant address space, so that
-// wave-uniform reads become scalar loads broadcast to all lanes.
+// small-state kernel) are read through the constant address space.
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
 
-template <typename T> struct Rot;
-template <> struct Rot<double> {
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4_t acc_t;
   __device__ static cptr<double> G(const DevState* s) { return (cptr<double>)s->G; }
   __device__ static cptr<double> g(const DevState* s) { return (cptr<double>)s->g; }
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result element v of lane l sits in result row dsub(l, v), column l % 16
+  __device__ static int dsub(int l, int v) { return 4 * v + (l >> 4); }
 };
-template <> struct Rot<float> {
+template <> struct Mfma<float> {
+  typedef f4_t acc_t;
   __device__ static cptr<float> G(const DevState* s) { return (cptr<float>)s->G32; }
   __device__ static cptr<float> g(const DevState* s) { return (cptr<float>)s->g32; }
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int dsub(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// Partial-record slot of entry g of group A (e products) or B (y products).
-template <int RB>
-__device__ __forceinline__ int slot_of(int idx, int NA) {
-  const bool b = idx >= NA;
-  const int g = b ? idx - NA : idx;
-  if (g < RB) return (b ? P_SUY : P_SUE) + g;
-  if (g == RB) return b ? P_SEY : P_SEE;
-  if (g == RB + 1) return b ? P_EY : P_EE;
-  if (g == RB + 2) return b ? P_YY : P_XX;
-  return -1;
-}
+#ifndef ODMD_PASS_MT
+#define ODMD_PASS_MT 1
+#endif
+#ifndef ODMD_PASS_PREFETCH
+#define ODMD_PASS_PREFETCH 1
+#endif
 
 template <typename TS, typename TIO, int RB>
-__device__ __forceinline__ void pass_body(const PassArgs& p, const DevState* __restrict__ st,
-                                          int rs, int r, int pending, int use_e) {
-  constexpr int NA = 64 * ((RB + 3 + 63) / 64);
-  constexpr int KA = NA / 64;
+__global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
+  constexpr int MT = ODMD_PASS_MT;        // 16-row blocks per unit
+  constexpr int UR = 16 * MT;             // rows per unit
+  constexpr int UPT = 64 / UR;            // units per 64-row tile
+  constexpr bool PF = ODMD_PASS_PREFETCH;
+  constexpr int KK = RB / 4 + 1;          // k-steps: RB basis columns + the Es column
+  constexpr int NT = (RB + 15) / 16;      // 16-column output blocks
+  constexpr int CT = RB;                  // column capacity of a tile
   constexpr int NWAVE = PASS_THREADS / 64;
+  typedef typename Mfma<TS>::acc_t acc_t;
+
+  const DevState* __restrict__ st = p.st;
+  const int rs = st->rs, r = st->r, pending = st->pending, use_e = st->use_e;
   TS* __restrict__ Us = static_cast<TS*>(p.Us);
   TS* __restrict__ Es = static_cast<TS*>(p.Es);
   const TIO* __restrict__ X = static_cast<const TIO*>(p.x);
   const TIO* __restrict__ Y = static_cast<const TIO*>(p.y);
-  cptr<double> a = (cptr<double>)st->a;
-  cptr<TS> G = Rot<TS>::G(st);
-  cptr<TS> gv = Rot<TS>::g(st);
-  const double beta = st->beta;
-  const int64_t ld = p.ld;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, l16 = lane & 15;
 
-  double accA[KA], accB[KA];
+  // per-lane coefficients of the first projection (a, beta) in registers;
+  // the rotation G' = [G; g^T] in LDS, pre-arranged in the MFMA operand
+  // layout (entry [kk][nt][lane] = G'[4 kk + lane/16][16 nt + lane%16])
+  __shared__ TS sG[KK][NT][64];
+  double al[KK];
+  {
+    cptr<double> a = (cptr<double>)st->a;
+    const double beta = st->beta;
 #pragma unroll
-  for (int q = 0; q < KA; ++q) accA[q] = accB[q] = 0.0;
+    for (int kk = 0; kk < KK; ++kk) {
+      const int c = 4 * kk + q;
+      al[kk] = c < rs ? a[c] : (c == RB && use_e ? beta : 0.0);
+    }
+    cptr<TS> G = Mfma<TS>::G(st);
+    cptr<TS> g = Mfma<TS>::g(st);
+    for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
+      const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
+      const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
+      TS v = TS(0);
+      if (pending && col < r) {
+        if (c < rs) v = G[col * RMAX + c];
+        else if (c == RB && use_e) v = g[col];
+      }
+      sG[kk][nt][ln] = v;
+    }
+    __syncthreads();
+  }
 
-  const int t0 = (int)((int64_t)blockIdx.x * p.tiles / p.nblk);
-  const int t1 = (int)((int64_t)(blockIdx.x + 1) * p.tiles / p.nblk);
-  for (int tile = t0; tile < t1; ++tile) {
-    // Keep the loop-invariant coefficient loads inside the loop: hoisted, the
-    // r x r rotation would not fit in scalar registers and would spill.
-    asm volatile("" : "+s"(G), "+s"(gv), "+s"(a));
-    const int64_t i = (int64_t)tile * PASS_THREADS + threadIdx.x;
-    const bool in = i < p.n;
-    TS us[RB];
+  double accE[KK], accY[KK], sEE = 0.0, sEY = 0.0, sXX = 0.0, sYY = 0.0;
 #pragma unroll
-    for (int j = 0; j < RB; ++j) us[j] = (in && j < rs) ? Us[j * ld + i] : TS(0);
-    const double es = (in && use_e) ? (double)Es[i] : 0.0;
-    const double xi = in ? (double)X[i] : 0.0;
-    const double yi = in ? (double)Y[i] : 0.0;
+  for (int kk = 0; kk < KK; ++kk) accE[kk] = accY[kk] = 0.0;
 
-    // first Gram-Schmidt residual against the (rotated) basis, in FP64
-    double e = xi;
-#pragma unroll
-    for (int j = 0; j < RB; ++j) e = fmad(-(double)us[j], a[j], e);
-    e = fmad(-es, beta, e);
-    const TS e_s = (TS)e;
-    if (in) Es[i] = e_s;
-    const double ed = (double)e_s;
+  const int64_t units = (p.n + UR - 1) / UR;
+  const int64_t u0 = (int64_t)blockIdx.x * units / p.nblk;
+  const int64_t u1 = (int64_t)(blockIdx.x + 1) * units / p.nblk;
 
-    double v[NA];
+  // operands of one unit: A[mt][kk] = [Us Es](16 mt + l%16, 4 kk + l/16)
+  auto load_unit = [&](int64_t u, TS (&A)[MT][KK], double (&xv)[MT], double (&yv)[MT]) {
+    const int64_t tile = u / UPT;
+    const int half = (int)(u % UPT);
+    const TS* __restrict__ T = Us + tile * (int64_t)CT * 64;
 #pragma unroll
-    for (int j = 0; j < NA; ++j) v[j] = 0.0;
+    for (int mt = 0; mt < MT; ++mt) {
+      const int rr = UR * half + 16 * mt + l16;
+      const int64_t row = tile * 64 + rr;
+      const bool in = row < p.n;
 #pragma unroll
-    for (int j = 0; j < RB; ++j) v[j] = (double)us[j] * ed;
-    v[RB] = es * ed;
-    v[RB + 1] = ed * ed;
-    v[RB + 2] = xi * xi;
-    wave_reduce_scatter<NA>(v, lane);
-#pragma unroll
-    for (int q = 0; q < KA; ++q) accA[q] += v[q];
+      for (int kk = 0; kk < KK; ++kk) {
+        const int c = 4 * kk + q;
+        TS v = TS(0);
+        if (in) {
+          if (c < rs) v = T[c * 64 + rr];
+          else if (c == RB && use_e) v = Es[row];
+        }
+        A[mt][kk] = v;
+      }
+      xv[mt] = in ? (double)X[row] : 0.0;
+      yv[mt] = in ? (double)Y[row] : 0.0;
+    }
+  };
 
-#pragma unroll
-    for (int j = 0; j < NA; ++j) v[j] = 0.0;
-#pragma unroll
-    for (int j = 0; j < RB; ++j) v[j] = (double)us[j] * yi;
-    v[RB] = es * yi;
-    v[RB + 1] = ed * yi;
-    v[RB + 2] = yi * yi;
-    wave_reduce_scatter<NA>(v, lane);
-#pragma unroll
-    for (int q = 0; q < KA; ++q) accB[q] += v[q];
+  // software pipeline: the next unit's loads are in flight while the matrix
+  // cores rotate the current one
+  TS A[MT][KK], An[MT][KK];
+  double xv[MT], yv[MT], xn[MT], yn[MT];
+  int64_t u = u0 + wave;
+  if (PF && u < u1) load_unit(u, A, xv, yv);
+  for (; u < u1; u += NWAVE) {
+    const bool more = PF && u + NWAVE < u1;
+    if (more) load_unit(u + NWAVE, An, xn, yn);
+    if (!PF) load_unit(u, A, xv, yv);
+    const int64_t tile = u / UPT;
+    const int half = (int)(u % UPT);
+    TS* __restrict__ T = Us + tile * (int64_t)CT * 64;
+    const int64_t rowbase = tile * 64 + UR * half;
 
-    // pending rotation of the previous update: U = Us G + Es g^T
+    // e = x - [Us Es] [a; beta], in FP64
+    double ed[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      double s = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk) s = __builtin_fma((double)A[mt][kk], al[kk], s);
+      s += __shfl_xor(s, 16, 64);
+      s += __shfl_xor(s, 32, 64);
+      const TS es = (TS)(xv[mt] - s);
+      const int64_t row = rowbase + 16 * mt + l16;
+      if (q == 0 && row < p.n) Es[row] = es;
+      ed[mt] = (double)es;
+    }
+
+    // projections, accumulated in-lane
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        accE[kk] = __builtin_fma((double)A[mt][kk], ed[mt], accE[kk]);
+        accY[kk] = __builtin_fma((double)A[mt][kk], yv[mt], accY[kk]);
+      }
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        sEE = __builtin_fma(ed[mt], ed[mt], sEE);
+        sEY = __builtin_fma(ed[mt], yv[mt], sEY);
+        sXX = __builtin_fma(xv[mt], xv[mt], sXX);
+        sYY = __builtin_fma(yv[mt], yv[mt], sYY);
+      }
+    }
+
+    // pending rotation on the matrix cores, computed transposed:
+    // U'^T = G'^T [Us Es]^T, so that lane l owns row 16 mt + l%16 of U' and
+    // every store instruction writes whole 16-row column segments
     if (pending) {
-      const TS est = (TS)es;
+      // k-steps outermost: the NT*MT accumulator chains are independent, so
+      // consecutive MFMAs never wait on each other's results
+      acc_t d[NT][MT];
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        TS acc = est * gv[k];
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-        for (int j = 0; j < RB; ++j) acc = fmad(us[j], G[k * RMAX + j], acc);
-        if (in && k < r) Us[k * ld + i] = acc;
+        for (int mt = 0; mt < MT; ++mt) d[nt][mt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const TS b = sG[kk][nt][lane];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) d[nt][mt] = Mfma<TS>::mma(b, A[mt][kk], d[nt][mt]);
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int rr = UR * half + 16 * mt + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = 16 * nt + Mfma<TS>::dsub(lane, v);
+            if (col < r) T[col * 64 + rr] = d[nt][mt][v];
+          }
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) A[mt][kk] = An[mt][kk];
+        xv[mt] = xn[mt];
+        yv[mt] = yn[mt];
       }
     }
   }
 
-  __shared__ double red[NWAVE][2 * 128];
+  // fixed-order reduction: across the 16 lanes that share a column (in-wave
+  // butterfly), then across the workgroup's waves in index order
 #pragma unroll
-  for (int q = 0; q < KA; ++q) {
-    red[wave][lane * KA + q] = accA[q];
-    red[wave][NA + lane * KA + q] = accB[q];
+  for (int o = 1; o < 16; o <<= 1) {
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      accE[kk] += __shfl_xor(accE[kk], o, 64);
+      accY[kk] += __shfl_xor(accY[kk], o, 64);
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    sEE += __shfl_xor(sEE, o, 64);
+    sEY += __shfl_xor(sEY, o, 64);
+    sXX += __shfl_xor(sXX, o, 64);
+    sYY += __shfl_xor(sYY, o, 64);
+  }
+  __shared__ double red[NWAVE][2 * KK * 4 + 4];
+  if (l16 == 0) {
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      red[wave][(4 * kk + q)] = accE[kk];
+      red[wave][4 * KK + (4 * kk + q)] = accY[kk];
+    }
+  }
+  if (lane == 0) {
+    red[wave][8 * KK + 0] = sEE;
+    red[wave][8 * KK + 1] = sEY;
+    red[wave][8 * KK + 2] = sXX;
+    red[wave][8 * KK + 3] = sYY;
   }
   __syncthreads();
+  // compact record: [Us^T e (RB) | Es.e | Us^T y (RB) | Es.y | e.e e.y x.x y.y]
   double* __restrict__ out = p.partials + (int64_t)blockIdx.x * PW;
-  for (int idx = threadIdx.x; idx < 2 * NA; idx += PASS_THREADS) {
-    const int s = slot_of<RB>(idx, NA);
-    if (s < 0) continue;
+  for (int idx = threadIdx.x; idx < 2 * (RB + 1) + 4; idx += PASS_THREADS) {
+    const int src = idx < 2 * (RB + 1) ? (idx / (RB + 1)) * 4 * KK + idx % (RB + 1)
+                                       : 8 * KK + (idx - 2 * (RB + 1));
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) t += red[w][idx];
-    out[s] = t;
+    for (int w = 0; w < NWAVE; ++w) t += red[w][src];
+    out[idx] = t;
   }
-}
-
-template <typename TS, typename TIO, int RB>
-__global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
-  const DevState* __restrict__ st = p.st;
-  pass_body<TS, TIO, RB>(p, st, st->rs, st->r, st->pending, st->use_e);
 }
 
 template <typename TS, typename TIO>
