@@ -431,7 +431,7 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
   return !S.fail;
 }
 
-__global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
+__device__ __forceinline__ void core_body(const CoreArgs& c) {
   DevState* __restrict__ st = c.st;
   __shared__ double sA[MMAX * LDK];
   __shared__ double sV[MMAX * LDK];
@@ -712,6 +712,18 @@ __global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) {
     st->eig_valid = 0;
     if (sweeps > MAX_SWEEPS) st->status |= ST_NOCONV;
   }
+}
+
+__global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) { core_body(c); }
+
+__global__ __launch_bounds__(CORE_THREADS) void k_core_batch(const CoreArgs* __restrict__ cs) {
+  const CoreArgs c = cs[blockIdx.x];
+  core_body(c);
+}
+
+hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_core_batch, dim3(count), dim3(CORE_THREADS), 0, s, cs);
+  return hipGetLastError();
 }
 
 hipError_t launch_core(const CoreArgs& c, hipStream_t s) {

@@ -7,6 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
@@ -161,6 +164,104 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   return ODMD_OK;
 }
 
+// Descriptor tables of batched launches: a small ring of pinned host / device
+// buffer pairs per device; a slot is reused only after the copy recorded on
+// it has completed.
+struct BatchSlot {
+  void* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+struct BatchRing {
+  std::mutex mu;
+  BatchSlot slot[4];
+  int next = 0;
+};
+std::mutex g_ring_mu;
+std::map<int, std::unique_ptr<BatchRing>> g_rings;
+
+BatchRing* ring_for(int device) {
+  std::lock_guard<std::mutex> lk(g_ring_mu);
+  auto& p = g_rings[device];
+  if (!p) p.reset(new BatchRing());
+  return p.get();
+}
+
+odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
+  hipStream_t stream = hs[0]->stream;
+  // group streams by (storage type, rank bucket): one pass launch per group
+  std::map<std::pair<int, int>, std::vector<int32_t>> groups;
+  for (int32_t i = 0; i < count; ++i) groups[{hs[i]->basis == ODMD_F64, hs[i]->rb}].push_back(i);
+  const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
+  const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
+  BatchRing* ring = ring_for(hs[0]->device);
+  std::lock_guard<std::mutex> lk(ring->mu);
+  BatchSlot& sl = ring->slot[ring->next];
+  ring->next = (ring->next + 1) % 4;
+  if (sl.used) HIP_OK(hipEventSynchronize(sl.done));
+  if (sl.cap < bytes) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.dev) (void)hipFree(sl.dev);
+    sl.host = sl.dev = nullptr;
+    sl.cap = 0;
+    if (hipHostMalloc(&sl.host, bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&sl.dev, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return ODMD_ENOMEM;
+    }
+    sl.cap = bytes;
+  }
+  if (!sl.done) HIP_OK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+  PassDesc* pd = static_cast<PassDesc*>(sl.host);
+  CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
+  struct Launch { int first, nd, nblocks, f64, rb; };
+  std::vector<Launch> launches;
+  int k = 0;
+  for (auto& g : groups) {
+    Launch L{k, 0, 0, g.first.first, g.first.second};
+    for (int32_t i : g.second) {
+      odmd_t h = hs[i];
+      PassDesc& d = pd[k++];
+      d.Us = h->Us;
+      d.Es = h->Es;
+      d.x = xs[i];
+      d.y = ys[i];
+      d.partials = h->partials;
+      d.st = h->st;
+      d.n = h->n;
+      d.nblk = h->nblk;
+      d.blk0 = L.nblocks;
+      L.nblocks += h->nblk;
+      ++L.nd;
+    }
+    launches.push_back(L);
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    odmd_t h = hs[i];
+    CoreArgs& c = cd[i];
+    c.st = h->st;
+    c.partials = h->partials;
+    c.nblk = h->nblk;
+    c.r_max = h->r_max;
+    c.basis_f32 = h->basis == ODMD_F32;
+    c.jacobi_only = h->jacobi_only;
+    c.rb = h->rb;
+  }
+  HIP_OK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
+  const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
+  for (const Launch& L : launches)
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.f64, L.rb, stream));
+  HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(static_cast<char*>(sl.dev) + pass_bytes),
+                           count, stream));
+  // the slot (host staging and device table) is free again once the
+  // kernels that read the table have run
+  HIP_OK(hipEventRecord(sl.done, stream));
+  sl.used = true;
+  return ODMD_OK;
+}
+
 odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool out_f32) {
   CombineArgs c;
   c.st = h->st;
@@ -284,11 +385,7 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
     if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
   }
   HIP_OK(hipSetDevice(hs[0]->device));
-  for (int32_t i = 0; i < count; ++i) {
-    const odmd_status s = launch_update(hs[i], xs[i], ys[i]);
-    if (s != ODMD_OK) return s;
-  }
-  return ODMD_OK;
+  return launch_batch(hs, xs, ys, count);
 }
 
 odmd_status odmd_sync(odmd_t h) {

@@ -21,6 +21,21 @@ struct PassArgs {
 // rb: rank bucket (multiple of 8, >= r_max of the stream)
 hipError_t launch_pass(const PassArgs& p, int basis_f64, int rb, hipStream_t s);
 
+// One stream of a batched pass launch (device-resident table, sorted by blk0).
+struct PassDesc {
+  void* Us;
+  void* Es;
+  const void* x;
+  const void* y;
+  double* partials;
+  const DevState* st;
+  int64_t n;
+  int nblk;             // workgroups of this stream
+  int blk0;             // its first workgroup in the launch
+};
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis_f64, int rb,
+                             hipStream_t s);
+
 struct CoreArgs {
   DevState* st;
   const double* partials;
@@ -31,6 +46,8 @@ struct CoreArgs {
   int rb;               // rank bucket of the pass (compact partial records)
 };
 hipError_t launch_core(const CoreArgs& c, hipStream_t s);
+// one workgroup per entry of a device-resident CoreArgs table
+hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s);
 
 struct CombineArgs {
   const DevState* st;   // coefficients coefA / coefB and the basis layout

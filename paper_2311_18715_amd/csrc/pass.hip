@@ -68,7 +68,7 @@ template <> struct Mfma<float> {
 #endif
 
 template <typename TS, typename TIO, int RB>
-__global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
+__device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr int MT = ODMD_PASS_MT;        // 16-row blocks per unit
   constexpr int UR = 16 * MT;             // rows per unit
   constexpr int UPT = 64 / UR;            // units per 64-row tile
@@ -121,8 +121,8 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
   for (int kk = 0; kk < KK; ++kk) accE[kk] = accY[kk] = 0.0;
 
   const int64_t units = (p.n + UR - 1) / UR;
-  const int64_t u0 = (int64_t)blockIdx.x * units / p.nblk;
-  const int64_t u1 = (int64_t)(blockIdx.x + 1) * units / p.nblk;
+  const int64_t u0 = (int64_t)blk * units / p.nblk;
+  const int64_t u1 = (int64_t)(blk + 1) * units / p.nblk;
 
   // operands of one unit: A[mt][kk] = [Us Es](16 mt + l%16, 4 kk + l/16)
   auto load_unit = [&](int64_t u, TS (&A)[MT][KK], double (&xv)[MT], double (&yv)[MT]) {
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
   }
   __syncthreads();
   // compact record: [Us^T e (RB) | Es.e | Us^T y (RB) | Es.y | e.e e.y x.x y.y]
-  double* __restrict__ out = p.partials + (int64_t)blockIdx.x * PW;
+  double* __restrict__ out = p.partials + (int64_t)blk * PW;
   for (int idx = threadIdx.x; idx < 2 * (RB + 1) + 4; idx += PASS_THREADS) {
     const int src = idx < 2 * (RB + 1) ? (idx / (RB + 1)) * 4 * KK + idx % (RB + 1)
                                        : 8 * KK + (idx - 2 * (RB + 1));
@@ -284,6 +284,62 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
     for (int w = 0; w < NWAVE; ++w) t += red[w][src];
     out[idx] = t;
   }
+}
+
+template <typename TS, typename TIO, int RB>
+__global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
+  pass_body<TS, TIO, RB>(p, blockIdx.x);
+}
+
+// Many streams of one storage type and rank bucket in one launch: workgroup b
+// belongs to the stream whose block range [blk0, blk0 + nblk) contains b, and
+// runs exactly the work that workgroup b - blk0 of that stream's own launch
+// would (same partition, same reduction order: results are bitwise equal).
+template <typename TS, typename TIO, int RB>
+__global__ __launch_bounds__(PASS_THREADS) void k_pass_batch(const PassDesc* __restrict__ d, int nd) {
+  typedef const __attribute__((address_space(4))) PassDesc* cdesc;
+  cdesc D = (cdesc)d;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (D[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  PassArgs p;
+  p.Us = D[lo].Us;
+  p.Es = D[lo].Es;
+  p.x = D[lo].x;
+  p.y = D[lo].y;
+  p.partials = D[lo].partials;
+  p.st = D[lo].st;
+  p.n = D[lo].n;
+  p.units = 0;
+  p.nblk = D[lo].nblk;
+  pass_body<TS, TIO, RB>(p, b - D[lo].blk0);
+}
+
+template <typename TS, typename TIO>
+static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int rb, hipStream_t s) {
+  const dim3 grid(nblocks), block(PASS_THREADS);
+  switch (rb) {
+    case 8: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 8>), grid, block, 0, s, d, nd); break;
+    case 16: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 16>), grid, block, 0, s, d, nd); break;
+    case 24: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 24>), grid, block, 0, s, d, nd); break;
+    case 32: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 32>), grid, block, 0, s, d, nd); break;
+    case 40: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 40>), grid, block, 0, s, d, nd); break;
+    case 48: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 48>), grid, block, 0, s, d, nd); break;
+    case 56: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 56>), grid, block, 0, s, d, nd); break;
+    case 64: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 64>), grid, block, 0, s, d, nd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis_f64, int rb,
+                             hipStream_t s) {
+  return basis_f64 ? launch_batch_rb<double, double>(d, nd, nblocks, rb, s)
+                   : launch_batch_rb<float, float>(d, nd, nblocks, rb, s);
 }
 
 template <typename TS, typename TIO>
