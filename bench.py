@@ -42,6 +42,30 @@ def make_stream():
     return s, s.snapshots(0, SNAPS)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_pass_f64_r40_wake_n160k.md")
+PASS_SOURCES = ("pass.hip", "pass.h", "odmd_internal.h")
+
+
+def measured_traffic():
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
+    or None when the pass sources changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_18715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    m_sha = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_sha or not m_bytes or m_sha.group(1) != h.hexdigest():
+        return None
+    return int(m_bytes.group(1))
+
+
 def cpu_baseline(X, seconds: float = 15.0):
     """The FP64 oracle on this host: warm up to the saturated rank, then time
     as many updates as fit in about `seconds` (at least 5)."""
@@ -74,6 +98,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, copy MIB MiB once on the device (a reference "
+                         "kernel of known traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -167,9 +194,17 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBPS, 4),
             "bytes_per_launch": bytes_upd,
             "launches_timed": int(pass_ms.size),
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
+    if args.calibrate_copy > 0:
+        a = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["calibration_copy_bytes"] = 2 * a.numel() * 8
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(X)
     print(json.dumps(result), flush=True)
