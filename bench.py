@@ -92,12 +92,204 @@ def cpu_baseline(X, seconds: float = 15.0):
                       f"saturated rank {R_MAX} (after {k0} warm-up updates), FP64 NumPy/LAPACK"}
 
 
+# (ii) S independent n = 160k streams through the batched update
+CONC_S = (8, 32, 128)
+CONC_WARM, CONC_STEPS, CONC_OFFSET = 100, 200, 7
+
+
+def concurrent_streams(torch, Xd, bytes_upd):
+    """S independent copies of the benchmark workload, advanced together by
+    odmd_update_batch.  Stream i reads the snapshot sequence shifted by
+    CONC_OFFSET * i, so every stream has its own (chained) data; the
+    working set (S x 52 MB of basis) is far beyond the last-level cache."""
+    from paper_2311_18715_amd.odmd import ODMD, handle_array, update_batch_ptrs
+    n = Xd.shape[1]
+    row = np.uint64(n * Xd.element_size())
+    base = np.uint64(Xd.data_ptr())
+    out = {}
+    for S in CONC_S:
+        assert CONC_OFFSET * (S - 1) + CONC_WARM + CONC_STEPS < Xd.shape[0]
+        models = [ODMD(n, R_MAX, TOL) for _ in range(S)]
+        H = handle_array(models)
+        offs = np.arange(S, dtype=np.uint64) * np.uint64(CONC_OFFSET)
+
+        def step(k):
+            xp = base + (offs + np.uint64(k)) * row
+            update_batch_ptrs(H, xp, xp + row)
+
+        for k in range(CONC_WARM):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(CONC_WARM, CONC_WARM + CONC_STEPS):
+            step(k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for m in models:
+            m.sync()
+        assert all(m.info().r == R_MAX for m in models)
+        ups = S * CONC_STEPS / dt
+        out[str(S)] = {"stream_updates_per_s": round(ups, 1),
+                       "us_per_batched_step": round(dt / CONC_STEPS * 1e6, 1),
+                       "hbm_gbps_algorithmic": round(ups * bytes_upd / 1e9, 1),
+                       "frac_of_peak": round(ups * bytes_upd / 1e9 / PEAK_HBM_GBPS, 4)}
+        for m in models:
+            m.close()
+        del models
+        torch.cuda.empty_cache()
+        print(f"concurrent S={S}: {out[str(S)]}", file=sys.stderr, flush=True)
+    return out
+
+
+# many-stream form: 256 independent streams, FP32 basis batched vs FP64 per stream
+MANY_COUNT, MANY_WARM, MANY_STEPS, MANY_CHUNK, MANY_TOL = 256, 40, 100, 20, 1e-8
+
+
+class _DeviceStream:
+    """Planted linear stream x_k = Re(sum_j phi_j lam_j^k b_j) generated on the
+    device: Gaussian i.i.d. modes from a seeded torch generator, eigenvalues
+    and amplitudes from the host PCG64 recipe of synth.random_planted."""
+
+    def __init__(self, torch, n, rank, seed):
+        import math
+        g = np.random.Generator(np.random.PCG64(seed))
+        npair, nreal = rank // 2, rank % 2
+        p = npair + nreal
+        lam = np.empty(p, np.complex128)
+        for j in range(npair):
+            lam[j] = g.uniform(0.97, 1.0) * np.exp(1j * g.uniform(2 * np.pi * 0.005, 2 * np.pi * 0.1))
+        if nreal:
+            lam[p - 1] = g.uniform(0.97, 1.0)
+        amp = (g.standard_normal(p) + 1j * g.standard_normal(p)) / math.sqrt(2.0)
+        if nreal:
+            amp[p - 1] = amp[p - 1].real
+        tg = torch.Generator(device="cuda")
+        tg.manual_seed(int(seed))
+        self.re = torch.randn((p, n), generator=tg, device="cuda", dtype=torch.float64) / math.sqrt(2 * n)
+        self.im = torch.randn((p, n), generator=tg, device="cuda", dtype=torch.float64) / math.sqrt(2 * n)
+        if nreal:
+            self.re[p - 1] *= math.sqrt(2.0)
+            self.im[p - 1] = 0.0
+        self.lam, self.amp, self.n = lam, amp, n
+        self.planted = np.concatenate([lam[:npair], np.conj(lam[:npair]), lam[npair:]])
+        self.torch = torch
+
+    def chunk(self, k0, count):
+        """Snapshots k0 .. k0+count-1 as rows of a (count, n) FP64 tensor."""
+        k = np.arange(k0, k0 + count)[:, None]
+        C = self.amp[None, :] * self.lam[None, :] ** k
+        cre = self.torch.from_numpy(np.ascontiguousarray(C.real)).cuda()
+        cim = self.torch.from_numpy(np.ascontiguousarray(C.imag)).cuda()
+        return cre @ self.re - cim @ self.im
+
+
+def _rel_eig_diff(ref, got):
+    """Greedy nearest matching of the eigenvalues of ref with |lam| >= 1e-2
+    max|lam|; the largest relative distance."""
+    big = ref[np.abs(ref) >= 1e-2 * np.abs(ref).max()]
+    free = list(range(len(got)))
+    worst = 0.0
+    for v in sorted(big, key=lambda z: -abs(z)):
+        if not free:
+            return float("inf")
+        j = min(free, key=lambda t: abs(got[t] - v))
+        free.remove(j)
+        worst = max(worst, abs(got[j] - v) / abs(v))
+    return worst
+
+
+def many_streams(torch):
+    """256 streams (n log-uniform in [1e4, 1e6], planted rank in {6..30},
+    r_max in {16..64}): the FP32-basis batched update against a loop of
+    per-stream FP64 updates over the same snapshots; eigenvalue agreement
+    between the two and against the planted values."""
+    import ctypes
+    from paper_2311_18715_amd import synth
+    from paper_2311_18715_amd.odmd import ODMD, handle_array, update_batch_ptrs, lib
+    descs = synth.batched_streams(MANY_COUNT)
+    gens = [_DeviceStream(torch, n, rank, seed) for (n, rank, _, seed) in descs]
+    m32 = [ODMD(n, rmax, MANY_TOL, basis="f32") for (n, _, rmax, _) in descs]
+    m64 = [ODMD(n, rmax, MANY_TOL, basis="f64") for (n, _, rmax, _) in descs]
+    H32 = handle_array(m32)
+    L = lib()
+    ns = np.array([d[0] for d in descs], dtype=np.uint64)
+    total = MANY_WARM + MANY_STEPS
+    t_batch = t_loop = 0.0
+    timed = 0
+    for k0 in range(0, total, MANY_CHUNK):
+        T = min(MANY_CHUNK, total - k0)
+        X64 = [g.chunk(k0, T + 1) for g in gens]
+        X32 = [x.float() for x in X64]
+        b32 = np.array([x.data_ptr() for x in X32], dtype=np.uint64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(T):
+            xp = b32 + np.uint64(k) * ns * np.uint64(4)
+            update_batch_ptrs(H32, xp, xp + ns * np.uint64(4))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(T):
+            for m, x in zip(m64, X64):
+                row = x.shape[1] * 8
+                L.odmd_update(m.handle, ctypes.c_void_p(x.data_ptr() + k * row),
+                              ctypes.c_void_p(x.data_ptr() + (k + 1) * row))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(f"many streams: steps {k0}..{k0 + T - 1} batched {t1 - t0:.3f} s, "
+              f"per-stream loop {t2 - t1:.3f} s", file=sys.stderr, flush=True)
+        if k0 >= MANY_WARM:
+            t_batch += t1 - t0
+            t_loop += t2 - t1
+            timed += T
+        del X64, X32
+    # Eigenvalues: FP32 batched against FP64 where both kept the same rank
+    # (the FP32 tolerance floor can drop a direction that FP64 keeps), and
+    # each form against the planted values where it kept all of them.
+    worst_pair = worst_planted32 = worst_planted64 = 0.0
+    same_rank = full32 = full64 = 0
+    pair_diffs = []
+    for g, a, b, (n, rank, rmax, _) in zip(gens, m32, m64, descs):
+        la, _ = a.eigs(vectors=False)
+        lb, _ = b.eigs(vectors=False)
+        if len(la) == len(lb):
+            same_rank += 1
+            pair_diffs.append(_rel_eig_diff(lb, la))
+            worst_pair = max(worst_pair, pair_diffs[-1])
+        if len(la) == rank:
+            full32 += 1
+            worst_planted32 = max(worst_planted32, _rel_eig_diff(g.planted, la))
+        if len(lb) == rank:
+            full64 += 1
+            worst_planted64 = max(worst_planted64, _rel_eig_diff(g.planted, lb))
+    ups32 = MANY_COUNT * timed / t_batch
+    ups64 = MANY_COUNT * timed / t_loop
+    res = {"streams": MANY_COUNT, "steps_timed": timed, "warmup_steps": MANY_WARM,
+           "fp32_batched_stream_updates_per_s": round(ups32, 1),
+           "fp64_per_stream_loop_updates_per_s": round(ups64, 1),
+           "speedup": round(ups32 / ups64, 2),
+           "eig_rel_diff_fp32_vs_fp64_max": float(f"{worst_pair:.3e}"),
+           "streams_same_rank_fp32_fp64": same_rank,
+           "eig_rel_diff_fp32_vs_fp64_median": float(f"{np.median(pair_diffs):.3e}"),
+           "streams_eig_within_1e-4": int(np.sum(np.array(pair_diffs) <= 1e-4)),
+           "eig_rel_err_vs_planted_max": {"fp32": float(f"{worst_planted32:.3e}"),
+                                          "fp64": float(f"{worst_planted64:.3e}")},
+           "streams_with_full_planted_rank": {"fp32": full32, "fp64": full64},
+           "n_total": int(ns.sum())}
+    for m in m32 + m64:
+        m.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the concurrent-stream and many-stream sections")
+    ap.add_argument("--many-only", action="store_true",
+                    help="run only the many-stream section (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy MIB MiB once on the device (a reference "
                          "kernel of known traffic for hardware byte counters)")
@@ -111,6 +303,9 @@ def main():
     from paper_2311_18715_amd.odmd import ODMD
 
     torch.cuda.set_device(0)
+    if args.many_only:
+        print(json.dumps({"many_streams": many_streams(torch)}), flush=True)
+        return
     _, X = make_stream()
     n = X.shape[0]
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda")
@@ -198,6 +393,13 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
+    if not args.no_extra:
+        del models
+        torch.cuda.empty_cache()
+        result["concurrent_n160k"] = concurrent_streams(torch, Xd, bytes_upd)
+        del Xd, out
+        torch.cuda.empty_cache()
+        result["many_streams"] = many_streams(torch)
     if args.calibrate_copy > 0:
         a = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

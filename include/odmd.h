@@ -84,6 +84,9 @@ odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
  *   workspace / workspace_bytes: NULL/0 to let the library allocate, else
  *          a device buffer of at least odmd_state_bytes(...) bytes, 256-byte
  *          aligned, owned by the caller and kept alive until odmd_destroy.
+ *   Either way the handle also holds 64 bytes of pinned host memory, into
+ *   which the device reports the rank after each update; the host sizes the
+ *   next launches from it (work follows the live rank, not r_max).
  */
 odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
                            odmd_dtype io, void* hip_stream, void* workspace,

@@ -431,7 +431,7 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
   return !S.fail;
 }
 
-__device__ __forceinline__ void core_body(const CoreArgs& c) {
+__device__ __forceinline__ void core_update(const CoreArgs& c) {
   DevState* __restrict__ st = c.st;
   __shared__ double sA[MMAX * LDK];
   __shared__ double sV[MMAX * LDK];
@@ -460,10 +460,13 @@ __device__ __forceinline__ void core_body(const CoreArgs& c) {
   if (tid < RMAX) sw[tid] = tid < r ? st->w[tid] : 0.0;
 
   // 1. fixed-order reduction of the per-workgroup partial sums (compact
-  //    records of pwc values, read as 16-byte pairs; sV is scratch here)
+  //    records of pwc values, read as 16-byte pairs; sV is scratch here).
+  //    The slot count does not depend on the record length, so every value
+  //    is summed in the same order whatever bucket the pass ran with (x.x of
+  //    a pair is then bit-equal to y.y of the pair before it).
   {
     const int pwc = 2 * (c.rb + 1) + 4, pw2 = pwc / 2;
-    const int nslot = CORE_THREADS / pw2;
+    constexpr int nslot = CORE_THREADS / (PW / 2);
     if (tid < nslot * pw2) {
       const int g = tid % pw2, sl = tid / pw2;
       double ax = 0.0, ay = 0.0;
@@ -711,6 +714,17 @@ __device__ __forceinline__ void core_body(const CoreArgs& c) {
     st->sweeps = sweeps;
     st->eig_valid = 0;
     if (sweeps > MAX_SWEEPS) st->status |= ST_NOCONV;
+  }
+}
+
+// One update of the small state, then the rank it leaves, tagged with the
+// update's sequence number, to the host-visible feedback word (the host
+// sizes later launches from it).
+__device__ __forceinline__ void core_body(const CoreArgs& c) {
+  core_update(c);
+  if (threadIdx.x == 0 && c.fb) {
+    const unsigned r = (unsigned)c.st->r;
+    *reinterpret_cast<volatile unsigned*>(c.fb) = ((c.seq & 0xFFFFFFu) << 8) | (r & 0xFFu);
   }
 }
 

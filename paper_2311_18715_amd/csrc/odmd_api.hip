@@ -44,6 +44,11 @@ struct odmd_s {
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
   std::vector<hipEvent_t> ev;   // triples: before pass, after pass, after core
   size_t ev_used = 0;
+  // Rank feedback: the core writes (seq << 8) | rank into this pinned host
+  // word after every update; seq counts the updates issued on the handle.
+  unsigned* fb_host = nullptr;
+  unsigned* fb_dev = nullptr;
+  unsigned seq = 0;
 };
 
 namespace {
@@ -125,6 +130,18 @@ odmd_status copy_field(odmd_t h, T* dst, const T* src_dev, size_t count) {
   return ODMD_OK;
 }
 
+// Live-column bucket for the next pass: an upper bound on the stored and
+// the logical rank after the last issued update.  The rank grows by at most
+// one per update, so the last rank the device reported plus the number of
+// updates issued since bounds it.  The bound is a multiple of 8 and never
+// exceeds the tile capacity.
+int live_bucket(odmd_t h) {
+  const unsigned v = __atomic_load_n(h->fb_host, __ATOMIC_ACQUIRE);
+  const unsigned lag = (h->seq - (v >> 8)) & 0xFFFFFFu;
+  const int64_t bound = std::min<int64_t>(h->r_max, (int64_t)(v & 0xFFu) + lag);
+  return std::max(8, rank_bucket((int)bound));
+}
+
 odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   hipEvent_t* ev = nullptr;
   if (h->prof) {
@@ -149,7 +166,10 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.n = h->n;
   p.units = h->units;
   p.nblk = h->nblk;
-  HIP_OK(launch_pass(p, h->basis == ODMD_F64, h->rb, h->stream));
+  p.ct = h->rb;
+  const int kb = live_bucket(h);
+  HIP_OK(launch_pass(p, h->basis == ODMD_F64, kb, h->stream));
+  h->seq = (h->seq + 1) & 0xFFFFFFu;
   if (ev) HIP_OK(hipEventRecord(ev[1], h->stream));
   CoreArgs c;
   c.st = h->st;
@@ -158,7 +178,9 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.r_max = h->r_max;
   c.basis_f32 = h->basis == ODMD_F32;
   c.jacobi_only = h->jacobi_only;
-  c.rb = h->rb;
+  c.rb = kb;
+  c.fb = h->fb_dev;
+  c.seq = h->seq;
   HIP_OK(launch_core(c, h->stream));
   if (ev) HIP_OK(hipEventRecord(ev[2], h->stream));
   return ODMD_OK;
@@ -192,8 +214,12 @@ BatchRing* ring_for(int device) {
 odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
   hipStream_t stream = hs[0]->stream;
   // group streams by (storage type, rank bucket): one pass launch per group
+  std::vector<int> kb(count);
   std::map<std::pair<int, int>, std::vector<int32_t>> groups;
-  for (int32_t i = 0; i < count; ++i) groups[{hs[i]->basis == ODMD_F64, hs[i]->rb}].push_back(i);
+  for (int32_t i = 0; i < count; ++i) {
+    kb[i] = live_bucket(hs[i]);
+    groups[{hs[i]->basis == ODMD_F64, kb[i]}].push_back(i);
+  }
   const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
   const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
   BatchRing* ring = ring_for(hs[0]->device);
@@ -232,6 +258,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
       d.st = h->st;
       d.n = h->n;
       d.nblk = h->nblk;
+      d.ct = h->rb;
       d.blk0 = L.nblocks;
       L.nblocks += h->nblk;
       ++L.nd;
@@ -247,7 +274,10 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     c.r_max = h->r_max;
     c.basis_f32 = h->basis == ODMD_F32;
     c.jacobi_only = h->jacobi_only;
-    c.rb = h->rb;
+    c.rb = kb[i];
+    h->seq = (h->seq + 1) & 0xFFFFFFu;
+    c.fb = h->fb_dev;
+    c.seq = h->seq;
   }
   HIP_OK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
   const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
@@ -335,11 +365,21 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
     delete s;
     return ODMD_EDEVICE;
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->fb_host), 64,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&s->fb_dev), s->fb_host, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    if (s->fb_host) (void)hipHostFree(s->fb_host);
+    delete s;
+    return ODMD_ENOMEM;
+  }
+  *s->fb_host = 0;
   if (workspace) {
     s->mem = static_cast<char*>(workspace);
   } else {
     if (hipMalloc(&s->mem, L.total) != hipSuccess) {
       (void)hipGetLastError();
+      (void)hipHostFree(s->fb_host);
       delete s;
       return ODMD_ENOMEM;
     }
@@ -357,6 +397,7 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
       hipStreamSynchronize(s->stream) != hipSuccess) {
     (void)hipGetLastError();
     if (s->own) (void)hipFree(s->mem);
+    (void)hipHostFree(s->fb_host);
     delete s;
     return ODMD_EDEVICE;
   }
@@ -554,6 +595,7 @@ odmd_status odmd_destroy(odmd_t h) {
     s = ODMD_EDEVICE;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->own && hipFree(h->mem) != hipSuccess) s = ODMD_EDEVICE;
+  if (h->fb_host && hipHostFree(h->fb_host) != hipSuccess) s = ODMD_EDEVICE;
   (void)hipGetLastError();
   delete h;
   return s;

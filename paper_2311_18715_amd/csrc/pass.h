@@ -16,9 +16,11 @@ struct PassArgs {
   int64_t n;
   int64_t units;        // 32-row units, ceil(n / 32)
   int nblk;             // workgroups
+  int ct;               // column capacity of a basis tile (rank bucket of r_max)
 };
 
-// rb: rank bucket (multiple of 8, >= r_max of the stream)
+// rb: live-column bucket of the launch (multiple of 8, >= the stored and
+// the logical rank of the stream, <= its tile capacity ct)
 hipError_t launch_pass(const PassArgs& p, int basis_f64, int rb, hipStream_t s);
 
 // One stream of a batched pass launch (device-resident table, sorted by blk0).
@@ -32,6 +34,7 @@ struct PassDesc {
   int64_t n;
   int nblk;             // workgroups of this stream
   int blk0;             // its first workgroup in the launch
+  int ct;               // column capacity of its basis tiles
 };
 hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis_f64, int rb,
                              hipStream_t s);
@@ -43,7 +46,9 @@ struct CoreArgs {
   int r_max;
   int basis_f32;        // also keep an FP32 copy of the rotation
   int jacobi_only;      // skip the secular solver (diagnostics)
-  int rb;               // rank bucket of the pass (compact partial records)
+  int rb;               // live-column bucket of the pass (compact partial records)
+  unsigned* fb;         // host-visible word: (seq << 8) | rank after this update
+  unsigned seq;         // update sequence number (24 bits) of this launch
 };
 hipError_t launch_core(const CoreArgs& c, hipStream_t s);
 // one workgroup per entry of a device-resident CoreArgs table

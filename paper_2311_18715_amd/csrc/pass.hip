@@ -75,7 +75,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr bool PF = ODMD_PASS_PREFETCH;
   constexpr int KK = RB / 4 + 1;          // k-steps: RB basis columns + the Es column
   constexpr int NT = (RB + 15) / 16;      // 16-column output blocks
-  constexpr int CT = RB;                  // column capacity of a tile
   constexpr int NWAVE = PASS_THREADS / 64;
   typedef typename Mfma<TS>::acc_t acc_t;
 
@@ -128,7 +127,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   auto load_unit = [&](int64_t u, TS (&A)[MT][KK], double (&xv)[MT], double (&yv)[MT]) {
     const int64_t tile = u / UPT;
     const int half = (int)(u % UPT);
-    const TS* __restrict__ T = Us + tile * (int64_t)CT * 64;
+    const TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int rr = UR * half + 16 * mt + l16;
@@ -161,7 +160,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     if (!PF) load_unit(u, A, xv, yv);
     const int64_t tile = u / UPT;
     const int half = (int)(u % UPT);
-    TS* __restrict__ T = Us + tile * (int64_t)CT * 64;
+    TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
     const int64_t rowbase = tile * 64 + UR * half;
 
     // e = x - [Us Es] [a; beta], in FP64
@@ -316,6 +315,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass_batch(const PassDesc* __r
   p.n = D[lo].n;
   p.units = 0;
   p.nblk = D[lo].nblk;
+  p.ct = D[lo].ct;
   pass_body<TS, TIO, RB>(p, b - D[lo].blk0);
 }
 

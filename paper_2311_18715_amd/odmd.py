@@ -230,3 +230,24 @@ def update_batch(models, xs, ys) -> None:
     X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
     Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
     _check(lib().odmd_update_batch(H, X, Y, n), "odmd_update_batch")
+
+
+def handle_array(models) -> np.ndarray:
+    """The models' handles as a uint64 array, for update_batch_ptrs."""
+    return np.array([m.handle.value for m in models], dtype=np.uint64)
+
+
+def update_batch_ptrs(handles: np.ndarray, xptrs: np.ndarray, yptrs: np.ndarray) -> None:
+    """odmd_update_batch on pre-built uint64 arrays of handles and device
+    pointers (no per-stream Python objects: for loops over many streams).
+    The caller keeps the memory behind the pointers alive and correctly
+    typed (n elements of each stream's snapshot type)."""
+    count = len(handles)
+    if len(xptrs) != count or len(yptrs) != count:
+        raise ValueError("handles, xptrs and yptrs must have the same length")
+    h = np.ascontiguousarray(handles, dtype=np.uint64)
+    x = np.ascontiguousarray(xptrs, dtype=np.uint64)
+    y = np.ascontiguousarray(yptrs, dtype=np.uint64)
+    vpp = ctypes.POINTER(ctypes.c_void_p)
+    _check(lib().odmd_update_batch(h.ctypes.data_as(vpp), x.ctypes.data_as(vpp),
+                                   y.ctypes.data_as(vpp), count), "odmd_update_batch")
