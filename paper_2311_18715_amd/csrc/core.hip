@@ -446,15 +446,18 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __shared__ int flag;
   __shared__ double sc[8];
   __shared__ int si[4];
+  __shared__ double sQ[CMAX * RMAX];   // Q (m x r), row c at sQ + c*RMAX
 
   const int tid = threadIdx.x;
-  const int r = st->r, rs = st->rs, pending = st->pending;
+  const int r = st->r, m = st->m, refolded = st->refold;
 
-  // 0. stage the previous rotation (in sA, free until the SVD) and the
-  //    shifted product C in LDS with one coalesced pass each
+  // 0. stage Q and the shifted product C in LDS with coalesced passes
+  for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
+    const int c0 = idx / RMAX, j = idx % RMAX;
+    sQ[idx] = (c0 < m && j < r) ? st->Q[idx] : 0.0;
+  }
   for (int idx = tid; idx < RMAX * RMAX; idx += CORE_THREADS) {
     const int j = idx % RMAX, k = idx / RMAX;
-    sA[idx] = (pending && j < rs && k < r) ? st->G[idx] : 0.0;
     sC[idx] = (j < r && k < r) ? st->C[idx] : 0.0;
   }
   if (tid < RMAX) sw[tid] = tid < r ? st->w[tid] : 0.0;
@@ -465,7 +468,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   //    is summed in the same order whatever bucket the pass ran with (x.x of
   //    a pair is then bit-equal to y.y of the pair before it).
   {
-    const int pwc = 2 * (c.rb + 1) + 4, pw2 = pwc / 2;
+    const int pwc = 2 * c.rb + 4, pw2 = pwc / 2;
     constexpr int nslot = CORE_THREADS / (PW / 2);
     if (tid < nslot * pw2) {
       const int g = tid % pw2, sl = tid / pw2;
@@ -484,36 +487,33 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       double t = 0.0;
       for (int sl = 0; sl < nslot; ++sl) t += sV[sl * pwc + tid];
       const int rb = c.rb;
-      int slot;
-      if (tid < rb) slot = P_SUE + tid;
-      else if (tid == rb) slot = P_SEE;
-      else if (tid <= 2 * rb) slot = P_SUY + (tid - rb - 1);
-      else if (tid == 2 * rb + 1) slot = P_SEY;
-      else slot = tid == 2 * rb + 2 ? P_EE : (tid == 2 * rb + 3 ? P_EY : (tid == 2 * rb + 4 ? P_XX : P_YY));
-      tot[slot] = t;
+      const int at = tid < rb ? P_SUE + tid : (tid < 2 * rb ? P_SUY + (tid - rb) : P_EE + (tid - 2 * rb));
+      tot[at] = t;
     }
     __syncthreads();
   }
 
-  // 2. second projection p2 = U^T e and U^T y in the basis the pass used
+  // 2. second projection p2 = U^T e = Q^T S^T e and U^T y = Q^T S^T y, with
+  //    the stored columns and the Q the pass read
   if (tid < r) {
-    double a2, b2;
-    if (pending) {
-      a2 = st->g[tid] * tot[P_SEE];
-      b2 = st->g[tid] * tot[P_SEY];
+    double a2 = 0.0, b2 = 0.0;
 #pragma unroll 8
-      for (int j = 0; j < rs; ++j) {
-        a2 += sA[tid * RMAX + j] * tot[P_SUE + j];
-        b2 += sA[tid * RMAX + j] * tot[P_SUY + j];
-      }
-    } else {
-      a2 = tot[P_SUE + tid];
-      b2 = tot[P_SUY + tid];
+    for (int c0 = 0; c0 < m; ++c0) {
+      a2 += sQ[c0 * RMAX + tid] * tot[P_SUE + c0];
+      b2 += sQ[c0 * RMAX + tid] * tot[P_SUY + c0];
     }
     p2[tid] = a2;
     pyr[tid] = b2;
   }
   __syncthreads();
+  // a refold pass left U = S[:, :r] (Q = I); the update below continues from it
+  if (refolded) {
+    for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
+      const int c0 = idx / RMAX, j = idx % RMAX;
+      sQ[idx] = (c0 == j && j < r) ? 1.0 : 0.0;
+    }
+  }
+  const int meff = refolded ? r : m;   // stored columns U is built from; e sits in column meff
 
   // 3. checks, residual norm, growth test
   if (tid == 0) {
@@ -527,7 +527,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
           isfinite(py2))) {
       skip = ST_NONFINITE;
-    } else if (st->m > 0 && xx != st->yy_prev) {
+    } else if (st->m_acc > 0 && xx != st->yy_prev) {
       skip = ST_SEQ;
     }
     double rho = sqrt(fmax(ee - pp, 0.0));
@@ -542,14 +542,23 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __syncthreads();
   const int skip = si[0];
   if (skip) {
-    // The pass already wrote the rotated basis: it is now the stored one.
-    if (tid < RMAX) st->a[tid] = tid < r ? st->py[tid] : 0.0;
+    // The model is unchanged.  If the pass refolded, the stored columns now
+    // hold U itself: Q = I, m = r and the next projection uses p_y directly.
+    if (refolded) {
+      for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
+        const int c0 = idx / RMAX, j = idx % RMAX;
+        const double v = (c0 == j && j < r) ? 1.0 : 0.0;
+        st->Q[idx] = v;
+        if (c.basis_f32) st->Q32[idx] = (float)v;
+      }
+      if (tid < CMAX) st->a[tid] = tid < r ? st->py[tid] : 0.0;
+    }
     if (tid == 0) {
       st->status |= skip;
-      st->rs = r;
-      st->pending = 0;
-      st->use_e = 0;
-      st->beta = 0.0;
+      if (refolded) {
+        st->m = r;
+        st->refold = 0;
+      }
     }
     return;
   }
@@ -599,12 +608,12 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int above = __syncthreads_count(tid < M && smax > 0.0 && sd[tid] > st->tol * smax);
   const int rn = min(above, c.r_max);
   if (rn == 0) {   // nothing kept (zero snapshots so far)
+    if (tid < CMAX) st->a[tid] = 0.0;
     if (tid == 0) {
       st->r = 0;
-      st->rs = 0;
-      st->pending = 0;
-      st->use_e = 0;
-      st->m += 1;
+      st->m = 0;
+      st->refold = 0;
+      st->m_acc += 1;
       st->yy_prev = sc[2];
       st->last_rho = rho;
       st->sweeps = sweeps;
@@ -630,30 +639,24 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   }
   __syncthreads();
 
-  // 8. rotation for the next pass: U' = U G + e g^T with
-  //    G = U_k[:r, :r'] - (p2 / rho) U_k[r, :r'],  g = U_k[r, :r'] / rho
+  // 8. The update's rotation U' = [U q] U_k[:, :r'] in the deferred form:
+  //    U = S Q and q = (e - U p2) / rho with e stored as column meff, so
+  //    U' = S Q' with Q' = [Q G; g^T] (rows < meff, then row meff), where
+  //      G = U_k[:r, :r'] - (p2 / rho) U_k[r, :r'],   g = U_k[r, :r'] / rho.
+  //    Q G is formed on the matrix cores straight from U_k (K V_k in sA):
+  //      (Q G)[c, k] = ( (Q U')[c, k] - irho U'[r, k] (Q p2)[c] ) / sigma'_k
+  //    with U'[i, k] = sA[perm[k] * LDK + i].
   const double irho = grow ? 1.0 / rho : 0.0;
-  for (int idx = tid; idx < RMAX * RMAX; idx += CORE_THREADS) {
-    const int j = idx % RMAX, k = idx / RMAX;   // row j of G (input column), column k
-    double v = 0.0;
-    if (j < r && k < rn) {
-      const int pk = perm[k];
-      const double inv = 1.0 / sd[pk];
-      v = (sA[pk * LDK + j] - p2[j] * irho * sA[pk * LDK + r]) * inv;
-    }
-    st->G[k * RMAX + j] = v;
-    if (c.basis_f32) st->G32[k * RMAX + j] = (float)v;
+  const int mnew = meff + grow;
+  // (Q p2)[c] into red, G p_y into pvec (the next pass's a needs it)
+  if (tid < CMAX) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < r; ++j) s += sQ[tid * RMAX + j] * p2[j];
+    red[tid] = s;
   }
   if (tid < RMAX) {
-    double gk = 0.0;
-    if (tid < rn) {
-      const int pk = perm[tid];
-      gk = sA[pk * LDK + r] * irho / sd[pk];
-    }
-    st->g[tid] = gk;
-    if (c.basis_f32) st->g32[tid] = (float)gk;
-    // a = G p1 with p1 = new p_y (the next x equals this y):
-    // a_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
+    // (G p_y)_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
     double av = 0.0, bsum = 0.0;
     if (tid < r) {
 #pragma unroll 8
@@ -663,14 +666,82 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       }
       av -= p2[tid] * irho * bsum;
     }
-    st->a[tid] = av;
-    if (tid == 0) {
-      double b = 0.0;
-      for (int k = 0; k < rn; ++k) b += urk[k] * pyn[k];
-      st->beta = b * irho;
-    }
+    pvec[tid] = av;          // pvec is free after the SVD: G p_y
   }
   __syncthreads();
+  // Q' tiles: CMAX/16 (rounded up) row blocks (c) x 4 column blocks (k) of
+  // 16 x 16, at most two per wave
+  typedef double d4_t __attribute__((ext_vector_type(4)));
+  constexpr int NQT = 4 * ((CMAX + 15) / 16);
+  static_assert(NQT <= 2 * (CORE_THREADS / 64), "two Q' tiles per wave at most");
+  d4_t qt[2];
+  {
+    const int wv = tid >> 6, l = tid & 63;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int tile = wv + 16 * h;
+      d4_t d = {0.0, 0.0, 0.0, 0.0};
+      if (tile < NQT) {
+        const int c0 = 16 * (tile >> 2), k0 = 16 * (tile & 3);
+        const int kb = k0 + (l & 15);
+        const int pk = kb < rn ? perm[kb] : 0;
+        for (int j0 = 0; j0 < r; j0 += 4) {
+          const int j = j0 + (l >> 4);
+          const int ca = c0 + (l & 15);
+          const double av = (j < r && ca < CMAX) ? sQ[ca * RMAX + j] : 0.0;
+          const double bv = (j < r && kb < rn) ? sA[pk * LDK + j] : 0.0;
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+        }
+        // element v of lane l: row c0 + 4 v + l/16, column k0 + l%16
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cr = c0 + 4 * v + (l >> 4);
+          double out = 0.0;
+          if (kb < rn) {
+            const double inv = 1.0 / sd[pk];
+            const double urr = sA[pk * LDK + r];
+            if (cr < meff) out = (d[v] - irho * urr * red[cr]) * inv;
+            else if (cr == meff && grow) out = urr * irho * inv;
+          }
+          d[v] = out;
+        }
+      }
+      qt[h] = d;
+    }
+  }
+  // next first-projection coefficients a = Q' p_y (rows < meff: Q (G p_y);
+  // row meff: g . p_y)
+  if (tid < CMAX) {
+    double av = 0.0;
+    if (tid < meff) {
+#pragma unroll 8
+      for (int j = 0; j < r; ++j) av += sQ[tid * RMAX + j] * pvec[j];
+    } else if (tid == meff && grow) {
+      double b = 0.0;
+      for (int k = 0; k < rn; ++k) b += urk[k] * pyn[k];
+      av = b * irho;
+    }
+    st->a[tid] = av;
+  }
+  __syncthreads();   // every thread is done reading Q: write Q' in place
+  {
+    const int wv = tid >> 6, l = tid & 63;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int tile = wv + 16 * h;
+      if (tile < NQT) {
+        const int c0 = 16 * (tile >> 2), k0 = 16 * (tile & 3);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cr = c0 + 4 * v + (l >> 4);
+          if (cr >= CMAX) continue;
+          const int idx = cr * RMAX + k0 + (l & 15);
+          st->Q[idx] = qt[h][v];
+          if (c.basis_f32) st->Q32[idx] = (float)qt[h][v];
+        }
+      }
+    }
+  }
 
   // 9. T = E V_k with E = [[C, 0], [w^T, 0]] (into sA, no longer needed)
   for (int idx = tid; idx < M * rn; idx += CORE_THREADS) {
@@ -704,11 +775,10 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     st->py[tid] = pyn[tid];
   }
   if (tid == 0) {
-    st->rs = r;
     st->r = rn;
-    st->pending = 1;
-    st->use_e = grow;
-    st->m += 1;
+    st->m = mnew;
+    st->refold = mnew >= c.ct;   // no free column for the next residual
+    st->m_acc += 1;
     st->yy_prev = sc[2];
     st->last_rho = rho;
     st->sweeps = sweeps;
@@ -717,14 +787,14 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   }
 }
 
-// One update of the small state, then the rank it leaves, tagged with the
-// update's sequence number, to the host-visible feedback word (the host
-// sizes later launches from it).
+// One update of the small state, then the stored-column count it leaves,
+// tagged with the update's sequence number, to the host-visible feedback
+// word (the host sizes later launches from it).
 __device__ __forceinline__ void core_body(const CoreArgs& c) {
   core_update(c);
   if (threadIdx.x == 0 && c.fb) {
-    const unsigned r = (unsigned)c.st->r;
-    *reinterpret_cast<volatile unsigned*>(c.fb) = ((c.seq & 0xFFFFFFu) << 8) | (r & 0xFFu);
+    const unsigned mm = (unsigned)c.st->m;
+    *reinterpret_cast<volatile unsigned*>(c.fb) = ((c.seq & 0xFFFFFFu) << 8) | (mm & 0xFFu);
   }
 }
 

@@ -13,8 +13,8 @@
 //      per eigenvalue, then V = Z X, unit 2-norm, largest entry real > 0;
 //   4. order by |lambda| descending, then Im descending;
 //   5. b~ = V^-1 p_y by Gaussian elimination with partial pivoting.
-// k_predict_coef: c_k for a chunk of steps, folded with the pending basis
-// rotation (U = Us G + Es g^T, so U c = Us (G c) + Es (g . c)).
+// k_predict_coef: c_k for a chunk of steps, folded with the basis
+// coefficients (U = S[:, :m] Q, so U c = S (Q c)).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -494,13 +494,13 @@ __global__ __launch_bounds__(64) void k_eig(DevState* st) {
   }
 }
 
-// Coefficients of one chunk of predicted states: column kk (state a+k0+kk+1)
-// of coefA is G c_k (pending rotation) or c_k, coefB[kk] = g . c_k.
+// Coefficients of one chunk of predicted states: column kk (state
+// a+k0+kk+1) of coefA is Q c_k, so that the state is S[:, :m] Q c_k.
 __global__ __launch_bounds__(256) void k_predict_coef(DevState* st, int k0, int K) {
   __shared__ double zr[4][RMAX], zi[4][RMAX], cc[4][RMAX];
   const int col = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int kk = blockIdx.x * 4 + col;
-  const int n = st->r, pending = st->pending, rs = st->rs;
+  const int n = st->r, m = st->m;
   const bool live = kk < K && n > 0 && st->eig_status == 0;
   const double kstep = (double)(k0 + kk + 1);
   if (live && l < n) {
@@ -522,39 +522,24 @@ __global__ __launch_bounds__(256) void k_predict_coef(DevState* st, int k0, int 
   }
   __syncthreads();
   if (kk < K) {
-    double v = 0.0;
-    if (live) {
-      if (pending) {
-        if (l < rs)
-          for (int k = 0; k < n; ++k) v += st->G[k * RMAX + l] * cc[col][k];
-      } else if (l < n) {
-        v = cc[col][l];
-      }
-    }
-    st->coefA[kk * RMAX + l] = v;
-    if (l == 0) {
-      double b = 0.0;
-      if (live && pending && st->use_e)
-        for (int k = 0; k < n; ++k) b += st->g[k] * cc[col][k];
-      st->coefB[kk] = b;
+    for (int c = l; c < CMAX; c += 64) {
+      double v = 0.0;
+      if (live && c < m)
+        for (int k = 0; k < n; ++k) v += st->Q[c * RMAX + k] * cc[col][k];
+      st->coefA[kk * CMAX + c] = v;
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && (n == 0 || st->eig_status != 0))
     st->status |= (n == 0 ? ST_EMPTY : ST_NOCONV);
 }
 
-// Coefficients that materialise the basis: column k of U.
+// Coefficients that materialise the basis: column k of U is S[:, :m] Q[:, k].
 __global__ __launch_bounds__(256) void k_basis_coef(DevState* st) {
-  const int pending = st->pending, r = st->r;
-  for (int idx = threadIdx.x; idx < RMAX * RMAX; idx += 256) {
-    const int j = idx % RMAX, k = idx / RMAX;
-    double v;
-    if (pending) v = (k < r) ? st->G[k * RMAX + j] : 0.0;
-    else v = (j == k && k < r) ? 1.0 : 0.0;
-    st->coefA[k * RMAX + j] = v;
+  const int m = st->m, r = st->r;
+  for (int idx = threadIdx.x; idx < CMAX * RMAX; idx += 256) {
+    const int c = idx % CMAX, k = idx / CMAX;
+    st->coefA[k * CMAX + c] = (c < m && k < r) ? st->Q[c * RMAX + k] : 0.0;
   }
-  for (int k = threadIdx.x; k < RMAX; k += 256)
-    st->coefB[k] = (pending && st->use_e && k < r) ? st->g[k] : 0.0;
 }
 
 hipError_t launch_eig(DevState* st, hipStream_t s) {

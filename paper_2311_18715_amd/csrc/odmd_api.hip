@@ -26,7 +26,7 @@ using namespace odmd;
 
 struct odmd_s {
   int64_t n = 0;
-  int r_max = 0, rb = 0;
+  int r_max = 0, ct = 0;      // rank cap, stored-column capacity of the tiles
   double tol = 0.0, tol_eff = 0.0;
   odmd_dtype basis = ODMD_F64, io = ODMD_F64;
   hipStream_t stream = nullptr;
@@ -37,15 +37,15 @@ struct odmd_s {
   DevState* st = nullptr;
   double* partials = nullptr;
   void* Us = nullptr;
-  void* Es = nullptr;
   int nblk = 0;
   int64_t units = 0;
   bool prof = false;
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
   std::vector<hipEvent_t> ev;   // triples: before pass, after pass, after core
   size_t ev_used = 0;
-  // Rank feedback: the core writes (seq << 8) | rank into this pinned host
-  // word after every update; seq counts the updates issued on the handle.
+  // Feedback: the core writes (seq << 8) | m (stored columns in use) into
+  // this pinned host word after every update; seq counts the updates issued
+  // on the handle.
   unsigned* fb_host = nullptr;
   unsigned* fb_dev = nullptr;
   unsigned seq = 0;
@@ -54,7 +54,7 @@ struct odmd_s {
 namespace {
 
 struct Layout {
-  size_t st = 0, partials = 0, Us = 0, Es = 0, total = 0;
+  size_t st = 0, partials = 0, Us = 0, total = 0;
   int64_t ntiles = 0, units = 0;
   int nblk = 0, ct = 0;
 };
@@ -73,16 +73,16 @@ bool valid_args(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dty
   return valid_types(basis, io);
 }
 
-int rank_bucket(int r_max) { return (r_max + 7) / 8 * 8; }
+int col_bucket(int cols) { return (cols + 7) / 8 * 8; }
 
-// Basis: 64-row tiles, column-major inside a tile, rank_bucket(r_max) columns
-// per tile; the residual Es holds the same padded row count.
+// Stored basis: 64-row tiles, column-major inside a tile, fold_capacity(r_max)
+// columns per tile.
 Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis) {
   Layout L;
-  L.ct = rank_bucket(r_max);
+  L.ct = fold_capacity(r_max);
   L.ntiles = (n + 63) / 64;
-  L.units = (n + 31) / 32;
-  L.nblk = (int)std::min<int64_t>((L.units + 3) / 4, PASS_MAX_BLOCKS);
+  L.units = (n + PASS_ROWS_PER_BLOCK - 1) / PASS_ROWS_PER_BLOCK;
+  L.nblk = (int)std::min<int64_t>(L.units, PASS_MAX_BLOCKS);
   size_t off = 0;
   L.st = off;
   off += round_up(sizeof(DevState), 256);
@@ -90,8 +90,6 @@ Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis) {
   off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
   L.Us = off;
   off += round_up(L.ntiles * L.ct * 64 * elem_bytes(basis), 256);
-  L.Es = off;
-  off += round_up(L.ntiles * 64 * elem_bytes(basis), 256);
   L.total = off;
   return L;
 }
@@ -130,16 +128,16 @@ odmd_status copy_field(odmd_t h, T* dst, const T* src_dev, size_t count) {
   return ODMD_OK;
 }
 
-// Live-column bucket for the next pass: an upper bound on the stored and
-// the logical rank after the last issued update.  The rank grows by at most
-// one per update, so the last rank the device reported plus the number of
-// updates issued since bounds it.  The bound is a multiple of 8 and never
-// exceeds the tile capacity.
+// Live-column bucket for the next pass: an upper bound on the stored
+// columns in use after the last issued update.  They grow by at most one per
+// update, so the last count the device reported plus the number of updates
+// issued since bounds them.  The bucket is a multiple of 8 and never exceeds
+// the tile capacity.
 int live_bucket(odmd_t h) {
   const unsigned v = __atomic_load_n(h->fb_host, __ATOMIC_ACQUIRE);
   const unsigned lag = (h->seq - (v >> 8)) & 0xFFFFFFu;
-  const int64_t bound = std::min<int64_t>(h->r_max, (int64_t)(v & 0xFFu) + lag);
-  return std::max(8, rank_bucket((int)bound));
+  const int64_t bound = std::min<int64_t>(h->ct, (int64_t)(v & 0xFFu) + lag);
+  return std::max(8, col_bucket((int)bound));
 }
 
 odmd_status launch_update(odmd_t h, const void* x, const void* y) {
@@ -158,7 +156,6 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   }
   PassArgs p;
   p.Us = h->Us;
-  p.Es = h->Es;
   p.x = x;
   p.y = y;
   p.partials = h->partials;
@@ -166,7 +163,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.n = h->n;
   p.units = h->units;
   p.nblk = h->nblk;
-  p.ct = h->rb;
+  p.ct = h->ct;
   const int kb = live_bucket(h);
   HIP_OK(launch_pass(p, h->basis == ODMD_F64, kb, h->stream));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
@@ -179,6 +176,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.basis_f32 = h->basis == ODMD_F32;
   c.jacobi_only = h->jacobi_only;
   c.rb = kb;
+  c.ct = h->ct;
   c.fb = h->fb_dev;
   c.seq = h->seq;
   HIP_OK(launch_core(c, h->stream));
@@ -251,14 +249,13 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
       odmd_t h = hs[i];
       PassDesc& d = pd[k++];
       d.Us = h->Us;
-      d.Es = h->Es;
       d.x = xs[i];
       d.y = ys[i];
       d.partials = h->partials;
       d.st = h->st;
       d.n = h->n;
       d.nblk = h->nblk;
-      d.ct = h->rb;
+      d.ct = h->ct;
       d.blk0 = L.nblocks;
       L.nblocks += h->nblk;
       ++L.nd;
@@ -275,6 +272,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     c.basis_f32 = h->basis == ODMD_F32;
     c.jacobi_only = h->jacobi_only;
     c.rb = kb[i];
+    c.ct = h->ct;
     h->seq = (h->seq + 1) & 0xFFFFFFu;
     c.fb = h->fb_dev;
     c.seq = h->seq;
@@ -296,17 +294,16 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   CombineArgs c;
   c.st = h->st;
   c.Us = h->Us;
-  c.Es = h->Es;
   c.out = out;
   c.n = h->n;
-  c.ct = h->rb;
+  c.ct = h->ct;
   c.ldo = ldo;
   c.K = K;
   const int64_t xb = (h->n + 255) / 256;
   int ysplit = (int)std::max<int64_t>(1, (1024 + xb - 1) / xb);
   ysplit = std::min(ysplit, std::max(1, (K + 7) / 8));
   c.kb = (K + ysplit - 1) / ysplit;
-  HIP_OK(launch_combine(c, h->basis == ODMD_F64, out_f32, h->rb, h->stream));
+  HIP_OK(launch_combine(c, h->basis == ODMD_F64, out_f32, h->ct, h->stream));
   return ODMD_OK;
 }
 
@@ -349,7 +346,7 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   if (!s) return ODMD_ENOMEM;
   s->n = n;
   s->r_max = r_max;
-  s->rb = rank_bucket(r_max);
+  s->ct = L.ct;
   s->tol = tol;
   s->tol_eff = basis == ODMD_F32 ? std::max(tol, 16.0 * 5.9604644775390625e-08) : tol;
   s->basis = basis;
@@ -389,7 +386,6 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   s->st = reinterpret_cast<DevState*>(s->mem + L.st);
   s->partials = reinterpret_cast<double*>(s->mem + L.partials);
   s->Us = s->mem + L.Us;
-  s->Es = s->mem + L.Es;
   const double tol_eff = s->tol_eff;
   if (hipMemsetAsync(s->mem, 0, L.total, s->stream) != hipSuccess ||
       hipMemcpyAsync(&s->st->tol, &tol_eff, sizeof(double), hipMemcpyHostToDevice, s->stream) !=
@@ -504,7 +500,7 @@ odmd_status odmd_get_info(odmd_t h, odmd_info* info) {
   info->r = hdr.r;
   info->r_max = h->r_max;
   info->n = h->n;
-  info->m = hdr.m;
+  info->m = hdr.m_acc;
   info->tol_eff = h->tol_eff;
   info->last_rho = hdr.last_rho;
   info->last_sweeps = hdr.sweeps;

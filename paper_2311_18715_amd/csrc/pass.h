@@ -7,11 +7,10 @@
 namespace odmd {
 
 struct PassArgs {
-  void* Us;             // stored basis: 64-row tiles, column-major inside a tile
-  void* Es;             // stored residual (n rounded up to 64 entries)
+  void* Us;             // stored basis S: 64-row tiles, column-major inside a tile
   const void* x;        // snapshot x_k (io type)
   const void* y;        // snapshot x_k+1 (io type)
-  double* partials;     // nblk records (stride PW) of 2 (rb + 1) + 4 values
+  double* partials;     // nblk records (stride PW) of 2 rb + 4 values
   const DevState* st;
   int64_t n;
   int64_t units;        // 32-row units, ceil(n / 32)
@@ -19,14 +18,13 @@ struct PassArgs {
   int ct;               // column capacity of a basis tile (rank bucket of r_max)
 };
 
-// rb: live-column bucket of the launch (multiple of 8, >= the stored and
-// the logical rank of the stream, <= its tile capacity ct)
+// rb: live-column bucket of the launch (multiple of 8, >= the stored
+// columns in use m, <= the tile capacity ct)
 hipError_t launch_pass(const PassArgs& p, int basis_f64, int rb, hipStream_t s);
 
 // One stream of a batched pass launch (device-resident table, sorted by blk0).
 struct PassDesc {
   void* Us;
-  void* Es;
   const void* x;
   const void* y;
   double* partials;
@@ -47,7 +45,8 @@ struct CoreArgs {
   int basis_f32;        // also keep an FP32 copy of the rotation
   int jacobi_only;      // skip the secular solver (diagnostics)
   int rb;               // live-column bucket of the pass (compact partial records)
-  unsigned* fb;         // host-visible word: (seq << 8) | rank after this update
+  int ct;               // stored-column capacity of the stream
+  unsigned* fb;         // host-visible word: (seq << 8) | stored columns after this update
   unsigned seq;         // update sequence number (24 bits) of this launch
 };
 hipError_t launch_core(const CoreArgs& c, hipStream_t s);
@@ -55,9 +54,8 @@ hipError_t launch_core(const CoreArgs& c, hipStream_t s);
 hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s);
 
 struct CombineArgs {
-  const DevState* st;   // coefficients coefA / coefB and the basis layout
-  const void* Us;       // stored basis (64-row tiles, column capacity ct)
-  const void* Es;       // stored residual
+  const DevState* st;   // coefficients coefA and the stored-column count m
+  const void* Us;       // stored basis S (64-row tiles, column capacity ct)
   void* out;            // out[k*ldo + i], k < K
   int64_t n, ldo;
   int ct;               // column capacity of a basis tile

@@ -1,29 +1,31 @@
-// Streaming pass of the online DMD update (HBM-bound, one read and one write
-// of the basis per update).
+// Streaming pass of the online DMD update (HBM-bound: one read of the live
+// stored columns, one column written; the stored columns are rewritten only
+// on the refold passes).
 //
 // One update appends the pair (x, y) to the snapshot matrices (Sec. 2.3).
 // Brand's column append needs the projection of x onto the basis and the
-// residual direction; this pass computes, in one sweep over the rows:
-//   * the pending rotation of the previous update, U = [Us Es] G' with
-//     G' = [G; g^T], written back to Us;
-//   * the first Gram-Schmidt residual e = x - U p1 = x - Us a - Es beta (a = G
-//     p1, beta = g . p1, p1 the cached projection U^T x, equal to the
-//     previous step's U^T y for chained pairs), stored to Es;
-//   * per-workgroup partial sums of Us^T e, Es.e, e.e, x.x and of Us^T y,
-//     Es.y, e.y, y.y, from which the small-state kernel forms the second
-//     Gram-Schmidt projection p2 = U^T e = G'^T [Us Es]^T e and U^T y (CGS2).
+// residual direction.  With the basis held as U = S[:, :m] Q, this pass
+// computes, in one sweep over the rows:
+//   * the first Gram-Schmidt residual e = x - U p1 = x - S a (a = Q p1, p1
+//     the cached projection U^T x, equal to the previous step's U^T y for
+//     chained pairs), stored as column `slot` of S;
+//   * per-workgroup partial sums of S^T e, S^T y, e.e, e.y, x.x and y.y, from
+//     which the small-state kernel forms the second Gram-Schmidt projection
+//     p2 = U^T e = Q^T S^T e and U^T y (CGS2);
+//   * on a refold pass (no free column left), S[:, :r] <- S Q in place on the
+//     matrix cores, with e then stored as column r.
 //
-// Layout and mapping (CDNA4): the basis is stored in tiles of 64 rows, each
-// tile column-major (element (i, c) at ((i/64)*CT + c)*64 + i%64, CT the
-// column capacity), so one column of a tile is 64 contiguous elements.  A
-// wavefront processes 32 rows at a time in the operand layout of the 16x16x4
-// matrix-core instruction: lane l holds rows 16*mt + l%16 (mt = 0, 1) of
-// columns 4*kk + l/16, so that
-//   * the rotation [Us Es] G' is a chain of MFMAs (G' staged in LDS in the
-//     operand layout), overlapped with the loads of the next unit;
+// Layout and mapping (CDNA4): S is stored in tiles of 64 rows, each tile
+// column-major (element (i, c) at ((i/64)*ct + c)*64 + i%64), so one column of
+// a tile is 64 contiguous elements.  A wavefront processes 16 rows at a time
+// in the operand layout of the 16x16x4 matrix-core instruction: lane l holds
+// row l%16 of columns 4*kk + l/16, so that
+//   * the refold S Q is a chain of MFMAs (Q staged in LDS in the operand
+//     layout);
 //   * e needs only an in-lane dot product plus two cross-lane additions;
 //   * the projections accumulate in-lane across all rows a lane sees and are
 //     reduced once per workgroup, in a fixed order (bitwise reproducible).
+// The next unit's loads are issued before the current unit is processed.
 #include <hip/hip_runtime.h>
 
 #include "odmd_internal.h"
@@ -42,8 +44,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
   typedef d4_t acc_t;
-  __device__ static cptr<double> G(const DevState* s) { return (cptr<double>)s->G; }
-  __device__ static cptr<double> g(const DevState* s) { return (cptr<double>)s->g; }
+  __device__ static cptr<double> Q(const DevState* s) { return (cptr<double>)s->Q; }
   __device__ static acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -52,65 +53,50 @@ template <> struct Mfma<double> {
 };
 template <> struct Mfma<float> {
   typedef f4_t acc_t;
-  __device__ static cptr<float> G(const DevState* s) { return (cptr<float>)s->G32; }
-  __device__ static cptr<float> g(const DevState* s) { return (cptr<float>)s->g32; }
+  __device__ static cptr<float> Q(const DevState* s) { return (cptr<float>)s->Q32; }
   __device__ static acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ static int dsub(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-#ifndef ODMD_PASS_MT
-#define ODMD_PASS_MT 1
-#endif
-#ifndef ODMD_PASS_PREFETCH
-#define ODMD_PASS_PREFETCH 1
-#endif
-
 template <typename TS, typename TIO, int RB>
 __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
-  constexpr int MT = ODMD_PASS_MT;        // 16-row blocks per unit
-  constexpr int UR = 16 * MT;             // rows per unit
+  constexpr int UR = 16;                  // rows per unit
   constexpr int UPT = 64 / UR;            // units per 64-row tile
-  constexpr bool PF = ODMD_PASS_PREFETCH;
-  constexpr int KK = RB / 4 + 1;          // k-steps: RB basis columns + the Es column
-  constexpr int NT = (RB + 15) / 16;      // 16-column output blocks
+  constexpr int KK = RB / 4;              // k-steps over the RB live stored columns
+  constexpr int NT = ((RB < RMAX ? RB : RMAX) + 15) / 16;   // 16-column output blocks of a refold (r <= RMAX)
   constexpr int NWAVE = PASS_THREADS / 64;
   typedef typename Mfma<TS>::acc_t acc_t;
 
   const DevState* __restrict__ st = p.st;
-  const int rs = st->rs, r = st->r, pending = st->pending, use_e = st->use_e;
+  const int m = st->m, r = st->r, refold = st->refold;
+  const int slot = refold ? r : m;        // the column that receives e
   TS* __restrict__ Us = static_cast<TS*>(p.Us);
-  TS* __restrict__ Es = static_cast<TS*>(p.Es);
   const TIO* __restrict__ X = static_cast<const TIO*>(p.x);
   const TIO* __restrict__ Y = static_cast<const TIO*>(p.y);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, l16 = lane & 15;
 
-  // per-lane coefficients of the first projection (a, beta) in registers;
-  // the rotation G' = [G; g^T] in LDS, pre-arranged in the MFMA operand
-  // layout (entry [kk][nt][lane] = G'[4 kk + lane/16][16 nt + lane%16])
+  // per-lane coefficients of the first projection in registers; Q in LDS,
+  // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
+  // Q[4 kk + lane/16][16 nt + lane%16]), for a refold
   __shared__ TS sG[KK][NT][64];
   double al[KK];
   {
     cptr<double> a = (cptr<double>)st->a;
-    const double beta = st->beta;
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
       const int c = 4 * kk + q;
-      al[kk] = c < rs ? a[c] : (c == RB && use_e ? beta : 0.0);
+      al[kk] = c < m ? a[c] : 0.0;
     }
-    cptr<TS> G = Mfma<TS>::G(st);
-    cptr<TS> g = Mfma<TS>::g(st);
-    for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
-      const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
-      const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
-      TS v = TS(0);
-      if (pending && col < r) {
-        if (c < rs) v = G[col * RMAX + c];
-        else if (c == RB && use_e) v = g[col];
+    if (refold) {
+      cptr<TS> Q = Mfma<TS>::Q(st);
+      for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
+        const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
+        const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
+        sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TS(0);
       }
-      sG[kk][nt][ln] = v;
     }
     __syncthreads();
   }
@@ -123,121 +109,88 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   const int64_t u0 = (int64_t)blk * units / p.nblk;
   const int64_t u1 = (int64_t)(blk + 1) * units / p.nblk;
 
-  // operands of one unit: A[mt][kk] = [Us Es](16 mt + l%16, 4 kk + l/16)
-  auto load_unit = [&](int64_t u, TS (&A)[MT][KK], double (&xv)[MT], double (&yv)[MT]) {
+  // operands of one unit: A[kk] = S(row, 4 kk + l/16) for stored columns < m
+  auto load_unit = [&](int64_t u, TS (&A)[KK], double& xv, double& yv) {
     const int64_t tile = u / UPT;
-    const int half = (int)(u % UPT);
+    const int rr = UR * (int)(u % UPT) + l16;
+    const int64_t row = tile * 64 + rr;
+    const bool in = row < p.n;
     const TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int rr = UR * half + 16 * mt + l16;
-      const int64_t row = tile * 64 + rr;
-      const bool in = row < p.n;
-#pragma unroll
-      for (int kk = 0; kk < KK; ++kk) {
-        const int c = 4 * kk + q;
-        TS v = TS(0);
-        if (in) {
-          if (c < rs) v = T[c * 64 + rr];
-          else if (c == RB && use_e) v = Es[row];
-        }
-        A[mt][kk] = v;
-      }
-      xv[mt] = in ? (double)X[row] : 0.0;
-      yv[mt] = in ? (double)Y[row] : 0.0;
+    for (int kk = 0; kk < KK; ++kk) {
+      const int c = 4 * kk + q;
+      A[kk] = (in && c < m) ? T[c * 64 + rr] : TS(0);
     }
+    xv = in ? (double)X[row] : 0.0;
+    yv = in ? (double)Y[row] : 0.0;
   };
 
-  // software pipeline: the next unit's loads are in flight while the matrix
-  // cores rotate the current one
-  TS A[MT][KK], An[MT][KK];
-  double xv[MT], yv[MT], xn[MT], yn[MT];
+  // software pipeline: the next unit's loads are in flight while the
+  // current one is processed
+  TS A[KK], An[KK];
+  double xv, yv, xn, yn;
   int64_t u = u0 + wave;
-  if (PF && u < u1) load_unit(u, A, xv, yv);
+  if (u < u1) load_unit(u, A, xv, yv);
   for (; u < u1; u += NWAVE) {
-    const bool more = PF && u + NWAVE < u1;
+    const bool more = u + NWAVE < u1;
     if (more) load_unit(u + NWAVE, An, xn, yn);
-    if (!PF) load_unit(u, A, xv, yv);
     const int64_t tile = u / UPT;
-    const int half = (int)(u % UPT);
+    const int rr = UR * (int)(u % UPT) + l16;
+    const int64_t row = tile * 64 + rr;
     TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
-    const int64_t rowbase = tile * 64 + UR * half;
 
-    // e = x - [Us Es] [a; beta], in FP64
-    double ed[MT];
+    // e = x - S a, in FP64, stored as column `slot`
+    double s = 0.0;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      double s = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < KK; ++kk) s = __builtin_fma((double)A[mt][kk], al[kk], s);
-      s += __shfl_xor(s, 16, 64);
-      s += __shfl_xor(s, 32, 64);
-      const TS es = (TS)(xv[mt] - s);
-      const int64_t row = rowbase + 16 * mt + l16;
-      if (q == 0 && row < p.n) Es[row] = es;
-      ed[mt] = (double)es;
-    }
+    for (int kk = 0; kk < KK; ++kk) s = __builtin_fma((double)A[kk], al[kk], s);
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    const TS es = (TS)(xv - s);
+    if (q == 0 && row < p.n) T[slot * 64 + rr] = es;
+    const double ed = (double)es;
 
     // projections, accumulated in-lane
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        accE[kk] = __builtin_fma((double)A[mt][kk], ed[mt], accE[kk]);
-        accY[kk] = __builtin_fma((double)A[mt][kk], yv[mt], accY[kk]);
-      }
+      accE[kk] = __builtin_fma((double)A[kk], ed, accE[kk]);
+      accY[kk] = __builtin_fma((double)A[kk], yv, accY[kk]);
     }
     if (q == 0) {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        sEE = __builtin_fma(ed[mt], ed[mt], sEE);
-        sEY = __builtin_fma(ed[mt], yv[mt], sEY);
-        sXX = __builtin_fma(xv[mt], xv[mt], sXX);
-        sYY = __builtin_fma(yv[mt], yv[mt], sYY);
-      }
+      sEE = __builtin_fma(ed, ed, sEE);
+      sEY = __builtin_fma(ed, yv, sEY);
+      sXX = __builtin_fma(xv, xv, sXX);
+      sYY = __builtin_fma(yv, yv, sYY);
     }
 
-    // pending rotation on the matrix cores, computed transposed:
-    // U'^T = G'^T [Us Es]^T, so that lane l owns row 16 mt + l%16 of U' and
-    // every store instruction writes whole 16-row column segments
-    if (pending) {
-      // k-steps outermost: the NT*MT accumulator chains are independent, so
-      // consecutive MFMAs never wait on each other's results
-      acc_t d[NT][MT];
+    // refold on the matrix cores, computed transposed: (S Q)^T = Q^T S^T, so
+    // that lane l owns row l%16 of S Q and every store instruction writes
+    // whole 16-row column segments; k-steps outermost keeps the NT
+    // accumulator chains independent
+    if (refold) {
+      acc_t d[NT];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) d[nt][mt] = acc_t{0, 0, 0, 0};
+      for (int nt = 0; nt < NT; ++nt) d[nt] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < KK; ++kk) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const TS b = sG[kk][nt][lane];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) d[nt][mt] = Mfma<TS>::mma(b, A[mt][kk], d[nt][mt]);
-        }
+        for (int nt = 0; nt < NT; ++nt) d[nt] = Mfma<TS>::mma(sG[kk][nt][lane], A[kk], d[nt]);
       }
+      if (row < p.n) {
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const int rr = UR * half + 16 * mt + l16;
+        for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int col = 16 * nt + Mfma<TS>::dsub(lane, v);
-            if (col < r) T[col * 64 + rr] = d[nt][mt][v];
+            if (col < r) T[col * 64 + rr] = d[nt][v];
           }
         }
       }
     }
     if (more) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) A[mt][kk] = An[mt][kk];
-        xv[mt] = xn[mt];
-        yv[mt] = yn[mt];
-      }
+      for (int kk = 0; kk < KK; ++kk) A[kk] = An[kk];
+      xv = xn;
+      yv = yn;
     }
   }
 
@@ -258,29 +211,27 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     sXX += __shfl_xor(sXX, o, 64);
     sYY += __shfl_xor(sYY, o, 64);
   }
-  __shared__ double red[NWAVE][2 * KK * 4 + 4];
+  // record: [S^T e (RB) | S^T y (RB) | e.e e.y x.x y.y]
+  __shared__ double red[NWAVE][2 * RB + 4];
   if (l16 == 0) {
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
-      red[wave][(4 * kk + q)] = accE[kk];
-      red[wave][4 * KK + (4 * kk + q)] = accY[kk];
+      red[wave][4 * kk + q] = accE[kk];
+      red[wave][RB + 4 * kk + q] = accY[kk];
     }
   }
   if (lane == 0) {
-    red[wave][8 * KK + 0] = sEE;
-    red[wave][8 * KK + 1] = sEY;
-    red[wave][8 * KK + 2] = sXX;
-    red[wave][8 * KK + 3] = sYY;
+    red[wave][2 * RB + 0] = sEE;
+    red[wave][2 * RB + 1] = sEY;
+    red[wave][2 * RB + 2] = sXX;
+    red[wave][2 * RB + 3] = sYY;
   }
   __syncthreads();
-  // compact record: [Us^T e (RB) | Es.e | Us^T y (RB) | Es.y | e.e e.y x.x y.y]
   double* __restrict__ out = p.partials + (int64_t)blk * PW;
-  for (int idx = threadIdx.x; idx < 2 * (RB + 1) + 4; idx += PASS_THREADS) {
-    const int src = idx < 2 * (RB + 1) ? (idx / (RB + 1)) * 4 * KK + idx % (RB + 1)
-                                       : 8 * KK + (idx - 2 * (RB + 1));
+  for (int idx = threadIdx.x; idx < 2 * RB + 4; idx += PASS_THREADS) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) t += red[w][src];
+    for (int w = 0; w < NWAVE; ++w) t += red[w][idx];
     out[idx] = t;
   }
 }
@@ -290,7 +241,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
   pass_body<TS, TIO, RB>(p, blockIdx.x);
 }
 
-// Many streams of one storage type and rank bucket in one launch: workgroup b
+// Many streams of one storage type and live-column bucket in one launch: workgroup b
 // belongs to the stream whose block range [blk0, blk0 + nblk) contains b, and
 // runs exactly the work that workgroup b - blk0 of that stream's own launch
 // would (same partition, same reduction order: results are bitwise equal).
@@ -307,7 +258,6 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass_batch(const PassDesc* __r
   }
   PassArgs p;
   p.Us = D[lo].Us;
-  p.Es = D[lo].Es;
   p.x = D[lo].x;
   p.y = D[lo].y;
   p.partials = D[lo].partials;
@@ -331,6 +281,7 @@ static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int rb
     case 48: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 48>), grid, block, 0, s, d, nd); break;
     case 56: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 56>), grid, block, 0, s, d, nd); break;
     case 64: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 64>), grid, block, 0, s, d, nd); break;
+    case 72: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 72>), grid, block, 0, s, d, nd); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -354,6 +305,7 @@ static hipError_t launch_rb(const PassArgs& p, int rb, hipStream_t s) {
     case 48: hipLaunchKernelGGL((k_pass<TS, TIO, 48>), grid, block, 0, s, p); break;
     case 56: hipLaunchKernelGGL((k_pass<TS, TIO, 56>), grid, block, 0, s, p); break;
     case 64: hipLaunchKernelGGL((k_pass<TS, TIO, 64>), grid, block, 0, s, p); break;
+    case 72: hipLaunchKernelGGL((k_pass<TS, TIO, 72>), grid, block, 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
