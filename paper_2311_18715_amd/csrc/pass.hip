@@ -82,14 +82,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
   // Q[4 kk + lane/16][16 nt + lane%16]), for a refold
   __shared__ TS sG[KK][NT][64];
-  double al[KK];
+  __shared__ double sa[4 * KK];          // a, zero past the m stored columns
   {
-    cptr<double> a = (cptr<double>)st->a;
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-      const int c = 4 * kk + q;
-      al[kk] = c < m ? a[c] : 0.0;
-    }
+    for (int c = threadIdx.x; c < 4 * KK; c += PASS_THREADS) sa[c] = c < m ? st->a[c] : 0.0;
     if (refold) {
       cptr<TS> Q = Mfma<TS>::Q(st);
       for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
@@ -109,44 +104,63 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   const int64_t u0 = (int64_t)blk * units / p.nblk;
   const int64_t u1 = (int64_t)(blk + 1) * units / p.nblk;
 
-  // operands of one unit: A[kk] = S(row, 4 kk + l/16) for stored columns < m
-  auto load_unit = [&](int64_t u, TS (&A)[KK], double& xv, double& yv) {
-    const int64_t tile = u / UPT;
-    const int rr = UR * (int)(u % UPT) + l16;
-    const int64_t row = tile * 64 + rr;
-    const bool in = row < p.n;
-    const TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
+  // Addressing: a unit is 16 rows of one tile, so its base is wave-uniform
+  // (scalar registers) and each lane adds a constant 32-bit offset.  Rows
+  // of the last tile past n are never written and stay zero, so stored
+  // columns are read without a row test.  Every load is issued
+  // unconditionally, so the number in flight is fixed and the waits can
+  // leave the prefetched unit outstanding: a k-step past the m live columns
+  // re-reads k-step 0 (a cache hit) and meets zero coefficients (a and the
+  // staged Q vanish past m; every stored value is finite, see the residual
+  // store), x and y are read at a clamped row and zeroed past n.
+  const uint32_t loff = (uint32_t)((q * 64 + l16) * sizeof(TS));
+  typedef const __attribute__((address_space(1))) char* gbase_t;
+  auto unit_base = [&](int64_t uu) -> gbase_t {
+    const int64_t tile = uu / UPT;
+    const uint64_t b = reinterpret_cast<uint64_t>(Us + tile * (int64_t)p.ct * 64 + UR * (uu % UPT));
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return (gbase_t)(((uint64_t)hi << 32) | lo);
+  };
+  auto load_unit = [&](int64_t uu, TS (&A)[KK], double& xv, double& yv) {
+    const gbase_t base = unit_base(uu);
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
-      const int c = 4 * kk + q;
-      A[kk] = (in && c < m) ? T[c * 64 + rr] : TS(0);
+      const int ks = 4 * kk < m ? kk : 0;   // uniform
+      A[kk] = *(const __attribute__((address_space(1))) TS*)(base + ks * 256 * (int)sizeof(TS) + loff);
     }
-    xv = in ? (double)X[row] : 0.0;
-    yv = in ? (double)Y[row] : 0.0;
+    const int64_t row = (uu / UPT) * 64 + UR * (uu % UPT) + l16;
+    const int64_t rc = row < p.n ? row : p.n - 1;
+    xv = (double)X[rc];     // zeroed past n at the point of use
+    yv = (double)Y[rc];
   };
 
-  // software pipeline: the next unit's loads are in flight while the
+  // software pipeline: the next unit's loads (the current unit's again on
+  // the last round, so the count never varies) are in flight while the
   // current one is processed
   TS A[KK], An[KK];
   double xv, yv, xn, yn;
-  int64_t u = u0 + wave;
+  int64_t u = u0 + __builtin_amdgcn_readfirstlane(wave);
   if (u < u1) load_unit(u, A, xv, yv);
   for (; u < u1; u += NWAVE) {
     const bool more = u + NWAVE < u1;
-    if (more) load_unit(u + NWAVE, An, xn, yn);
+    load_unit(more ? u + NWAVE : u, An, xn, yn);
     const int64_t tile = u / UPT;
     const int rr = UR * (int)(u % UPT) + l16;
     const int64_t row = tile * 64 + rr;
     TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
+    if (row >= p.n) xv = yv = 0.0;
 
     // e = x - S a, in FP64, stored as column `slot`
     double s = 0.0;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) s = __builtin_fma((double)A[kk], al[kk], s);
+    for (int kk = 0; kk < KK; ++kk) s = __builtin_fma((double)A[kk], sa[4 * kk + q], s);
     s += __shfl_xor(s, 16, 64);
     s += __shfl_xor(s, 32, 64);
     const TS es = (TS)(xv - s);
-    if (q == 0 && row < p.n) T[slot * 64 + rr] = es;
+    // a non-finite residual (rejected by the small-state kernel, which sees
+    // it in the sums below) is stored as zero: stored columns stay finite
+    if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(es) ? es : TS(0);
     const double ed = (double)es;
 
     // projections, accumulated in-lane
@@ -167,31 +181,27 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     // whole 16-row column segments; k-steps outermost keeps the NT
     // accumulator chains independent
     if (refold) {
-      acc_t d[NT];
+      // one 16-column output block at a time keeps the accumulator small
+      // (the refold pass is the rare one; the register budget is set for
+      // the plain pass)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) d[nt] = acc_t{0, 0, 0, 0};
+      for (int nt = 0; nt < NT; ++nt) {
+        acc_t d = acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int kk = 0; kk < KK; ++kk) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) d[nt] = Mfma<TS>::mma(sG[kk][nt][lane], A[kk], d[nt]);
-      }
-      if (row < p.n) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
+        for (int kk = 0; kk < KK; ++kk) d = Mfma<TS>::mma(sG[kk][nt][lane], A[kk], d);
+        if (row < p.n) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int col = 16 * nt + Mfma<TS>::dsub(lane, v);
-            if (col < r) T[col * 64 + rr] = d[nt][v];
+            if (col < r) T[col * 64 + rr] = d[v];
           }
         }
       }
     }
-    if (more) {
 #pragma unroll
-      for (int kk = 0; kk < KK; ++kk) A[kk] = An[kk];
-      xv = xn;
-      yv = yn;
-    }
+    for (int kk = 0; kk < KK; ++kk) A[kk] = An[kk];
+    xv = xn;
+    yv = yn;
   }
 
   // fixed-order reduction: across the 16 lanes that share a column (in-wave
