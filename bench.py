@@ -10,10 +10,14 @@ updates (projection, CGS2, core SVD, basis rotation, A~), the
 eigendecomposition of A~, and a 500-state rollout, on a fresh model.
 value = updates per second over the timed steps.
 
-Printed beside it (one JSON line): the streaming pass's roofline (its
-algorithmic bytes n (r + r') 8 + 2 n 8 per update divided by its average
-HIP-event duration, against 8 TB/s), p50/p99 device latency of one update,
-and the CPU oracle timed on a bounded sample on this host.
+Printed beside it (one JSON line): the streaming pass's roofline (the
+algorithmic bytes of one update, n (r + r') 8 + 2 n 8 (read U, write U',
+read x and y), divided by the pass's average HIP-event duration, against
+8 TB/s; the measured HBM traffic per pass comes from the committed rocprofv3
+counter summary), p50/p99 device latency of one update, S = 8/32/128
+concurrent n = 160k streams through the batched update, the 256-stream FP32
+batched form against a per-stream FP64 loop, and the CPU oracle timed on a
+bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -382,7 +386,8 @@ def main():
                      "core_mean": round(float(np.mean(core_ms)) * 1e3, 2)},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_pass<double,double,40> (streaming pass)",
+            "kernel": "k_pass<double,double,KB> (streaming pass; KB = live-column bucket, 56 at "
+                      "steady state: 40 live basis columns + 16 deferred-rotation columns)",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
