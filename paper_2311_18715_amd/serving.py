@@ -1,0 +1,227 @@
+"""Continuous-batching request loop over many online-DMD streams.
+
+Many concurrent simulations each feed one stream: snapshot pairs to append
+(updates, Sec. 2.3) and requests for predicted states (the O(N r) rollout).
+Every stream's state (stored basis, sigma, A~, ...) stays resident on the
+device.  A stream is admitted when its device bytes (odmd_state_bytes) fit
+in the memory budget; otherwise it waits, in arrival order, until closed
+streams free enough.
+
+Each scheduling round takes the head request of every admitted stream that
+has one: all head updates go to the device as one batched update
+(odmd_update_batch, one fused launch per kernel for all of them), head
+predictions are queued behind it.  Requests that arrive while a round runs on
+the device join the next round; a stream's requests are served strictly in
+order, so every result equals the one the stream would get alone (the
+batched launch is bitwise equal to per-stream launches).
+
+The device work of a round is recorded with one event; a request's latency
+runs from its submission to the host's observation that its round finished.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Deque, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    """One update or prediction request.  ``out`` holds the predicted states
+    (steps x n device tensor) of a prediction once ``done``."""
+    kind: str                       # "update" | "predict"
+    sid: int
+    x: object = None
+    y: object = None
+    steps: int = 0
+    out: object = None
+    t_submit: float = 0.0
+    t_done: float = 0.0
+    done: bool = False
+    error: Optional[str] = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_submit
+
+
+@dataclasses.dataclass
+class _Stream:
+    sid: int
+    n: int
+    r_max: int
+    tol: float
+    basis: str
+    bytes: int
+    model: object = None
+    workspace: object = None
+    queue: Deque[Request] = dataclasses.field(default_factory=collections.deque)
+    closing: bool = False
+
+
+class Server:
+    """Request loop with HBM-budget admission and continuous batching.
+
+    budget_bytes bounds the sum of the admitted streams' device state
+    (odmd_state_bytes); prediction outputs are allocated per request and
+    are not part of it.  ``backend`` is the module that provides ODMD,
+    handle_array and update_batch_ptrs (the library binding; a stand-in can
+    be passed for host-only tests of the scheduling logic)."""
+
+    def __init__(self, budget_bytes: int, backend=None, torch_module=None,
+                 clock: Callable[[], float] = time.perf_counter):
+        if backend is None:
+            from paper_2311_18715_amd import odmd as backend
+        if torch_module is None:
+            import torch as torch_module
+        self.B, self.torch, self.clock = backend, torch_module, clock
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.peak_used = 0
+        self.streams: Dict[int, _Stream] = {}
+        self.waiting: Deque[_Stream] = collections.deque()
+        self.inflight: List = []          # (event, [requests]) per round
+        self.completed: List[Request] = []
+        self.rounds = 0
+        self.batch_sizes: List[int] = []
+
+    # ---- streams -------------------------------------------------------
+    def open(self, sid: int, n: int, r_max: int, tol: float, basis: str = "f32") -> bool:
+        """Register a stream; returns True if it was admitted at once."""
+        if sid in self.streams:
+            raise ValueError(f"stream {sid} already open")
+        nbytes = int(self.B.ODMD.state_bytes(n, r_max, basis))
+        if nbytes <= 0 or nbytes > self.budget:
+            raise ValueError(f"stream {sid} cannot fit the budget ({nbytes} bytes)")
+        st = _Stream(sid, int(n), int(r_max), float(tol), basis, nbytes)
+        self.streams[sid] = st
+        self.waiting.append(st)
+        self._admit()
+        return st.model is not None
+
+    def close(self, sid: int) -> None:
+        """Close a stream once its queued requests are served."""
+        self.streams[sid].closing = True
+
+    def admitted(self, sid: int) -> bool:
+        return self.streams[sid].model is not None
+
+    def _admit(self) -> None:
+        while self.waiting and self.used + self.waiting[0].bytes <= self.budget:
+            st = self.waiting.popleft()
+            ws = self.torch.empty(st.bytes + 256, dtype=self.torch.uint8, device="cuda")
+            st.workspace = ws
+            st.model = self.B.ODMD(st.n, st.r_max, st.tol, basis=st.basis, workspace=ws)
+            self.used += st.bytes
+            self.peak_used = max(self.peak_used, self.used)
+
+    def _release(self, st: _Stream) -> None:
+        st.model.close()
+        st.model = None
+        st.workspace = None
+        self.used -= st.bytes
+        del self.streams[st.sid]
+
+    # ---- requests ------------------------------------------------------
+    def submit_update(self, sid: int, x, y) -> Request:
+        r = Request("update", sid, x=x, y=y, t_submit=self.clock())
+        self.streams[sid].queue.append(r)
+        return r
+
+    def submit_predict(self, sid: int, steps: int) -> Request:
+        r = Request("predict", sid, steps=int(steps), t_submit=self.clock())
+        self.streams[sid].queue.append(r)
+        return r
+
+    # ---- scheduling ----------------------------------------------------
+    def pump(self) -> int:
+        """One round: the head request of every admitted stream goes to the
+        device (updates batched into one launch).  Returns the number of
+        requests launched."""
+        self.poll()
+        self._admit()
+        ups, preds = [], []
+        for st in list(self.streams.values()):
+            if st.model is None:
+                continue
+            if not st.queue:
+                if st.closing:
+                    self._release(st)
+                continue
+            head = st.queue[0]
+            if head.kind == "update":
+                ups.append((st, head))
+            else:
+                preds.append((st, head))
+        launched = []
+        if ups:
+            H = self.B.handle_array([st.model for st, _ in ups])
+            xp = np.array([r.x.data_ptr() for _, r in ups], dtype=np.uint64)
+            yp = np.array([r.y.data_ptr() for _, r in ups], dtype=np.uint64)
+            self.B.update_batch_ptrs(H, xp, yp)
+            for st, r in ups:
+                st.queue.popleft()
+                launched.append(r)
+            self.batch_sizes.append(len(ups))
+        for st, r in preds:
+            try:
+                r.out = st.model.predict(r.steps)
+            except Exception as e:          # e.g. a rank-0 model
+                r.error = str(e)
+            st.queue.popleft()
+            launched.append(r)
+        if launched:
+            ev = self.torch.cuda.Event()
+            ev.record()
+            self.inflight.append((ev, launched))
+            self.rounds += 1
+        return len(launched)
+
+    def poll(self) -> None:
+        """Mark the requests of finished rounds done."""
+        keep = []
+        now = None
+        for ev, reqs in self.inflight:
+            if ev.query():
+                now = now if now is not None else self.clock()
+                for r in reqs:
+                    r.t_done, r.done = now, True
+                    self.completed.append(r)
+            else:
+                keep.append((ev, reqs))
+        self.inflight = keep
+
+    def idle(self) -> bool:
+        return not self.inflight and not self.waiting and \
+            all(not st.queue for st in self.streams.values())
+
+    def drain(self) -> None:
+        """Run rounds until every queued request is done.  Raises if queued
+        work waits for admission that no open stream will ever make room
+        for (the caller must close streams)."""
+        while True:
+            launched = self.pump()
+            if self.idle():
+                break
+            if not any(st.queue for st in self.streams.values() if st.model is not None):
+                # only waits for the device, or for admission, are left
+                self.torch.cuda.synchronize()
+                self.poll()
+                if launched == 0 and not self.inflight:
+                    self.pump()        # releases closing streams, admits waiting ones
+                    if not any(st.queue for st in self.streams.values()
+                               if st.model is not None) and self.waiting:
+                        raise RuntimeError("admission blocked: the budget is held by open "
+                                           "streams with no queued work; close some")
+        self.torch.cuda.synchronize()
+        self.poll()
+
+    def latency_us(self, kind: str = "update") -> Dict[str, float]:
+        lat = np.array([r.latency for r in self.completed if r.kind == kind]) * 1e6
+        if lat.size == 0:
+            return {"p50": float("nan"), "p99": float("nan"), "count": 0}
+        return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                "count": int(lat.size)}

@@ -1,0 +1,97 @@
+"""Serving loop on the GPU: streams of different size, rank cap and storage
+type arrive interleaved, wait for admission under a memory budget, share
+batched rounds, and each one's predictions equal, bit for bit, those of the
+same stream run alone through plain updates."""
+import numpy as np
+import pytest
+
+from paper_2311_18715_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2311_18715_amd.odmd import ODMD
+    from paper_2311_18715_amd.serving import Server
+
+SPECS = [  # (n, planted rank, r_max, basis, updates)
+    (3000, 6, 16, "f32", 60), (777, 10, 12, "f64", 45), (20000, 30, 64, "f32", 70),
+    (5000, 12, 40, "f64", 50), (12345, 20, 24, "f32", 65), (64, 4, 8, "f64", 30),
+    (9000, 26, 33, "f32", 55), (40000, 8, 32, "f32", 40),
+]
+PRED_AT = {0: [20], 2: [35], 3: [10, 30], 6: [50]}   # predictions after these updates
+STEPS = 9
+
+
+def streams():
+    out = []
+    for i, (n, rank, rmax, basis, m) in enumerate(SPECS):
+        s = synth.random_planted(n, rank, seed=4000 + i, noise=1e-7)
+        X = s.snapshots(0, m + 1)
+        dt = torch.float64 if basis == "f64" else torch.float32
+        out.append(torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda", dt))
+    return out
+
+
+def script(seed=5):
+    """Interleaved arrival order: (stream, update index or 'predict')."""
+    rng = np.random.default_rng(seed)
+    pos = [0] * len(SPECS)
+    events = []
+    while any(pos[i] < SPECS[i][4] for i in range(len(SPECS))):
+        i = int(rng.integers(len(SPECS)))
+        if pos[i] >= SPECS[i][4]:
+            continue
+        events.append((i, pos[i]))
+        pos[i] += 1
+        if pos[i] in PRED_AT.get(i, []):
+            events.append((i, "predict"))
+    for i in range(len(SPECS)):
+        events.append((i, "predict"))          # a final prediction per stream
+    return events
+
+
+def test_mix_equals_alone_under_admission():
+    data = streams()
+    events = script()
+    # alone: each stream by itself, plain per-stream updates
+    alone = {}
+    for i, (n, _, rmax, basis, m) in enumerate(SPECS):
+        g = ODMD(n, rmax, 1e-8, basis=basis)
+        outs = []
+        for k in range(m):
+            g.update(data[i][k], data[i][k + 1])
+            if k + 1 in PRED_AT.get(i, []):
+                outs.append(g.predict(STEPS).cpu().numpy())
+        outs.append(g.predict(STEPS).cpu().numpy())
+        g.sync()
+        alone[i] = outs
+        g.close()
+    # mix: all streams through the server; the budget holds about half of them
+    need = [ODMD.state_bytes(n, rmax, basis) for (n, _, rmax, basis, _) in SPECS]
+    budget = int(0.5 * sum(need)) + max(need)
+    S = Server(budget)
+    for i, (n, _, rmax, basis, _) in enumerate(SPECS):
+        S.open(i, n, rmax, 1e-8, basis)
+    assert any(not S.admitted(i) for i in range(len(SPECS)))   # admission binds
+    preds = {i: [] for i in range(len(SPECS))}
+    for j, (i, what) in enumerate(events):
+        if what == "predict":
+            preds[i].append(S.submit_predict(i, STEPS))
+        else:
+            S.submit_update(i, data[i][what], data[i][what + 1])
+        if len(preds[i]) == len(PRED_AT.get(i, [])) + 1:
+            S.close(i)                          # its last request is queued
+        if j % 3 == 2:
+            S.pump()                             # requests keep arriving between rounds
+    S.drain()
+    assert S.peak_used <= budget
+    assert max(S.batch_sizes) > 1                # rounds really mixed streams
+    for i in range(len(SPECS)):
+        got = [r.out.cpu().numpy() for r in preds[i]]
+        assert all(r.done and r.error is None for r in preds[i])
+        assert len(got) == len(alone[i])
+        for a, b in zip(got, alone[i]):
+            assert np.array_equal(a, b), f"stream {i} differs alone vs in the mix"
+    lat = S.latency_us("update")
+    assert lat["count"] == sum(s[4] for s in SPECS)

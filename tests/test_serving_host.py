@@ -1,0 +1,147 @@
+"""Host logic of the serving loop (admission, ordering, batching), on the CPU
+with a stand-in backend that records what the scheduler asks of the device."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2311_18715_amd.serving import Server
+
+
+class _Ptr:
+    _ids = itertools.count(1)
+
+    def __init__(self):
+        self._p = next(self._ids) * 4096
+
+    def data_ptr(self):
+        return self._p
+
+
+class FakeTorch:
+    uint8 = "uint8"
+
+    class cuda:
+        class Event:
+            def record(self):
+                pass
+
+            def query(self):
+                return True
+
+        @staticmethod
+        def synchronize():
+            pass
+
+    @staticmethod
+    def empty(nbytes, dtype=None, device=None):
+        return _Ptr()
+
+
+class FakeBackend:
+    """ODMD stand-in: state_bytes = 8 n r_max; records each batched update
+    and prediction in the order the scheduler issues them."""
+
+    def __init__(self):
+        self.log = []
+        self.live = set()
+        B = self
+
+        class ODMD:
+            _next = itertools.count(1)
+
+            def __init__(self, n, r_max, tol, basis="f32", workspace=None):
+                self.n, self.id = n, next(ODMD._next)
+                self.handle = type("H", (), {"value": self.id})()
+                B.live.add(self.id)
+                B.models[self.id] = self
+
+            @staticmethod
+            def state_bytes(n, r_max, basis="f32", io=None):
+                return 8 * n * r_max
+
+            def predict(self, steps):
+                B.log.append(("predict", self.id, steps))
+                return np.zeros((steps, self.n))
+
+            def close(self):
+                B.live.discard(self.id)
+
+        self.models = {}
+        self.ODMD = ODMD
+
+    def handle_array(self, models):
+        return np.array([m.handle.value for m in models], dtype=np.uint64)
+
+    def update_batch_ptrs(self, H, xp, yp):
+        self.log.append(("batch", tuple(int(h) for h in H), tuple(int(x) for x in xp)))
+
+
+def make(budget):
+    B = FakeBackend()
+    return Server(budget, backend=B, torch_module=FakeTorch), B
+
+
+def test_admission_fifo_and_budget():
+    S, B = make(budget=8 * 100 * 10 * 2)          # room for two n=100, r_max=10 streams
+    assert S.open(1, 100, 10, 1e-8)
+    assert S.open(2, 100, 10, 1e-8)
+    assert not S.open(3, 100, 10, 1e-8)           # waits
+    assert not S.open(4, 50, 10, 1e-8)            # waits behind 3 (FIFO), though it would fit later
+    assert S.used == 2 * 8000 and not S.admitted(3)
+    S.close(1)
+    S.pump()                                      # 1 has no work: released
+    S.pump()                                      # 3 admitted into the freed room
+    assert S.admitted(3) and not S.admitted(4)
+    assert S.used <= S.budget and S.peak_used <= S.budget
+    S.close(2)
+    S.pump()
+    S.pump()
+    assert S.admitted(4)
+    with pytest.raises(ValueError):
+        S.open(9, 10_000, 64, 1e-8)               # larger than the whole budget
+
+
+def test_rounds_keep_stream_order_and_batch_heads():
+    S, B = make(budget=10**9)
+    for sid in range(3):
+        S.open(sid, 100 + sid, 8, 1e-8)
+    xs = {sid: [_Ptr() for _ in range(4)] for sid in range(3)}
+    reqs = []
+    for k in range(3):
+        for sid in range(3):
+            reqs.append(S.submit_update(sid, xs[sid][k], xs[sid][k + 1]))
+    pr = S.submit_predict(1, 7)
+    S.drain()
+    batches = [e for e in B.log if e[0] == "batch"]
+    # one update per stream per round, all three streams in each of 3 rounds
+    assert len(batches) == 3 and all(len(b[1]) == 3 for b in batches)
+    for k, b in enumerate(batches):
+        assert b[2] == tuple(xs[sid][k].data_ptr() for sid in range(3))
+    # the prediction of stream 1 runs after its three updates
+    order = [e[0] for e in B.log]
+    assert order.index("predict") == len(order) - 1
+    assert all(r.done for r in reqs) and pr.done and pr.out.shape == (7, 101)
+
+
+def test_late_arrivals_join_the_next_round():
+    S, B = make(budget=10**9)
+    S.open(0, 10, 4, 1e-8)
+    S.open(1, 10, 4, 1e-8)
+    p = [_Ptr() for _ in range(4)]
+    S.submit_update(0, p[0], p[1])
+    S.pump()                                       # round 1: stream 0 only
+    S.submit_update(1, p[2], p[3])                 # arrives while round 1 runs
+    S.submit_update(0, p[1], p[2])
+    S.pump()                                       # round 2: both
+    batches = [e for e in B.log if e[0] == "batch"]
+    assert [len(b[1]) for b in batches] == [1, 2]
+
+
+def test_blocked_admission_is_reported():
+    S, B = make(budget=8 * 100 * 10)
+    S.open(1, 100, 10, 1e-8)
+    S.open(2, 100, 10, 1e-8)                      # waits; stream 1 stays open and idle
+    S.submit_update(2, _Ptr(), _Ptr())
+    with pytest.raises(RuntimeError):
+        S.drain()
