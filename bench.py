@@ -284,6 +284,90 @@ def many_streams(torch):
     return res
 
 
+# serving form: Poisson arrivals over many streams, admission under a budget
+SERVE_COUNT, SERVE_N, SERVE_UPDATES, SERVE_PRED = 128, (1e4, 2e5), (100, 200), 100
+SERVE_RATES = (2e4, 6e4, 2e5)          # offered requests/s
+SERVE_BUDGET_FRAC = 0.4                # of the streams' total device state
+
+
+def serving_section(torch):
+    """Streams with n log-uniform in [1e4, 2e5], r_max in {16, 32, 64}, FP32
+    basis, planted rank in {6..30}, U[100, 200] updates each.  All streams
+    ask for admission at the start; the budget holds 40 % of their state, so
+    later streams wait for earlier ones to close.  Requests arrive as a
+    Poisson process at the offered rate, each from a random admitted,
+    unfinished stream (a simulation sends snapshots once it has a slot):
+    90 % its next update, 10 % a 100-state prediction.  Reports achieved
+    rates, p50/p99 request latency (submission to observed completion) and
+    the streams' admission waits."""
+    import math
+    from paper_2311_18715_amd.odmd import ODMD
+    from paper_2311_18715_amd.serving import Server
+    rng = np.random.Generator(np.random.PCG64(231118715 + 5))
+    specs = []
+    for i in range(SERVE_COUNT):
+        n = int(round(math.exp(rng.uniform(math.log(SERVE_N[0]), math.log(SERVE_N[1])))))
+        specs.append((n, int(rng.integers(6, 31)), int(rng.choice([16, 32, 64])),
+                      int(rng.integers(SERVE_UPDATES[0], SERVE_UPDATES[1] + 1)), 231118715 + 7000 + i))
+    data = [_DeviceStream(torch, n, rank, seed).chunk(0, m + 1).float() for (n, rank, _, m, seed) in specs]
+    need = [ODMD.state_bytes(n, rmax, "f32") for (n, _, rmax, _, _) in specs]
+    budget = int(SERVE_BUDGET_FRAC * sum(need)) + max(need)
+    out = {"streams": SERVE_COUNT, "budget_bytes": budget, "total_state_bytes": int(sum(need)),
+           "rates": []}
+    for rate in SERVE_RATES:
+        S = Server(budget)
+        for i, (n, _, rmax, _, _) in enumerate(specs):
+            S.open(i, n, rmax, 1e-8, "f32")
+        pos = [0] * SERVE_COUNT
+        left = set(range(SERVE_COUNT))
+        n_req = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        next_t = t0
+        t_admit = {}
+        while left:
+            now = time.perf_counter()
+            for i in left:
+                if i not in t_admit and S.admitted(i):
+                    t_admit[i] = now - t0
+            active = sorted(i for i in left if i in t_admit)
+            while active and next_t <= now:
+                i = int(rng.choice(active))
+                if rng.random() < 0.1:
+                    S.submit_predict(i, SERVE_PRED)
+                else:
+                    k = pos[i]
+                    S.submit_update(i, data[i][k], data[i][k + 1])
+                    pos[i] += 1
+                    if pos[i] == specs[i][3]:
+                        left.discard(i)
+                        active.remove(i)
+                        S.close(i)
+                n_req += 1
+                next_t += rng.exponential(1.0 / rate)
+            if not active:
+                next_t = max(next_t, time.perf_counter())   # no stream could have sent
+            S.pump()
+        S.drain()
+        dt = time.perf_counter() - t0
+        ups = sum(1 for r in S.completed if r.kind == "update")
+        out["rates"].append({
+            "offered_requests_per_s": rate,
+            "achieved_requests_per_s": round(n_req / dt, 1),
+            "stream_updates_per_s": round(ups / dt, 1),
+            "update_latency_us": {k: round(v, 1) for k, v in S.latency_us("update").items()},
+            "predict_latency_us": {k: round(v, 1) for k, v in S.latency_us("predict").items()},
+            "admission_wait_ms": {"p50": round(float(np.percentile(list(t_admit.values()), 50)) * 1e3, 1),
+                                  "max": round(max(t_admit.values()) * 1e3, 1)},
+            "rounds": S.rounds,
+            "mean_batch": round(float(np.mean(S.batch_sizes)), 1),
+            "peak_state_bytes": S.peak_used})
+        print(f"serving rate {rate:g}: {out['rates'][-1]}", file=sys.stderr, flush=True)
+        del S
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +378,8 @@ def main():
                     help="skip the concurrent-stream and many-stream sections")
     ap.add_argument("--many-only", action="store_true",
                     help="run only the many-stream section (for profiling)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving section")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy MIB MiB once on the device (a reference "
                          "kernel of known traffic for hardware byte counters)")
@@ -309,6 +395,9 @@ def main():
     torch.cuda.set_device(0)
     if args.many_only:
         print(json.dumps({"many_streams": many_streams(torch)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_section(torch)}), flush=True)
         return
     _, X = make_stream()
     n = X.shape[0]
@@ -405,6 +494,8 @@ def main():
         del Xd, out
         torch.cuda.empty_cache()
         result["many_streams"] = many_streams(torch)
+        torch.cuda.empty_cache()
+        result["serving"] = serving_section(torch)
     if args.calibrate_copy > 0:
         a = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

@@ -140,6 +140,17 @@ odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double*
  */
 odmd_status odmd_predict(odmd_t h, int32_t steps, void* out);
 
+/*
+ * odmd_predict for several streams at once: the eigendecompositions they
+ * need run in one launch (one workgroup per stream), then each stream's
+ * states are written as by odmd_predict.  hs[i] distinct handles sharing one
+ * device and HIP stream, steps[i] >= 1, outs[i] as odmd_predict's out (host
+ * arrays of count entries, read during the call).  Asynchronous; results
+ * equal those of odmd_predict bit for bit.  ODMD_EINVAL for a NULL entry,
+ * steps < 1, a repeated handle or handles on different streams.
+ */
+odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* outs, int32_t count);
+
 /* Wait for the handle's stream; return and clear a latched error. */
 odmd_status odmd_sync(odmd_t h);
 

@@ -100,7 +100,7 @@ __device__ __forceinline__ bool make_reflector(double x, double y, double z, dou
   return true;
 }
 
-__global__ __launch_bounds__(64) void k_eig(DevState* st) {
+__device__ __forceinline__ void eig_body(DevState* st) {
   if (st->eig_valid) return;
   __shared__ double H[RMAX * LDH];
   __shared__ double Z[RMAX * LDH];
@@ -542,8 +542,20 @@ __global__ __launch_bounds__(256) void k_basis_coef(DevState* st) {
   }
 }
 
+__global__ __launch_bounds__(64) void k_eig(DevState* st) { eig_body(st); }
+
+// One workgroup per stream of a device-resident table of states.
+__global__ __launch_bounds__(64) void k_eig_batch(DevState* const* __restrict__ sts) {
+  eig_body(sts[blockIdx.x]);
+}
+
 hipError_t launch_eig(DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_eig, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_batch(DevState* const* sts, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig_batch, dim3(count), dim3(64), 0, s, sts);
   return hipGetLastError();
 }
 

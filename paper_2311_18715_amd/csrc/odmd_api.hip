@@ -209,19 +209,11 @@ BatchRing* ring_for(int device) {
   return p.get();
 }
 
-odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
-  hipStream_t stream = hs[0]->stream;
-  // group streams by (storage type, rank bucket): one pass launch per group
-  std::vector<int> kb(count);
-  std::map<std::pair<int, int>, std::vector<int32_t>> groups;
-  for (int32_t i = 0; i < count; ++i) {
-    kb[i] = live_bucket(hs[i]);
-    groups[{hs[i]->basis == ODMD_F64, kb[i]}].push_back(i);
-  }
-  const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
-  const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
-  BatchRing* ring = ring_for(hs[0]->device);
-  std::lock_guard<std::mutex> lk(ring->mu);
+// Next staging slot of the device's ring, grown to at least `bytes`; the
+// ring stays locked (lk) until the caller has recorded the slot's event.
+odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>& lk, BatchSlot*& out) {
+  BatchRing* ring = ring_for(device);
+  lk = std::unique_lock<std::mutex>(ring->mu);
   BatchSlot& sl = ring->slot[ring->next];
   ring->next = (ring->next + 1) % 4;
   if (sl.used) HIP_OK(hipEventSynchronize(sl.done));
@@ -238,6 +230,28 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     sl.cap = bytes;
   }
   if (!sl.done) HIP_OK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+  out = &sl;
+  return ODMD_OK;
+}
+
+odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
+  hipStream_t stream = hs[0]->stream;
+  // group streams by (storage type, rank bucket): one pass launch per group
+  std::vector<int> kb(count);
+  std::map<std::pair<int, int>, std::vector<int32_t>> groups;
+  for (int32_t i = 0; i < count; ++i) {
+    kb[i] = live_bucket(hs[i]);
+    groups[{hs[i]->basis == ODMD_F64, kb[i]}].push_back(i);
+  }
+  const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
+  const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
+  std::unique_lock<std::mutex> lk;
+  BatchSlot* slp = nullptr;
+  {
+    const odmd_status s = acquire_slot(hs[0]->device, bytes, lk, slp);
+    if (s != ODMD_OK) return s;
+  }
+  BatchSlot& sl = *slp;
   PassDesc* pd = static_cast<PassDesc*>(sl.host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
   struct Launch { int first, nd, nblocks, f64, rb; };
@@ -304,6 +318,20 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   ysplit = std::min(ysplit, std::max(1, (K + 7) / 8));
   c.kb = (K + ysplit - 1) / ysplit;
   HIP_OK(launch_combine(c, h->basis == ODMD_F64, out_f32, h->ct, h->stream));
+  return ODMD_OK;
+}
+
+// Coefficients and read-out of predicted states a+1 .. a+steps (the
+// eigendecomposition has been queued before).
+odmd_status launch_rollout(odmd_t h, int32_t steps, void* out) {
+  const int es = elem_bytes(h->io);
+  for (int k0 = 0; k0 < steps; k0 += COEF_CHUNK) {
+    const int K = std::min(COEF_CHUNK, steps - k0);
+    HIP_OK(launch_predict_coef(h->st, k0, K, h->stream));
+    char* o = static_cast<char*>(out) + (int64_t)k0 * h->n * es;
+    const odmd_status s = launch_combine_cols(h, o, h->n, K, h->io == ODMD_F32);
+    if (s != ODMD_OK) return s;
+  }
   return ODMD_OK;
 }
 
@@ -472,12 +500,34 @@ odmd_status odmd_predict(odmd_t h, int32_t steps, void* out) {
   if (!h || !out || steps < 1) return ODMD_EINVAL;
   HIP_OK(hipSetDevice(h->device));
   HIP_OK(launch_eig(h->st, h->stream));
-  const int es = elem_bytes(h->io);
-  for (int k0 = 0; k0 < steps; k0 += COEF_CHUNK) {
-    const int K = std::min(COEF_CHUNK, steps - k0);
-    HIP_OK(launch_predict_coef(h->st, k0, K, h->stream));
-    char* o = static_cast<char*>(out) + (int64_t)k0 * h->n * es;
-    const odmd_status s = launch_combine_cols(h, o, h->n, K, h->io == ODMD_F32);
+  return launch_rollout(h, steps, out);
+}
+
+odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* outs, int32_t count) {
+  if (!hs || !steps || !outs || count < 0) return ODMD_EINVAL;
+  if (count == 0) return ODMD_OK;
+  std::unordered_set<odmd_t> seen;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i] || !outs[i] || steps[i] < 1) return ODMD_EINVAL;
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return ODMD_EINVAL;
+    if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
+  }
+  HIP_OK(hipSetDevice(hs[0]->device));
+  {
+    std::unique_lock<std::mutex> lk;
+    BatchSlot* sl = nullptr;
+    const odmd_status s = acquire_slot(hs[0]->device, (size_t)count * sizeof(DevState*), lk, sl);
+    if (s != ODMD_OK) return s;
+    DevState** tab = static_cast<DevState**>(sl->host);
+    for (int32_t i = 0; i < count; ++i) tab[i] = hs[i]->st;
+    HIP_OK(hipMemcpyAsync(sl->dev, sl->host, (size_t)count * sizeof(DevState*), hipMemcpyHostToDevice,
+                          hs[0]->stream));
+    HIP_OK(launch_eig_batch(static_cast<DevState* const*>(sl->dev), count, hs[0]->stream));
+    HIP_OK(hipEventRecord(sl->done, hs[0]->stream));
+    sl->used = true;
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const odmd_status s = launch_rollout(hs[i], steps[i], outs[i]);
     if (s != ODMD_OK) return s;
   }
   return ODMD_OK;

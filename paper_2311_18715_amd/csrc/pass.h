@@ -66,6 +66,8 @@ hipError_t launch_combine(const CombineArgs& c, int basis_f64, int out_f32, int 
 
 hipError_t launch_basis_coef(DevState* st, hipStream_t s);
 hipError_t launch_eig(DevState* st, hipStream_t s);
+// one workgroup per entry of a device-resident table of states
+hipError_t launch_eig_batch(DevState* const* sts, int count, hipStream_t s);
 hipError_t launch_predict_coef(DevState* st, int k0, int steps, hipStream_t s);
 
 }  // namespace odmd

@@ -22,7 +22,7 @@ STATUS = {
 }
 EXPORTS = [
     "odmd_create", "odmd_create_ex", "odmd_state_bytes", "odmd_update", "odmd_update_batch",
-    "odmd_eigs", "odmd_predict", "odmd_sync", "odmd_destroy", "odmd_status_str",
+    "odmd_eigs", "odmd_predict", "odmd_predict_batch", "odmd_sync", "odmd_destroy", "odmd_status_str",
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
     "odmd_profile_samples",
 ]
@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
                                   ctypes.c_int),
             "odmd_eigs": ([vp, i32, ctypes.POINTER(i32), pd, pd, pd, pd], ctypes.c_int),
             "odmd_predict": ([vp, i32, vp], ctypes.c_int),
+            "odmd_predict_batch": ([ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp), i32],
+                                   ctypes.c_int),
             "odmd_sync": ([vp], ctypes.c_int),
             "odmd_destroy": ([vp], ctypes.c_int),
             "odmd_status_str": ([ctypes.c_int], ctypes.c_char_p),
@@ -230,6 +232,21 @@ def update_batch(models, xs, ys) -> None:
     X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
     Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
     _check(lib().odmd_update_batch(H, X, Y, n), "odmd_update_batch")
+
+
+def predict_batch(models, steps):
+    """odmd_predict_batch: predicted states of several streams, their
+    eigendecompositions in one launch.  Returns one (steps_i, n_i) device
+    tensor per model."""
+    import torch
+    n = len(models)
+    steps = [int(s) for s in steps]
+    outs = [torch.empty((s, m.n), dtype=m.dtype, device="cuda") for m, s in zip(models, steps)]
+    H = (ctypes.c_void_p * n)(*[m.handle for m in models])
+    S = (ctypes.c_int32 * n)(*steps)
+    O = (ctypes.c_void_p * n)(*[_dptr(o) for o in outs])
+    _check(lib().odmd_predict_batch(H, S, O, n), "odmd_predict_batch")
+    return outs
 
 
 def handle_array(models) -> np.ndarray:

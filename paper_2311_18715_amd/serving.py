@@ -166,13 +166,18 @@ class Server:
                 st.queue.popleft()
                 launched.append(r)
             self.batch_sizes.append(len(ups))
-        for st, r in preds:
+        if preds:
+            # the eigendecompositions of all of them in one launch
             try:
-                r.out = st.model.predict(r.steps)
-            except Exception as e:          # e.g. a rank-0 model
-                r.error = str(e)
-            st.queue.popleft()
-            launched.append(r)
+                outs = self.B.predict_batch([st.model for st, _ in preds], [r.steps for _, r in preds])
+            except Exception as e:
+                outs = [None] * len(preds)
+                for _, r in preds:
+                    r.error = str(e)
+            for (st, r), o in zip(preds, outs):
+                r.out = o
+                st.queue.popleft()
+                launched.append(r)
         if launched:
             ev = self.torch.cuda.Event()
             ev.record()

@@ -69,3 +69,18 @@ def test_batch_of_one_and_validation():
     assert np.array_equal(a.state()["atilde"], b.state()["atilde"])
     with pytest.raises(Exception):
         update_batch([a, a], [Xd[0], Xd[0]], [Xd[1], Xd[1]])    # duplicate handle
+
+
+def test_predict_batch_equals_individual():
+    from paper_2311_18715_amd.odmd import predict_batch
+    steps = 25
+    data = make_streams(steps)
+    A = [ODMD(n, rmax, 1e-10, basis=b) for (n, _, rmax, b) in SPECS]
+    for k in range(steps):
+        update_batch(A, [Xd[k] for _, Xd in data], [Xd[k + 1] for _, Xd in data])
+    one = [g.predict(17 + i) for i, g in enumerate(A)]
+    many = predict_batch(A, [17 + i for i in range(len(A))])
+    for a, b in zip(one, many):
+        assert torch.equal(a, b)
+    with pytest.raises(Exception):
+        predict_batch([A[0], A[0]], [3, 3])

@@ -1,0 +1,64 @@
+"""FP32 precision form against the FP64 oracle.
+
+The survey's precision configuration (wake generator with 10 shedding
+harmonics and 10 transients, noise 1e-5 relative, r_max = 64, FP32 basis,
+FP64 core and eigensolver), reduced to n = 60,000 (300 x 100 grid) and 300
+snapshots so that the oracle finishes in seconds.  Both sides see the same
+FP32-rounded snapshots; the oracle runs with the GPU's effective tolerance.
+
+Tolerances (FP32 path): 1e-4 relative on eigenvalues and 1e-3 rad on the
+principal subspace angle.  Readings: the eigenvalue tolerance applies to the
+modes present in the data above the noise (the mean flow and the shedding
+harmonics; the transients, |lambda| <= 0.99, have decayed by 300 steps to
+far below the 1e-5 noise, where no method recovers them), and the principal
+subspace is spanned by the singular directions with sigma >= 1e-3 sigma_1.
+"""
+import numpy as np
+import pytest
+
+from oracle import odmd_oracle as O
+from paper_2311_18715_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2311_18715_amd.odmd import ODMD
+
+
+def test_fp32_wake_against_fp64_oracle():
+    s = synth.wake(nx=300, ny=100, harmonics=10, transients=10, noise=1e-5)
+    X = s.snapshots(0, 301)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).float().cuda()
+    X32 = Xd.double().cpu().numpy().T
+    n = X.shape[0]
+    g = ODMD(n, 64, 1e-8, basis="f32")
+    o = O.OnlineDMD(n, 64, g.info().tol_eff)
+    for k in range(300):
+        g.update(Xd[k], Xd[k + 1])
+        o.update(X32[:, k], X32[:, k + 1])
+    g.sync()
+    st = g.state()
+    assert st["r"] == o.r
+    # eigenvalues of the modes present above the noise
+    lam, _ = g.eigs()
+    lo, _ = o.eigs()
+    pl = s.planted_eigs()
+    persist = pl[np.abs(np.abs(pl) - 1.0) < 1e-12]
+    assert len(persist) == 21
+    mg, mo = O.match_eigs(persist, lam), O.match_eigs(persist, lo)
+    assert np.max(np.abs(mg - mo) / np.abs(mo)) < 1e-4
+    assert np.max(np.abs(mg - persist)) < 1e-6          # and both recover the planted values
+    # principal subspace
+    U = g.basis_matrix().cpu().numpy()
+    k = int(np.sum(o.sigma >= 1e-3 * o.sigma[0]))
+    assert k >= 21
+    assert O.subspace_angle(U[:, :k], o.U[:, :k]) <= 1e-3
+    assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) < 1e-5
+    # singular values above the noise
+    np.testing.assert_allclose(st["sigma"][:k], o.sigma[:k], rtol=1e-4)
+    # 500-step rollout against the oracle's
+    pg = g.predict(500).double().cpu().numpy()
+    po = o.predict(500)
+    err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)
+    assert err.max() < 1e-4

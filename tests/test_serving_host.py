@@ -70,6 +70,9 @@ class FakeBackend:
         self.models = {}
         self.ODMD = ODMD
 
+    def predict_batch(self, models, steps):
+        return [m.predict(s) for m, s in zip(models, steps)]
+
     def handle_array(self, models):
         return np.array([m.handle.value for m in models], dtype=np.uint64)
 
