@@ -39,7 +39,7 @@ extern "C" {
 typedef struct odmd_s* odmd_t;
 
 /* Element types.  ODMD_F64 / ODMD_F32 may be used for the basis and for
- * snapshots; ODMD_BF16 only for the basis. */
+ * snapshots; ODMD_BF16 only for the basis (with FP32 snapshots). */
 typedef enum { ODMD_F64 = 0, ODMD_F32 = 1, ODMD_BF16 = 2 } odmd_dtype;
 
 typedef enum {
@@ -73,11 +73,13 @@ odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
  * As odmd_create, with the basis storage type, the snapshot (and
  * prediction output) type, the HIP stream (hipStream_t, NULL = null
  * stream) and optionally caller-owned device memory.
- *   basis: ODMD_F64, ODMD_F32 (ODMD_BF16 returns ODMD_EINVAL until
- *          supported).  For an FP32 basis the effective tolerance is
- *          max(tol, 16 * 2^-24): FP32 storage cannot hold a direction
- *          weaker than that.
- *   io:    ODMD_F64 or ODMD_F32; must equal basis for F64/F32 bases.
+ *   basis: ODMD_F64, ODMD_F32 or ODMD_BF16 (stored columns rounded to
+ *          nearest even; residuals, projections and the small problems
+ *          stay FP64).  The effective tolerance is max(tol, 16 * 2^-24)
+ *          for an FP32 basis and max(tol, 2^-8) for BF16: the storage
+ *          cannot hold a direction weaker than that.
+ *   io:    ODMD_F64 or ODMD_F32; equal to basis for F64/F32 bases, ODMD_F32
+ *          for a BF16 basis.
  *   The small SVD of each update is solved through its secular equation,
  *   with one-sided Jacobi as the fallback; the environment variable
  *   ODMD_CORE_SVD=jacobi, read here, selects Jacobi only (diagnostics).

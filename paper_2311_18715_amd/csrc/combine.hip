@@ -11,6 +11,7 @@
 
 #include "odmd_internal.h"
 #include "pass.h"
+#include "storage.h"
 
 namespace odmd {
 
@@ -25,7 +26,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs c) {
   double u[RB];
   const TS* __restrict__ T = Us + (i >> 6) * (int64_t)c.ct * 64 + (i & 63);
 #pragma unroll
-  for (int j = 0; j < RB; ++j) u[j] = j < ncols ? (double)T[j * 64] : 0.0;
+  for (int j = 0; j < RB; ++j) u[j] = j < ncols ? Storage<TS>::to_double(T[j * 64]) : 0.0;
   const int k0 = blockIdx.y * c.kb;
   const int k1 = min(c.K, k0 + c.kb);
   // coefficients are read-only for the launch: scalar loads via the
@@ -59,9 +60,13 @@ static hipError_t launch_t(const CombineArgs& c, int rb, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const CombineArgs& c, int basis_f64, int out_f32, int rb, hipStream_t s) {
-  if (basis_f64) return out_f32 ? launch_t<double, float>(c, rb, s) : launch_t<double, double>(c, rb, s);
-  return out_f32 ? launch_t<float, float>(c, rb, s) : launch_t<float, double>(c, rb, s);
+hipError_t launch_combine(const CombineArgs& c, int basis, int out_f32, int rb, hipStream_t s) {
+  switch (basis) {
+    case 0: return out_f32 ? launch_t<double, float>(c, rb, s) : launch_t<double, double>(c, rb, s);
+    case 1: return out_f32 ? launch_t<float, float>(c, rb, s) : launch_t<float, double>(c, rb, s);
+    case 2: return out_f32 ? launch_t<bf16, float>(c, rb, s) : launch_t<bf16, double>(c, rb, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace odmd

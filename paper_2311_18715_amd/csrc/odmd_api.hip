@@ -61,8 +61,11 @@ struct Layout {
 
 int elem_bytes(odmd_dtype t) { return t == ODMD_F64 ? 8 : (t == ODMD_F32 ? 4 : 2); }
 
+// F64 and F32 bases take snapshots of their own type; a BF16 basis takes
+// F32 snapshots.
 bool valid_types(odmd_dtype basis, odmd_dtype io) {
-  if (basis != ODMD_F64 && basis != ODMD_F32) return false;   // BF16 storage not yet offered
+  if (basis == ODMD_BF16) return io == ODMD_F32;
+  if (basis != ODMD_F64 && basis != ODMD_F32) return false;
   return io == basis;
 }
 
@@ -165,7 +168,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.nblk = h->nblk;
   p.ct = h->ct;
   const int kb = live_bucket(h);
-  HIP_OK(launch_pass(p, h->basis == ODMD_F64, kb, h->stream));
+  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
   if (ev) HIP_OK(hipEventRecord(ev[1], h->stream));
   CoreArgs c;
@@ -173,7 +176,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.partials = h->partials;
   c.nblk = h->nblk;
   c.r_max = h->r_max;
-  c.basis_f32 = h->basis == ODMD_F32;
+  c.basis_f32 = h->basis != ODMD_F64;
   c.jacobi_only = h->jacobi_only;
   c.rb = kb;
   c.ct = h->ct;
@@ -236,12 +239,12 @@ odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>&
 
 odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
   hipStream_t stream = hs[0]->stream;
-  // group streams by (storage type, rank bucket): one pass launch per group
+  // group streams by (storage type, live-column bucket): one pass launch per group
   std::vector<int> kb(count);
   std::map<std::pair<int, int>, std::vector<int32_t>> groups;
   for (int32_t i = 0; i < count; ++i) {
     kb[i] = live_bucket(hs[i]);
-    groups[{hs[i]->basis == ODMD_F64, kb[i]}].push_back(i);
+    groups[{(int)hs[i]->basis, kb[i]}].push_back(i);
   }
   const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
   const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
@@ -254,7 +257,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   BatchSlot& sl = *slp;
   PassDesc* pd = static_cast<PassDesc*>(sl.host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
-  struct Launch { int first, nd, nblocks, f64, rb; };
+  struct Launch { int first, nd, nblocks, basis, rb; };
   std::vector<Launch> launches;
   int k = 0;
   for (auto& g : groups) {
@@ -283,7 +286,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     c.partials = h->partials;
     c.nblk = h->nblk;
     c.r_max = h->r_max;
-    c.basis_f32 = h->basis == ODMD_F32;
+    c.basis_f32 = h->basis != ODMD_F64;
     c.jacobi_only = h->jacobi_only;
     c.rb = kb[i];
     c.ct = h->ct;
@@ -294,7 +297,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   HIP_OK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
   const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
   for (const Launch& L : launches)
-    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.f64, L.rb, stream));
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.basis, L.rb, stream));
   HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(static_cast<char*>(sl.dev) + pass_bytes),
                            count, stream));
   // the slot (host staging and device table) is free again once the
@@ -317,7 +320,7 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   int ysplit = (int)std::max<int64_t>(1, (1024 + xb - 1) / xb);
   ysplit = std::min(ysplit, std::max(1, (K + 7) / 8));
   c.kb = (K + ysplit - 1) / ysplit;
-  HIP_OK(launch_combine(c, h->basis == ODMD_F64, out_f32, h->ct, h->stream));
+  HIP_OK(launch_combine(c, (int)h->basis, out_f32, h->ct, h->stream));
   return ODMD_OK;
 }
 
@@ -376,7 +379,11 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   s->r_max = r_max;
   s->ct = L.ct;
   s->tol = tol;
-  s->tol_eff = basis == ODMD_F32 ? std::max(tol, 16.0 * 5.9604644775390625e-08) : tol;
+  // a stored basis cannot hold a direction weaker than its own rounding:
+  // FP32 16 units of roundoff, BF16 one unit (2^-8)
+  s->tol_eff = basis == ODMD_F32    ? std::max(tol, 16.0 * 5.9604644775390625e-08)
+               : basis == ODMD_BF16 ? std::max(tol, 0.00390625)
+                                    : tol;
   s->basis = basis;
   s->io = io;
   s->stream = static_cast<hipStream_t>(hip_stream);

@@ -18,9 +18,10 @@ struct PassArgs {
   int ct;               // column capacity of a basis tile (rank bucket of r_max)
 };
 
+// basis: storage type (0 double, 1 float, 2 bf16; the odmd_dtype codes);
 // rb: live-column bucket of the launch (multiple of 8, >= the stored
 // columns in use m, <= the tile capacity ct)
-hipError_t launch_pass(const PassArgs& p, int basis_f64, int rb, hipStream_t s);
+hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s);
 
 // One stream of a batched pass launch (device-resident table, sorted by blk0).
 struct PassDesc {
@@ -34,7 +35,7 @@ struct PassDesc {
   int blk0;             // its first workgroup in the launch
   int ct;               // column capacity of its basis tiles
 };
-hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis_f64, int rb,
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis, int rb,
                              hipStream_t s);
 
 struct CoreArgs {
@@ -61,8 +62,8 @@ struct CombineArgs {
   int ct;               // column capacity of a basis tile
   int K, kb;            // columns, columns per workgroup row of the grid
 };
-// out type: 0 = FP64, 1 = FP32; basis_f64 selects the stored type
-hipError_t launch_combine(const CombineArgs& c, int basis_f64, int out_f32, int rb, hipStream_t s);
+// out type: 0 = FP64, 1 = FP32; basis: storage type code as for launch_pass
+hipError_t launch_combine(const CombineArgs& c, int basis, int out_f32, int rb, hipStream_t s);
 
 hipError_t launch_basis_coef(DevState* st, hipStream_t s);
 hipError_t launch_eig(DevState* st, hipStream_t s);

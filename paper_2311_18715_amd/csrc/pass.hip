@@ -30,6 +30,7 @@
 
 #include "odmd_internal.h"
 #include "pass.h"
+#include "storage.h"
 
 namespace odmd {
 
@@ -67,7 +68,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr int KK = RB / 4;              // k-steps over the RB live stored columns
   constexpr int NT = ((RB < RMAX ? RB : RMAX) + 15) / 16;   // 16-column output blocks of a refold (r <= RMAX)
   constexpr int NWAVE = PASS_THREADS / 64;
-  typedef typename Mfma<TS>::acc_t acc_t;
+  typedef Storage<TS> SC;
+  typedef typename SC::tc TC;             // compute type of the matrix-core refold
+  typedef typename Mfma<TC>::acc_t acc_t;
 
   const DevState* __restrict__ st = p.st;
   const int m = st->m, r = st->r, refold = st->refold;
@@ -81,16 +84,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   // per-lane coefficients of the first projection in registers; Q in LDS,
   // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
   // Q[4 kk + lane/16][16 nt + lane%16]), for a refold
-  __shared__ TS sG[KK][NT][64];
+  __shared__ TC sG[KK][NT][64];
   __shared__ double sa[4 * KK];          // a, zero past the m stored columns
   {
     for (int c = threadIdx.x; c < 4 * KK; c += PASS_THREADS) sa[c] = c < m ? st->a[c] : 0.0;
     if (refold) {
-      cptr<TS> Q = Mfma<TS>::Q(st);
+      cptr<TC> Q = Mfma<TC>::Q(st);
       for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
         const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
         const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
-        sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TS(0);
+        sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TC(0);
       }
     }
     __syncthreads();
@@ -114,7 +117,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   // staged Q vanish past m; every stored value is finite, see the residual
   // store), x and y are read at a clamped row and zeroed past n.
   const uint32_t loff = (uint32_t)((q * 64 + l16) * sizeof(TS));
-  typedef const __attribute__((address_space(1))) char* gbase_t;
+  typedef gbytes gbase_t;
   auto unit_base = [&](int64_t uu) -> gbase_t {
     const int64_t tile = uu / UPT;
     const uint64_t b = reinterpret_cast<uint64_t>(Us + tile * (int64_t)p.ct * 64 + UR * (uu % UPT));
@@ -127,7 +130,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
       const int ks = 4 * kk < m ? kk : 0;   // uniform
-      A[kk] = *(const __attribute__((address_space(1))) TS*)(base + ks * 256 * (int)sizeof(TS) + loff);
+      A[kk] = SC::gload(base + ks * 256 * (int)sizeof(TS) + loff);
     }
     const int64_t row = (uu / UPT) * 64 + UR * (uu % UPT) + l16;
     const int64_t rc = row < p.n ? row : p.n - 1;
@@ -154,20 +157,21 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     // e = x - S a, in FP64, stored as column `slot`
     double s = 0.0;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) s = __builtin_fma((double)A[kk], sa[4 * kk + q], s);
+    for (int kk = 0; kk < KK; ++kk) s = __builtin_fma(SC::to_double(A[kk]), sa[4 * kk + q], s);
     s += __shfl_xor(s, 16, 64);
     s += __shfl_xor(s, 32, 64);
-    const TS es = (TS)(xv - s);
+    const TS es = SC::from_double(xv - s);
+    const double ed = SC::to_double(es);    // the stored value, which the sums see
     // a non-finite residual (rejected by the small-state kernel, which sees
     // it in the sums below) is stored as zero: stored columns stay finite
-    if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(es) ? es : TS(0);
-    const double ed = (double)es;
+    if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(ed) ? es : SC::from_double(0.0);
 
     // projections, accumulated in-lane
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
-      accE[kk] = __builtin_fma((double)A[kk], ed, accE[kk]);
-      accY[kk] = __builtin_fma((double)A[kk], yv, accY[kk]);
+      const double av = SC::to_double(A[kk]);
+      accE[kk] = __builtin_fma(av, ed, accE[kk]);
+      accY[kk] = __builtin_fma(av, yv, accY[kk]);
     }
     if (q == 0) {
       sEE = __builtin_fma(ed, ed, sEE);
@@ -188,12 +192,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
       for (int nt = 0; nt < NT; ++nt) {
         acc_t d = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) d = Mfma<TS>::mma(sG[kk][nt][lane], A[kk], d);
+        for (int kk = 0; kk < KK; ++kk) d = Mfma<TC>::mma(sG[kk][nt][lane], SC::to_tc(A[kk]), d);
         if (row < p.n) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int col = 16 * nt + Mfma<TS>::dsub(lane, v);
-            if (col < r) T[col * 64 + rr] = d[v];
+            const int col = 16 * nt + Mfma<TC>::dsub(lane, v);
+            if (col < r) T[col * 64 + rr] = SC::from_tc(d[v]);
           }
         }
       }
@@ -297,10 +301,14 @@ static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int rb
   return hipGetLastError();
 }
 
-hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis_f64, int rb,
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis, int rb,
                              hipStream_t s) {
-  return basis_f64 ? launch_batch_rb<double, double>(d, nd, nblocks, rb, s)
-                   : launch_batch_rb<float, float>(d, nd, nblocks, rb, s);
+  switch (basis) {
+    case 0: return launch_batch_rb<double, double>(d, nd, nblocks, rb, s);
+    case 1: return launch_batch_rb<float, float>(d, nd, nblocks, rb, s);
+    case 2: return launch_batch_rb<bf16, float>(d, nd, nblocks, rb, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename TS, typename TIO>
@@ -321,8 +329,13 @@ static hipError_t launch_rb(const PassArgs& p, int rb, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const PassArgs& p, int basis_f64, int rb, hipStream_t s) {
-  return basis_f64 ? launch_rb<double, double>(p, rb, s) : launch_rb<float, float>(p, rb, s);
+hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s) {
+  switch (basis) {
+    case 0: return launch_rb<double, double>(p, rb, s);
+    case 1: return launch_rb<float, float>(p, rb, s);
+    case 2: return launch_rb<bf16, float>(p, rb, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace odmd

@@ -114,9 +114,10 @@ class ODMD:
                  stream=None, workspace=None):
         import torch
         self._torch = torch
+        io = io or ("f32" if basis == "bf16" else basis)     # a BF16 basis takes FP32 snapshots
         bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
-        it = {"f64": F64, "f32": F32}[io or basis]
-        self.n, self.r_max, self.basis, self.io = int(n), int(r_max), basis, io or basis
+        it = {"f64": F64, "f32": F32}[io]
+        self.n, self.r_max, self.basis, self.io = int(n), int(r_max), basis, io
         self.dtype = torch.float64 if self.io == "f64" else torch.float32
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -133,8 +134,9 @@ class ODMD:
 
     @staticmethod
     def state_bytes(n: int, r_max: int, basis: str = "f64", io: str | None = None) -> int:
+        io = io or ("f32" if basis == "bf16" else basis)
         bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
-        it = {"f64": F64, "f32": F32}[io or basis]
+        it = {"f64": F64, "f32": F32}[io]
         return int(lib().odmd_state_bytes(int(n), int(r_max), bt, it))
 
     @property

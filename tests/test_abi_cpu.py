@@ -49,7 +49,8 @@ def test_state_bytes_is_host_only():
     assert L.odmd_state_bytes(100, 65, B.F64, B.F64) == 0       # above the rank cap
     assert L.odmd_state_bytes(10, 11, B.F64, B.F64) == 0        # r_max > n
     assert L.odmd_state_bytes(100, 8, B.F64, B.F32) == 0        # io must match basis
-    assert L.odmd_state_bytes(100, 8, B.BF16, B.F32) == 0       # not offered
+    assert L.odmd_state_bytes(100, 8, B.BF16, B.F32) > 0        # BF16 basis, FP32 snapshots
+    assert L.odmd_state_bytes(100, 8, B.BF16, B.BF16) == 0      # BF16 snapshots are not offered
 
 
 @needs_lib
