@@ -25,10 +25,39 @@ namespace odmd {
 constexpr int LDK = MMAX + 1;        // LDS leading dimension of the core
 constexpr int MAX_SWEEPS = 40;
 
-__device__ __forceinline__ double halfwave_sum(double v) {
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+// Cross-lane sums inside 16-lane rows on the DPP network (quad swaps, then
+// the half-row and row mirrors): every lane of a row ends with the same
+// value, since each step adds the same two partial sums in either order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double quarter_sum(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
   return v;
+}
+__device__ __forceinline__ double quarter_prod(double v) {
+  v *= dpp_move<0xB1>(v);
+  v *= dpp_move<0x4E>(v);
+  v *= dpp_move<0x141>(v);
+  v *= dpp_move<0x140>(v);
+  return v;
+}
+// 32-lane sums: the row sum, then the neighbouring row's (odd rows swap
+// with even rows; the two halves of the pair hold own and partner values)
+__device__ __forceinline__ double halfwave_sum(double v) {
+  v = quarter_sum(v);
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  return __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32)) +
+         __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
 }
 
 // Round-robin (circle) schedule: in round k of Mp-1 rounds, pair i of Mp/2.
@@ -140,10 +169,14 @@ struct SecShared {
   double tol;
 };
 
-__device__ __forceinline__ double quarter_sum(double v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-  return v;
+// 1/x from the hardware reciprocal estimate and two Newton steps
+// (r <- r + r (1 - x r)), each squaring the relative error: about 1 ulp,
+// for the finite non-zero x of the secular terms
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return r;
 }
 
 // lambda_i - d_j^2 = (d_K^2 - d_j^2) + mu_i, with d_K the pole root i is stored against
@@ -294,13 +327,15 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
     for (int m = 0; m < SEC_TERMS; ++m) dsh[m] = (tdj[m] - dK) * (tdj[m] + dK);
     double mu = 0.5 * (lo + hi);
     int it = 0;
+    const int nterm = (nd + 15) >> 4;   // term slots holding a live pole
     for (; it < SEC_MAXIT; ++it) {
       double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
 #pragma unroll
       for (int m = 0; m < SEC_TERMS; ++m) {
+        if (m >= nterm) break;            // uniform
         const int k = ql + 16 * m;
         if (k < nd) {
-          const double rinv = 1.0 / (dsh[m] - mu);
+          const double rinv = recip(dsh[m] - mu);
           const double t = tzz[m] * rinv;
           if (k >= ilo) {
             psi += t;
@@ -351,18 +386,17 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
   __syncthreads();
   if (S.fail) return false;
 
-  // z~ from the computed roots (Loewner's formula)
-  if (tid < nd) {
-    const int jj = tid;
+  // z~ from the computed roots (Loewner's formula), one quarter-wave per
+  // entry, the product split over its 16 lanes
+  for (int jj = qw; jj < nd; jj += CORE_THREADS / 16) {
     const double dj = S.dj[jj];
-    double prod = lam_minus_d(S, jj, dj);
-#pragma unroll 4
-    for (int i = 0; i < nd; ++i) {
-      if (i == jj) continue;
+    double prod = 1.0;
+    for (int i = ql; i < nd; i += 16) {
       const double di = S.dj[i];
-      prod *= lam_minus_d(S, i, dj) / ((di - dj) * (di + dj));
+      prod *= i == jj ? lam_minus_d(S, jj, dj) : lam_minus_d(S, i, dj) / ((di - dj) * (di + dj));
     }
-    S.zh[jj] = S.zs[jj] * sqrt(fmax(prod, 0.0));
+    prod = quarter_prod(prod);
+    if (ql == 0) S.zh[jj] = S.zs[jj] * sqrt(fmax(prod, 0.0));
   }
   // clear the outputs
   for (int idx = tid; idx < n * n; idx += CORE_THREADS) {
@@ -431,6 +465,8 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
   return !S.fail;
 }
 
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void core_update(const CoreArgs& c) {
   DevState* __restrict__ st = c.st;
   __shared__ double sA[MMAX * LDK];
@@ -451,14 +487,29 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int tid = threadIdx.x;
   const int r = st->r, m = st->m, refolded = st->refold;
 
-  // 0. stage Q and the shifted product C in LDS with coalesced passes
-  for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
-    const int c0 = idx / RMAX, j = idx % RMAX;
-    sQ[idx] = (c0 < m && j < r) ? st->Q[idx] : 0.0;
-  }
-  for (int idx = tid; idx < RMAX * RMAX; idx += CORE_THREADS) {
-    const int j = idx % RMAX, k = idx / RMAX;
-    sC[idx] = (j < r && k < r) ? st->C[idx] : 0.0;
+  // 0. stage Q and the shifted product C in LDS with coalesced passes, all
+  //    of a thread's loads issued before its first store
+  {
+    constexpr int NQ = (CMAX * RMAX + CORE_THREADS - 1) / CORE_THREADS;
+    constexpr int NC = (RMAX * RMAX + CORE_THREADS - 1) / CORE_THREADS;
+    double qv[NQ], cv[NC];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int idx = tid + i * CORE_THREADS;
+      const int c0 = idx / RMAX, j = idx % RMAX;
+      qv[i] = (idx < CMAX * RMAX && c0 < m && j < r) ? st->Q[idx] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int idx = tid + i * CORE_THREADS;
+      const int j = idx % RMAX, k = idx / RMAX;
+      cv[i] = (j < r && k < r) ? st->C[idx] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+      if (tid + i * CORE_THREADS < CMAX * RMAX) sQ[tid + i * CORE_THREADS] = qv[i];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) sC[tid + i * CORE_THREADS] = cv[i];
   }
   if (tid < RMAX) sw[tid] = tid < r ? st->w[tid] : 0.0;
 
@@ -648,30 +699,33 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   //    with U'[i, k] = sA[perm[k] * LDK + i].
   const double irho = grow ? 1.0 / rho : 0.0;
   const int mnew = meff + grow;
-  // (Q p2)[c] into red, G p_y into pvec (the next pass's a needs it)
-  if (tid < CMAX) {
-    double s = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < r; ++j) s += sQ[tid * RMAX + j] * p2[j];
-    red[tid] = s;
-  }
-  if (tid < RMAX) {
-    // (G p_y)_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
-    double av = 0.0, bsum = 0.0;
-    if (tid < r) {
-#pragma unroll 8
-      for (int k = 0; k < rn; ++k) {
-        av += sA[perm[k] * LDK + tid] * wk[k];
-        bsum += urk[k] * pyn[k];
+  // (Q p2)[c] into red, G p_y into pvec (pvec is free after the SVD; the
+  // next pass's a needs it): one 16-lane quarter-wave per entry
+  const int qw = tid >> 4, ql = tid & 15;
+  {
+    double bs = 0.0;                       // g . p_y up to 1/rho: U_k(r, :) p_y
+    for (int k = ql; k < rn; k += 16) bs += urk[k] * pyn[k];
+    const double bsum = quarter_sum(bs);
+    for (int row = qw; row < CMAX + RMAX; row += CORE_THREADS / 16) {
+      double t = 0.0;
+      if (row < CMAX) {
+        if (row < m || refolded)
+          for (int j = ql; j < r; j += 16) t += sQ[row * RMAX + j] * p2[j];
+        t = quarter_sum(t);
+        if (ql == 0) red[row] = t;
+      } else {
+        // (G p_y)_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
+        const int j = row - CMAX;
+        if (j < r)
+          for (int k = ql; k < rn; k += 16) t += sA[perm[k] * LDK + j] * wk[k];
+        t = quarter_sum(t);
+        if (ql == 0) pvec[j] = j < r ? t - p2[j] * irho * bsum : 0.0;
       }
-      av -= p2[tid] * irho * bsum;
     }
-    pvec[tid] = av;          // pvec is free after the SVD: G p_y
   }
   __syncthreads();
   // Q' tiles: CMAX/16 (rounded up) row blocks (c) x 4 column blocks (k) of
   // 16 x 16, at most two per wave
-  typedef double d4_t __attribute__((ext_vector_type(4)));
   constexpr int NQT = 4 * ((CMAX + 15) / 16);
   static_assert(NQT <= 2 * (CORE_THREADS / 64), "two Q' tiles per wave at most");
   d4_t qt[2];
@@ -710,18 +764,16 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
   // next first-projection coefficients a = Q' p_y (rows < meff: Q (G p_y);
-  // row meff: g . p_y)
-  if (tid < CMAX) {
-    double av = 0.0;
-    if (tid < meff) {
-#pragma unroll 8
-      for (int j = 0; j < r; ++j) av += sQ[tid * RMAX + j] * pvec[j];
-    } else if (tid == meff && grow) {
-      double b = 0.0;
-      for (int k = 0; k < rn; ++k) b += urk[k] * pyn[k];
-      av = b * irho;
+  // row meff: g . p_y), one quarter-wave per entry
+  for (int row = qw; row < CMAX; row += CORE_THREADS / 16) {
+    double t = 0.0;
+    if (row < meff) {
+      for (int j = ql; j < r; j += 16) t += sQ[row * RMAX + j] * pvec[j];
+    } else if (row == meff && grow) {
+      for (int k = ql; k < rn; k += 16) t += urk[k] * pyn[k];
     }
-    st->a[tid] = av;
+    t = quarter_sum(t);
+    if (ql == 0) st->a[row] = row == meff && grow ? t * irho : t;
   }
   __syncthreads();   // every thread is done reading Q: write Q' in place
   {
@@ -743,31 +795,63 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
 
-  // 9. T = E V_k with E = [[C, 0], [w^T, 0]] (into sA, no longer needed)
-  for (int idx = tid; idx < M * rn; idx += CORE_THREADS) {
-    const int i = idx % M, bcol = idx / M;
-    const int pb = perm[bcol];
-    double s = 0.0;
-    if (i < r) {
-#pragma unroll 8
-      for (int j = 0; j < r; ++j) s += sC[j * RMAX + i] * sV[pb * LDK + j];
-    } else {
-#pragma unroll 8
-      for (int j = 0; j < r; ++j) s += sw[j] * sV[pb * LDK + j];
+  // 9. T = E V_k[:, kept] with E = [[C, 0], [w^T, 0]] (M x r, the zero
+  //    last column dropped), on the matrix cores: 16 x 16 tiles of T, K = r,
+  //    written into sA (U_k is no longer read)
+  {
+    const int wv = tid >> 6, l = tid & 63;
+    const int ntr = (M + 15) / 16, ntc = (rn + 15) / 16;
+    for (int tile = wv; tile < ntr * ntc; tile += CORE_THREADS / 64) {
+      const int i0 = 16 * (tile % ntr), b0 = 16 * (tile / ntr);
+      const int ia = i0 + (l & 15), bb = b0 + (l & 15);
+      const int pb = bb < rn ? perm[bb] : 0;
+      d4_t d = {0.0, 0.0, 0.0, 0.0};
+      for (int j0 = 0; j0 < r; j0 += 4) {
+        const int j = j0 + (l >> 4);
+        double av = 0.0, bv = 0.0;
+        if (j < r) {
+          av = ia < r ? sC[j * RMAX + ia] : (ia == r ? sw[j] : 0.0);
+          bv = bb < rn ? sV[pb * LDK + j] : 0.0;
+        }
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v + (l >> 4);
+        if (i < M && bb < rn) sA[bb * LDK + i] = d[v];
+      }
     }
-    sA[bcol * LDK + i] = s;   // U_k is no longer read (synced above)
   }
   __syncthreads();
 
-  // 10. C <- V_k^T T (kept block), sigma, w, p_y, A~
-  for (int idx = tid; idx < rn * rn; idx += CORE_THREADS) {
-    const int i = idx % rn, j = idx / rn;
-    const int pi = perm[i];
-    double s = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < M; ++k) s += sV[pi * LDK + k] * sA[j * LDK + k];
-    st->C[j * RMAX + i] = s;
-    st->At[j * RMAX + i] = (sgn[i] * s + pyn[i] * wn[j]) / sgn[j];
+  // 10. C <- V_k[:, kept]^T T (rn x rn, K = M) on the matrix cores; sigma,
+  //     w, p_y and A~_ij = (sigma_i C_ij + p_y,i w_j) / sigma_j
+  {
+    const int wv = tid >> 6, l = tid & 63;
+    const int nt = (rn + 15) / 16;
+    for (int tile = wv; tile < nt * nt; tile += CORE_THREADS / 64) {
+      const int i0 = 16 * (tile % nt), j0 = 16 * (tile / nt);
+      const int ia = i0 + (l & 15), jb = j0 + (l & 15);
+      const int pa = ia < rn ? perm[ia] : 0;
+      d4_t d = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < M; k0 += 4) {
+        const int k = k0 + (l >> 4);
+        double av = 0.0, bv = 0.0;
+        if (k < M) {
+          av = ia < rn ? sV[pa * LDK + k] : 0.0;
+          bv = jb < rn ? sA[jb * LDK + k] : 0.0;
+        }
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v + (l >> 4);
+        if (i < rn && jb < rn) {
+          st->C[jb * RMAX + i] = d[v];
+          st->At[jb * RMAX + i] = (sgn[i] * d[v] + pyn[i] * wn[jb]) / sgn[jb];
+        }
+      }
+    }
   }
   if (tid < rn) {
     st->sigma[tid] = sgn[tid];
