@@ -292,7 +292,8 @@ SERVE_BUDGET_FRAC = 0.4                # of the streams' total device state
 
 def serving_section(torch):
     """Streams with n log-uniform in [1e4, 2e5], r_max in {16, 32, 64}, FP32
-    basis, planted rank in {6..30}, U[100, 200] updates each.  All streams
+    or BF16 basis (one half each), planted rank in {6..30}, U[100, 200]
+    updates each.  All streams
     ask for admission at the start; the budget holds 40 % of their state, so
     later streams wait for earlier ones to close.  Requests arrive as a
     Poisson process at the offered rate, each from a random admitted,
@@ -308,16 +309,18 @@ def serving_section(torch):
     for i in range(SERVE_COUNT):
         n = int(round(math.exp(rng.uniform(math.log(SERVE_N[0]), math.log(SERVE_N[1])))))
         specs.append((n, int(rng.integers(6, 31)), int(rng.choice([16, 32, 64])),
-                      int(rng.integers(SERVE_UPDATES[0], SERVE_UPDATES[1] + 1)), 231118715 + 7000 + i))
-    data = [_DeviceStream(torch, n, rank, seed).chunk(0, m + 1).float() for (n, rank, _, m, seed) in specs]
-    need = [ODMD.state_bytes(n, rmax, "f32") for (n, _, rmax, _, _) in specs]
+                      int(rng.integers(SERVE_UPDATES[0], SERVE_UPDATES[1] + 1)), 231118715 + 7000 + i,
+                      "bf16" if rng.random() < 0.5 else "f32"))
+    data = [_DeviceStream(torch, n, rank, seed).chunk(0, m + 1).float()
+            for (n, rank, _, m, seed, _) in specs]
+    need = [ODMD.state_bytes(n, rmax, basis) for (n, _, rmax, _, _, basis) in specs]
     budget = int(SERVE_BUDGET_FRAC * sum(need)) + max(need)
     out = {"streams": SERVE_COUNT, "budget_bytes": budget, "total_state_bytes": int(sum(need)),
            "rates": []}
     for rate in SERVE_RATES:
         S = Server(budget)
-        for i, (n, _, rmax, _, _) in enumerate(specs):
-            S.open(i, n, rmax, 1e-8, "f32")
+        for i, (n, _, rmax, _, _, basis) in enumerate(specs):
+            S.open(i, n, rmax, 1e-8, basis)
         pos = [0] * SERVE_COUNT
         left = set(range(SERVE_COUNT))
         n_req = 0
