@@ -192,21 +192,22 @@ odmd_status odmd_get_basis(odmd_t h, double* out);
 /*
  * Kernel timing.  odmd_profile(h, capacity) with capacity > 0 creates HIP
  * events for at least `capacity` updates (up front, so that timing adds no
- * allocation later) and makes every later update record events on the
- * handle's stream around its streaming pass and around its small-SVD phase;
- * capacity 0 stops recording.  odmd_profile_read (synchronising) returns the
- * summed durations in milliseconds and the number of timed updates, then
- * resets.
+ * allocation later) and makes every later update launch its streaming pass
+ * and its small-SVD kernel with a start and an end event each, which take
+ * the kernel's own begin and end timestamps; capacity 0 stops recording.
+ * odmd_profile_read (synchronising) returns the summed pass and core
+ * durations in milliseconds and the number of timed updates, then resets.
  */
 odmd_status odmd_profile(odmd_t h, int32_t capacity);
 odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_t* count);
 
 /* Per-update samples instead of sums (synchronising): pass_ms[k], core_ms[k]
- * for the first min(cap, timed updates) updates (host arrays of length cap);
- * *count receives the number of timed updates.  Resets like
- * odmd_profile_read. */
+ * and update_ms[k] (pass start to core end, including the launch gap
+ * between the two; update_ms may be NULL) for the first
+ * min(cap, timed updates) updates (host arrays of length cap); *count
+ * receives the number of timed updates.  Resets like odmd_profile_read. */
 odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double* core_ms,
-                                 int64_t* count);
+                                 double* update_ms, int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -14,51 +14,18 @@
 //     p_y <- U_k^T [U^T y; q^T y].
 // The SVD of K is a one-sided (Hestenes) Jacobi iteration with a
 // round-robin pair order, one 32-lane half-wavefront per column pair.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "odmd_internal.h"
 #include "pass.h"
+#include "xlane.h"
 
 namespace odmd {
 
 constexpr int LDK = MMAX + 1;        // LDS leading dimension of the core
 constexpr int MAX_SWEEPS = 40;
-
-// Cross-lane sums inside 16-lane rows on the DPP network (quad swaps, then
-// the half-row and row mirrors): every lane of a row ends with the same
-// value, since each step adds the same two partial sums in either order.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-__device__ __forceinline__ double quarter_sum(double v) {
-  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0x141>(v);   // row_half_mirror
-  v += dpp_move<0x140>(v);   // row_mirror
-  return v;
-}
-__device__ __forceinline__ double quarter_prod(double v) {
-  v *= dpp_move<0xB1>(v);
-  v *= dpp_move<0x4E>(v);
-  v *= dpp_move<0x141>(v);
-  v *= dpp_move<0x140>(v);
-  return v;
-}
-// 32-lane sums: the row sum, then the neighbouring row's (odd rows swap
-// with even rows; the two halves of the pair hold own and partner values)
-__device__ __forceinline__ double halfwave_sum(double v) {
-  v = quarter_sum(v);
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-  return __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32)) +
-         __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
-}
 
 // Round-robin (circle) schedule: in round k of Mp-1 rounds, pair i of Mp/2.
 __device__ __forceinline__ void rr_pair(int k, int i, int Mp, int& a, int& b) {
@@ -302,7 +269,7 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
 #pragma unroll
       for (int m = 0; m < SEC_TERMS; ++m)
         if (ql + 16 * m < nd) fm += tzz[m] / ((tdj[m] - dI) * (tdj[m] + dI) - half);
-      fm = 1.0 + quarter_sum(fm);
+      fm = 1.0 + row_sum(fm);
       K = fm > 0.0 ? i : i - 1;
     }
     const double dK = S.dj[K];
@@ -312,7 +279,7 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
 #pragma unroll
       for (int m = 0; m < SEC_TERMS; ++m) zsum += tzz[m];
       lo = 0.0;
-      hi = quarter_sum(zsum);
+      hi = row_sum(zsum);
     } else {
       lo = (S.dj[i] - dK) * (S.dj[i] + dK);
       hi = (S.dj[i - 1] - dK) * (S.dj[i - 1] + dK);
@@ -346,10 +313,10 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
           }
         }
       }
-      psi = quarter_sum(psi);
-      phi = quarter_sum(phi);
-      dpsi = quarter_sum(dpsi);
-      dphi = quarter_sum(dphi);
+      psi = row_sum(psi);
+      phi = row_sum(phi);
+      dpsi = row_sum(dpsi);
+      dphi = row_sum(dphi);
       const double w = 1.0 + psi + phi;
       if (w > 0.0) hi = mu;
       else lo = mu;
@@ -395,7 +362,7 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
       const double di = S.dj[i];
       prod *= i == jj ? lam_minus_d(S, jj, dj) : lam_minus_d(S, i, dj) / ((di - dj) * (di + dj));
     }
-    prod = quarter_prod(prod);
+    prod = row_prod(prod);
     if (ql == 0) S.zh[jj] = S.zs[jj] * sqrt(fmax(prod, 0.0));
   }
   // clear the outputs
@@ -705,20 +672,20 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   {
     double bs = 0.0;                       // g . p_y up to 1/rho: U_k(r, :) p_y
     for (int k = ql; k < rn; k += 16) bs += urk[k] * pyn[k];
-    const double bsum = quarter_sum(bs);
+    const double bsum = row_sum(bs);
     for (int row = qw; row < CMAX + RMAX; row += CORE_THREADS / 16) {
       double t = 0.0;
       if (row < CMAX) {
         if (row < m || refolded)
           for (int j = ql; j < r; j += 16) t += sQ[row * RMAX + j] * p2[j];
-        t = quarter_sum(t);
+        t = row_sum(t);
         if (ql == 0) red[row] = t;
       } else {
         // (G p_y)_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
         const int j = row - CMAX;
         if (j < r)
           for (int k = ql; k < rn; k += 16) t += sA[perm[k] * LDK + j] * wk[k];
-        t = quarter_sum(t);
+        t = row_sum(t);
         if (ql == 0) pvec[j] = j < r ? t - p2[j] * irho * bsum : 0.0;
       }
     }
@@ -772,7 +739,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     } else if (row == meff && grow) {
       for (int k = ql; k < rn; k += 16) t += urk[k] * pyn[k];
     }
-    t = quarter_sum(t);
+    t = row_sum(t);
     if (ql == 0) st->a[row] = row == meff && grow ? t * irho : t;
   }
   __syncthreads();   // every thread is done reading Q: write Q' in place
@@ -894,8 +861,8 @@ hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_core(const CoreArgs& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_core, dim3(1), dim3(CORE_THREADS), 0, s, c);
+hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  hipExtLaunchKernelGGL(k_core, dim3(1), dim3(CORE_THREADS), 0, s, e0, e1, 0, c);
   return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@
 
 using namespace odmd;
 
+constexpr size_t EV_PER_UPDATE = 4;   // timing events of one profiled update
+
 struct odmd_s {
   int64_t n = 0;
   int r_max = 0, ct = 0;      // rank cap, stored-column capacity of the tiles
@@ -41,7 +43,7 @@ struct odmd_s {
   int64_t units = 0;
   bool prof = false;
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
-  std::vector<hipEvent_t> ev;   // triples: before pass, after pass, after core
+  std::vector<hipEvent_t> ev;   // per update: pass start, pass end, core start, core end
   size_t ev_used = 0;
   // Feedback: the core writes (seq << 8) | m (stored columns in use) into
   // this pinned host word after every update; seq counts the updates issued
@@ -146,16 +148,15 @@ int live_bucket(odmd_t h) {
 odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   hipEvent_t* ev = nullptr;
   if (h->prof) {
-    if (h->ev_used + 3 > h->ev.size()) {
-      for (int k = 0; k < 3; ++k) {
+    if (h->ev_used + EV_PER_UPDATE > h->ev.size()) {
+      for (int k = 0; k < EV_PER_UPDATE; ++k) {
         hipEvent_t e;
         HIP_OK(hipEventCreate(&e));
         h->ev.push_back(e);
       }
     }
     ev = &h->ev[h->ev_used];
-    h->ev_used += 3;
-    HIP_OK(hipEventRecord(ev[0], h->stream));
+    h->ev_used += EV_PER_UPDATE;
   }
   PassArgs p;
   p.Us = h->Us;
@@ -168,9 +169,8 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.nblk = h->nblk;
   p.ct = h->ct;
   const int kb = live_bucket(h);
-  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream));
+  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
-  if (ev) HIP_OK(hipEventRecord(ev[1], h->stream));
   CoreArgs c;
   c.st = h->st;
   c.partials = h->partials;
@@ -182,8 +182,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.ct = h->ct;
   c.fb = h->fb_dev;
   c.seq = h->seq;
-  HIP_OK(launch_core(c, h->stream));
-  if (ev) HIP_OK(hipEventRecord(ev[2], h->stream));
+  HIP_OK(launch_core(c, h->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
   return ODMD_OK;
 }
 
@@ -595,7 +594,7 @@ odmd_status odmd_get_state(odmd_t h, int32_t cap, double* sigma, double* atilde,
 odmd_status odmd_profile(odmd_t h, int32_t capacity) {
   if (!h || capacity < 0) return ODMD_EINVAL;
   HIP_OK(hipSetDevice(h->device));
-  while (h->ev.size() < 3 * (size_t)capacity) {
+  while (h->ev.size() < EV_PER_UPDATE * (size_t)capacity) {
     hipEvent_t e;
     HIP_OK(hipEventCreate(&e));
     h->ev.push_back(e);
@@ -604,37 +603,48 @@ odmd_status odmd_profile(odmd_t h, int32_t capacity) {
   return ODMD_OK;
 }
 
+// durations of timed update k: pass, core, and pass start to core end
+static odmd_status update_times(odmd_t h, size_t k, float* t) {
+  const hipEvent_t* e = &h->ev[EV_PER_UPDATE * k];
+  HIP_OK(hipEventElapsedTime(&t[0], e[0], e[1]));
+  HIP_OK(hipEventElapsedTime(&t[1], e[2], e[3]));
+  HIP_OK(hipEventElapsedTime(&t[2], e[0], e[3]));
+  return ODMD_OK;
+}
+
 odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_t* count) {
   if (!h || !pass_ms || !core_ms || !count) return ODMD_EINVAL;
   HIP_OK(hipSetDevice(h->device));
   HIP_OK(hipStreamSynchronize(h->stream));
+  const size_t n = h->ev_used / EV_PER_UPDATE;
   double a = 0.0, b = 0.0;
-  for (size_t k = 0; k + 3 <= h->ev_used; k += 3) {
-    float t1 = 0.f, t2 = 0.f;
-    HIP_OK(hipEventElapsedTime(&t1, h->ev[k], h->ev[k + 1]));
-    HIP_OK(hipEventElapsedTime(&t2, h->ev[k + 1], h->ev[k + 2]));
-    a += t1;
-    b += t2;
+  for (size_t k = 0; k < n; ++k) {
+    float t[3];
+    const odmd_status st = update_times(h, k, t);
+    if (st != ODMD_OK) return st;
+    a += t[0];
+    b += t[1];
   }
   *pass_ms = a;
   *core_ms = b;
-  *count = (int64_t)(h->ev_used / 3);
+  *count = (int64_t)n;
   h->ev_used = 0;
   return ODMD_OK;
 }
 
 odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double* core_ms,
-                                 int64_t* count) {
+                                 double* update_ms, int64_t* count) {
   if (!h || !pass_ms || !core_ms || !count || cap < 0) return ODMD_EINVAL;
   HIP_OK(hipSetDevice(h->device));
   HIP_OK(hipStreamSynchronize(h->stream));
-  const int64_t n = (int64_t)(h->ev_used / 3);
+  const int64_t n = (int64_t)(h->ev_used / EV_PER_UPDATE);
   for (int64_t k = 0; k < n && k < cap; ++k) {
-    float t1 = 0.f, t2 = 0.f;
-    HIP_OK(hipEventElapsedTime(&t1, h->ev[3 * k], h->ev[3 * k + 1]));
-    HIP_OK(hipEventElapsedTime(&t2, h->ev[3 * k + 1], h->ev[3 * k + 2]));
-    pass_ms[k] = t1;
-    core_ms[k] = t2;
+    float t[3];
+    const odmd_status st = update_times(h, (size_t)k, t);
+    if (st != ODMD_OK) return st;
+    pass_ms[k] = t[0];
+    core_ms[k] = t[1];
+    if (update_ms) update_ms[k] = t[2];
   }
   *count = n;
   h->ev_used = 0;

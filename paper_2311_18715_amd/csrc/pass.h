@@ -20,8 +20,10 @@ struct PassArgs {
 
 // basis: storage type (0 double, 1 float, 2 bf16; the odmd_dtype codes);
 // rb: live-column bucket of the launch (multiple of 8, >= the stored
-// columns in use m, <= the tile capacity ct)
-hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s);
+// columns in use m, <= the tile capacity ct).  e0 / e1 (may be null): events
+// that take the kernel's own start and end timestamps.
+hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // One stream of a batched pass launch (device-resident table, sorted by blk0).
 struct PassDesc {
@@ -50,7 +52,8 @@ struct CoreArgs {
   unsigned* fb;         // host-visible word: (seq << 8) | stored columns after this update
   unsigned seq;         // update sequence number (24 bits) of this launch
 };
-hipError_t launch_core(const CoreArgs& c, hipStream_t s);
+hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 // one workgroup per entry of a device-resident CoreArgs table
 hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s);
 

@@ -26,11 +26,13 @@
 //   * the projections accumulate in-lane across all rows a lane sees and are
 //     reduced once per workgroup, in a fixed order (bitwise reproducible).
 // The next unit's loads are issued before the current unit is processed.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "odmd_internal.h"
 #include "pass.h"
 #include "storage.h"
+#include "xlane.h"
 
 namespace odmd {
 
@@ -81,24 +83,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, l16 = lane & 15;
 
-  // per-lane coefficients of the first projection in registers; Q in LDS,
-  // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
-  // Q[4 kk + lane/16][16 nt + lane%16]), for a refold
-  __shared__ TC sG[KK][NT][64];
-  __shared__ double sa[4 * KK];          // a, zero past the m stored columns
-  {
-    for (int c = threadIdx.x; c < 4 * KK; c += PASS_THREADS) sa[c] = c < m ? st->a[c] : 0.0;
-    if (refold) {
-      cptr<TC> Q = Mfma<TC>::Q(st);
-      for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
-        const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
-        const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
-        sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TC(0);
-      }
-    }
-    __syncthreads();
-  }
-
   double accE[KK], accY[KK], sEE = 0.0, sEY = 0.0, sXX = 0.0, sYY = 0.0;
 #pragma unroll
   for (int kk = 0; kk < KK; ++kk) accE[kk] = accY[kk] = 0.0;
@@ -143,8 +127,31 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   // current one is processed
   TS A[KK], An[KK];
   double xv, yv, xn, yn;
+  // the coefficients a of the first projection go to LDS, with Q
+  // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
+  // Q[4 kk + lane/16][16 nt + lane%16]) for a refold.  a is loaded before
+  // the first unit, so that waiting for it leaves the unit's loads in flight.
+  static_assert(PASS_THREADS >= 4 * KK, "one thread per coefficient");
+  __shared__ TC sG[KK][NT][64];
+  __shared__ double sa[4 * KK];          // a, zero past the m stored columns
+  const int ca = threadIdx.x;
+  const double a_c = (ca < 4 * KK && ca < m) ? st->a[ca] : 0.0;
+  // (unconditional, as in the loop: a wave without a unit of its own
+  // re-reads the workgroup's first one, u0 < u1 since there are at least as
+  // many units as workgroups)
   int64_t u = u0 + __builtin_amdgcn_readfirstlane(wave);
-  if (u < u1) load_unit(u, A, xv, yv);
+  load_unit(u < u1 ? u : u0, A, xv, yv);
+  if (ca < 4 * KK) sa[ca] = a_c;
+  if (refold) {
+    cptr<TC> Q = Mfma<TC>::Q(st);
+    for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
+      const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
+      const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
+      sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TC(0);
+    }
+  }
+  __syncthreads();
+
   for (; u < u1; u += NWAVE) {
     const bool more = u + NWAVE < u1;
     load_unit(more ? u + NWAVE : u, An, xn, yn);
@@ -158,8 +165,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     double s = 0.0;
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) s = __builtin_fma(SC::to_double(A[kk]), sa[4 * kk + q], s);
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
+    s = add_half_pair(add_row_pair(s));
     const TS es = SC::from_double(xv - s);
     const double ed = SC::to_double(es);    // the stored value, which the sums see
     // a non-finite residual (rejected by the small-state kernel, which sees
@@ -208,23 +214,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     yv = yn;
   }
 
-  // fixed-order reduction: across the 16 lanes that share a column (in-wave
-  // butterfly), then across the workgroup's waves in index order
+  // fixed-order reduction: across the 16 lanes that share a column (one
+  // 16-lane row), then across the workgroup's waves in index order
 #pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-      accE[kk] += __shfl_xor(accE[kk], o, 64);
-      accY[kk] += __shfl_xor(accY[kk], o, 64);
-    }
+  for (int kk = 0; kk < KK; ++kk) {
+    accE[kk] = row_sum(accE[kk]);
+    accY[kk] = row_sum(accY[kk]);
   }
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    sEE += __shfl_xor(sEE, o, 64);
-    sEY += __shfl_xor(sEY, o, 64);
-    sXX += __shfl_xor(sXX, o, 64);
-    sYY += __shfl_xor(sYY, o, 64);
-  }
+  // the four scalar sums live in the first row only
+  sEE = row_sum(sEE);
+  sEY = row_sum(sEY);
+  sXX = row_sum(sXX);
+  sYY = row_sum(sYY);
   // record: [S^T e (RB) | S^T y (RB) | e.e e.y x.x y.y]
   __shared__ double red[NWAVE][2 * RB + 4];
   if (l16 == 0) {
@@ -312,28 +313,30 @@ hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis, 
 }
 
 template <typename TS, typename TIO>
-static hipError_t launch_rb(const PassArgs& p, int rb, hipStream_t s) {
+static hipError_t launch_rb(const PassArgs& p, int rb, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
   const dim3 grid(p.nblk), block(PASS_THREADS);
   switch (rb) {
-    case 8: hipLaunchKernelGGL((k_pass<TS, TIO, 8>), grid, block, 0, s, p); break;
-    case 16: hipLaunchKernelGGL((k_pass<TS, TIO, 16>), grid, block, 0, s, p); break;
-    case 24: hipLaunchKernelGGL((k_pass<TS, TIO, 24>), grid, block, 0, s, p); break;
-    case 32: hipLaunchKernelGGL((k_pass<TS, TIO, 32>), grid, block, 0, s, p); break;
-    case 40: hipLaunchKernelGGL((k_pass<TS, TIO, 40>), grid, block, 0, s, p); break;
-    case 48: hipLaunchKernelGGL((k_pass<TS, TIO, 48>), grid, block, 0, s, p); break;
-    case 56: hipLaunchKernelGGL((k_pass<TS, TIO, 56>), grid, block, 0, s, p); break;
-    case 64: hipLaunchKernelGGL((k_pass<TS, TIO, 64>), grid, block, 0, s, p); break;
-    case 72: hipLaunchKernelGGL((k_pass<TS, TIO, 72>), grid, block, 0, s, p); break;
+    case 8: hipExtLaunchKernelGGL((k_pass<TS, TIO, 8>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 16: hipExtLaunchKernelGGL((k_pass<TS, TIO, 16>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 24: hipExtLaunchKernelGGL((k_pass<TS, TIO, 24>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 32: hipExtLaunchKernelGGL((k_pass<TS, TIO, 32>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 40: hipExtLaunchKernelGGL((k_pass<TS, TIO, 40>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 48: hipExtLaunchKernelGGL((k_pass<TS, TIO, 48>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 56: hipExtLaunchKernelGGL((k_pass<TS, TIO, 56>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 64: hipExtLaunchKernelGGL((k_pass<TS, TIO, 64>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 72: hipExtLaunchKernelGGL((k_pass<TS, TIO, 72>), grid, block, 0, s, e0, e1, 0, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s) {
+hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1) {
   switch (basis) {
-    case 0: return launch_rb<double, double>(p, rb, s);
-    case 1: return launch_rb<float, float>(p, rb, s);
-    case 2: return launch_rb<bf16, float>(p, rb, s);
+    case 0: return launch_rb<double, double>(p, rb, s, e0, e1);
+    case 1: return launch_rb<float, float>(p, rb, s, e0, e1);
+    case 2: return launch_rb<bf16, float>(p, rb, s, e0, e1);
   }
   return hipErrorInvalidValue;
 }

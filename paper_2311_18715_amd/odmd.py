@@ -75,7 +75,7 @@ def lib() -> ctypes.CDLL:
             "odmd_get_basis": ([vp, vp], ctypes.c_int),
             "odmd_profile": ([vp, i32], ctypes.c_int),
             "odmd_profile_read": ([vp, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
-            "odmd_profile_samples": ([vp, i64, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
+            "odmd_profile_samples": ([vp, i64, pd, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -207,12 +207,14 @@ class ODMD:
         return a.value, b.value, c.value
 
     def profile_samples(self, cap: int = 1 << 16):
-        """Per-update (pass_ms, core_ms) arrays of the timed updates."""
-        a, b, c = np.zeros(cap), np.zeros(cap), ctypes.c_int64()
-        _check(lib().odmd_profile_samples(self._h, cap, _dbl(a), _dbl(b), ctypes.byref(c)),
+        """Per-update (pass_ms, core_ms, update_ms) arrays of the timed
+        updates: kernel durations of the pass and the core, and pass start
+        to core end."""
+        a, b, u, c = np.zeros(cap), np.zeros(cap), np.zeros(cap), ctypes.c_int64()
+        _check(lib().odmd_profile_samples(self._h, cap, _dbl(a), _dbl(b), _dbl(u), ctypes.byref(c)),
                "odmd_profile_samples")
         k = min(cap, c.value)
-        return a[:k].copy(), b[:k].copy()
+        return a[:k].copy(), b[:k].copy(), u[:k].copy()
 
     def close(self) -> None:
         if getattr(self, "_h", None):
