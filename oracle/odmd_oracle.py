@@ -197,11 +197,13 @@ class OnlineDMD:
 
 
 class OnlineDMDF1:
-    """Cross-check form for general (not necessarily chained) pairs.
+    """Online DMD for general (not necessarily chained) pairs.
 
     Keeps B = Y W (n x r) instead of the shifted product C, and forms
     A~ = U^T B S^-1 straight from the definition; B follows the right factor
-    through B <- ([B y] V_k)[:, :r'].
+    through B <- ([B y] V_k)[:, :r'].  The left factor, sigma and the
+    rank rules are those of the chained form; p_y = U^T y of the last pair
+    anchors the rollout.
     """
 
     def __init__(self, n: int, r_max: int, tol: float):
@@ -229,7 +231,16 @@ class OnlineDMDF1:
         self.p_y = self.U.T @ y
 
     def atilde(self) -> np.ndarray:
+        """A~ = U^T B S^-1 = U^T Y W S^-1 (Sec. 2.3), B = Y W."""
         return (self.U.T @ self.B) / self.sigma[None, :]
+
+    def eigs(self):
+        return eig_sorted(self.atilde())
+
+    def predict(self, steps: int) -> np.ndarray:
+        """States after the last y seen, as for chained pairs."""
+        lam, V = self.eigs()
+        return rollout(self.U, V, lam, self.p_y, steps)
 
 
 def batch_dmd(X: np.ndarray, Y: np.ndarray, r_max: int, tol: float):

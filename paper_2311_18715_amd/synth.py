@@ -206,3 +206,27 @@ def batched_streams(count: int = 256, n_lo: float = 1e4, n_hi: float = 1e6,
         n = int(round(math.exp(g.uniform(math.log(n_lo), math.log(n_hi)))))
         out.append((n, int(g.integers(6, 31)), int(g.integers(16, 65)), seed + i))
     return out
+
+
+def restarted_pairs(s: PlantedStream, segments: int, length: int, seed: int):
+    """Unchained snapshot pairs of one planted operator.
+
+    ``segments`` trajectories of ``length`` pairs each, every one started
+    from fresh amplitudes b_j ~ CN(0, 1) (drawn from PCG64(seed)) at a random
+    start time in [0, 200), with the stream's own relative noise (per-segment
+    noise seeds).  Returns (X, Y), each (n, segments * length): Y[:, j] is
+    the successor of X[:, j] inside its trajectory, and X[:, j + 1] differs
+    from Y[:, j] wherever a new segment starts.
+    """
+    g = np.random.Generator(np.random.PCG64(seed))
+    p = s.lam.shape[0]
+    xs, ys = [], []
+    for sgm in range(segments):
+        amp = (g.standard_normal(p) + 1j * g.standard_normal(p)) / math.sqrt(2.0)
+        k0 = int(g.integers(0, 200))
+        t = dataclasses.replace(s, amp=amp, seed=s.seed + 7919 * (sgm + 1))
+        z = t.snapshots(k0, k0 + length + 1)
+        xs.append(z[:, :-1])
+        ys.append(z[:, 1:])
+    return np.hstack(xs), np.hstack(ys)
+

@@ -197,6 +197,63 @@ def test_f1_equals_f2_without_truncation():
     assert rel_eig_err(la, lb) < 1e-11
 
 
+def run_pairs(X, Y, r_max, tol, cls=O.OnlineDMDF1):
+    o = cls(X.shape[0], r_max, tol)
+    for j in range(X.shape[1]):
+        o.update(X[:, j], Y[:, j])
+    return o
+
+
+def test_f1_general_pairs_recover_planted_eigs():
+    """Unchained pairs of one exact linear map: the spectrum on the planted
+    subspace is recovered whatever the pairing (closed form)."""
+    s = synth.planted_small(n=300)
+    X, Y = synth.restarted_pairs(s, 6, 15, seed=17)
+    o = run_pairs(X, Y, 20, 1e-10)
+    assert o.r == 6
+    assert rel_eig_err(s.planted_eigs(), np.linalg.eigvals(o.atilde())) < 1e-11
+    # the chained form refuses these pairs
+    with pytest.raises(O.UnchainedPair):
+        run_pairs(X, Y, 20, 1e-10, cls=O.OnlineDMD)
+
+
+@pytest.mark.parametrize("n,m", [(60, 25), (300, 48)])
+def test_f1_general_pairs_match_pinv_operator(n, m):
+    """Independent random x_j, y_j, no truncation: U A~ U^T equals the
+    projected operator P_X Y X^+ formed by pseudo-inverse (brute force)."""
+    g = np.random.default_rng(3 * n + m)
+    X, Y = g.standard_normal((n, m)), g.standard_normal((n, m))
+    o = run_pairs(X, Y, m + 2, 1e-13)
+    assert o.r == m
+    Xp = np.linalg.pinv(X)
+    A = (X @ Xp) @ Y @ Xp
+    P = o.U @ o.atilde() @ o.U.T
+    assert np.max(np.abs(P - A)) < 1e-10 * np.max(np.abs(A))
+    # rollout anchored at the last y: x^_1 = U A~ U^T y_last
+    np.testing.assert_allclose(o.predict(1)[0], A @ Y[:, -1], rtol=0, atol=1e-9 * np.max(np.abs(A @ Y[:, -1])))
+
+
+def test_f1_planted_mistake_is_caught():
+    """B rotated with the left factor U_k instead of V_k (a plausible
+    transposition) breaks the pseudo-inverse pin."""
+    class BadF1(O.OnlineDMDF1):
+        def update(self, x, y):
+            p, rho, q = O._cgs2(self.U, x, self.tol)
+            Uk, s, Vk = O._core_svd(self.sigma, p, rho)
+            rn = O._truncation_rank(s, self.r_max, self.tol)
+            self.U = np.hstack([self.U, q[:, None]]) @ Uk[:, :rn]
+            self.B = np.hstack([self.B, y[:, None]]) @ Uk[:, :rn]
+            self.sigma = s[:rn].copy()
+            self.p_y = self.U.T @ y
+
+    g = np.random.default_rng(9)
+    X, Y = g.standard_normal((60, 25)), g.standard_normal((60, 25))
+    o = run_pairs(X, Y, 27, 1e-13, cls=BadF1)
+    Xp = np.linalg.pinv(X)
+    A = (X @ Xp) @ Y @ Xp
+    assert np.max(np.abs(o.U @ o.atilde() @ o.U.T - A)) > 1e-3 * np.max(np.abs(A))
+
+
 # ---------------------------------------------------------------- invariants
 
 def test_scaling_invariance():
