@@ -103,6 +103,68 @@ CONC_S = (8, 32, 128)
 CONC_WARM, CONC_STEPS, CONC_OFFSET = 100, 200, 7
 
 
+def general_pairs(torch, Xd, bytes_upd):
+    """The benchmark's stream through a general-pair handle, with every
+    fifth full-order step replaced (the pair (x_k, x_k+1) for k = 4 mod 5
+    is left out, so the next pair does not chain): updates/s and µs per
+    update from the wall clock over the timed updates."""
+    from paper_2311_18715_amd.odmd import ODMD
+    n = Xd.shape[1]
+    ks = [k for k in range(Xd.shape[0] - 1) if k % 5 != 4]
+    g = ODMD(n, R_MAX, TOL, pairs="general")
+    warm = [k for k in ks if k < STEADY_FROM]
+    timed = [k for k in ks if STEADY_FROM <= k < STEADY_FROM + 800]
+    for k in warm:
+        g.update(Xd[k], Xd[k + 1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in timed:
+        g.update(Xd[k], Xd[k + 1])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.sync()
+    r = g.info().r
+    g.close()
+    ups = len(timed) / dt
+    return {"updates_per_s": round(ups, 1), "us_per_update": round(dt / len(timed) * 1e6, 2),
+            "updates_timed": len(timed), "rank": r,
+            "pairs": "x_k -> x_k+1 of the stream, k = 4 mod 5 left out (unchained after each gap)",
+            "hbm_gbps_algorithmic_chained_bytes": round(ups * bytes_upd / 1e9, 1)}
+
+
+def hybrid_section(torch):
+    """The hybrid FOM/DMD workflow (Sec. 2.1) on the implicit heat stand-in,
+    400 x 400 grid (n = 160,000), 240 steps from a start on the forced
+    periodic orbit plus one decaying mode: FOM calls avoided, final-state
+    error against a FOM-only run, and the wall time of both."""
+    from paper_2311_18715_amd.hybrid import HeatFOM, run_hybrid
+    from paper_2311_18715_amd.odmd import ODMD
+    steps = 240
+    fom = HeatFOM(torch, 400, 400)
+    u0 = fom.initial_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = u0
+    for k in range(steps):
+        ref = fom.step(ref, k)
+    torch.cuda.synchronize()
+    t_fom = time.perf_counter() - t0
+    fom_iters = fom.cg_iters
+    fom.cg_iters = 0
+    t0 = time.perf_counter()
+    res = run_hybrid(fom, u0, steps, lambda n: ODMD(n, 16, 1e-10, pairs="general"),
+                     eps_dmd=1e-8, horizon=32, check_convergence=False)
+    torch.cuda.synchronize()
+    t_hyb = time.perf_counter() - t0
+    err = float(torch.linalg.norm(res.final - ref) / torch.linalg.norm(ref))
+    return {"steps": steps, "n": fom.n, "fom_calls": res.fom_calls,
+            "fom_calls_avoided_frac": round(res.fom_fraction_avoided, 4),
+            "final_rel_error_vs_fom_only": float(f"{err:.3e}"),
+            "fom_only_s": round(t_fom, 3), "hybrid_s": round(t_hyb, 3),
+            "cg_iterations": {"fom_only": fom_iters, "hybrid": fom.cg_iters},
+            "eps_dmd": 1e-8, "r_max": 16}
+
+
 def concurrent_streams(torch, Xd, bytes_upd):
     """S independent copies of the benchmark workload, advanced together by
     odmd_update_batch.  Stream i reads the snapshot sequence shifted by
@@ -383,6 +445,10 @@ def main():
                     help="skip the concurrent-stream and many-stream sections")
     ap.add_argument("--many-only", action="store_true",
                     help="run only the many-stream section (for profiling)")
+    ap.add_argument("--hybrid-only", action="store_true",
+                    help="run only the hybrid FOM/DMD section and print it")
+    ap.add_argument("--general-only", action="store_true",
+                    help="run only the general-pair section and print it")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving section")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -404,9 +470,16 @@ def main():
     if args.serving_only:
         print(json.dumps({"serving": serving_section(torch)}), flush=True)
         return
+    if args.hybrid_only:
+        print(json.dumps({"hybrid_heat_n160k": hybrid_section(torch)}), flush=True)
+        return
     _, X = make_stream()
     n = X.shape[0]
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda")
+    if args.general_only:
+        bytes_upd = n * (R_MAX + R_MAX) * 8 + 2 * n * 8
+        print(json.dumps({"general_pairs_n160k": general_pairs(torch, Xd, bytes_upd)}), flush=True)
+        return
     out = torch.empty((ROLLOUT, n), dtype=torch.float64, device="cuda")
     m = SNAPS - 1
     models = [ODMD(n, R_MAX, TOL) for _ in range(args.warmup + args.steps)]
@@ -496,12 +569,16 @@ def main():
     if not args.no_extra:
         del models
         torch.cuda.empty_cache()
+        result["general_pairs_n160k"] = general_pairs(torch, Xd, bytes_upd)
+        torch.cuda.empty_cache()
         result["concurrent_n160k"] = concurrent_streams(torch, Xd, bytes_upd)
         del Xd, out
         torch.cuda.empty_cache()
         result["many_streams"] = many_streams(torch)
         torch.cuda.empty_cache()
         result["serving"] = serving_section(torch)
+        torch.cuda.empty_cache()
+        result["hybrid_heat_n160k"] = hybrid_section(torch)
     if args.calibrate_copy > 0:
         a = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

@@ -98,14 +98,38 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
 size_t odmd_state_bytes(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io);
 
 /*
+ * General pairs (Sec. 2.3 with U+ and U- built from pairs that need not
+ * chain: several trajectories, or a hybrid run in which accepted
+ * predictions replace full-order steps, so that x_k of a pair is not the
+ * x_k1 of the pair before).  Arguments, memory and errors as for
+ * odmd_create_ex.  The handle keeps B = Y W (n x r, Y the matrix of all
+ * x_k1, W the right singular vectors) beside U, in the same stored-column
+ * form (a second set of stored columns, appended with each x_k1 and
+ * refolded when full), and A~ = U^T B S^-1.  Each update recomputes
+ * U^T x_k with an extra sweep over the stored columns (the chained form
+ * reuses the previous step's U^T x_k1), so it moves about twice the bytes
+ * of a chained update; no chaining check is made.  odmd_update_batch
+ * rejects such handles (ODMD_EINVAL); every other call works as for a
+ * chained handle, the prediction anchored at the last x_k1.
+ */
+odmd_status odmd_create_general(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
+                                odmd_dtype io, void* hip_stream, void* workspace,
+                                size_t workspace_bytes, odmd_t* h);
+
+/* Device bytes of a general-pair handle (0 for invalid arguments). */
+size_t odmd_state_bytes_general(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io);
+
+/*
  * Append one snapshot pair: x_k (a new column of U-) and x_k+1 (a new
- * column of U+), Sec. 2.3, "only a single snapshot is appended to the
- * snapshot matrix every iteration".  x_k, x_k1: device, n elements of the
- * io type, contiguous; they must stay valid until the stream has run the
+ * column of U+); Sec. 2.3 grows each snapshot matrix by one column per
+ * iteration, a rank-1 update.  x_k, x_k1: device, n elements of the io
+ * type, contiguous; they must stay valid until the stream has run the
  * update.  The first call initialises the model from x_k (Sec. 2.1).
- * Later pairs must chain: x_k must equal, element for element, the x_k1 of
- * the previous accepted update; otherwise the update is skipped and
- * ODMD_ESEQ is latched.  Asynchronous.
+ * On a chained handle (odmd_create, odmd_create_ex) later pairs must
+ * chain: x_k must equal, element for element, the x_k1 of the previous
+ * accepted update; otherwise the update is skipped and ODMD_ESEQ is
+ * latched.  A general-pair handle (odmd_create_general) takes any pair.
+ * Asynchronous.
  */
 odmd_status odmd_update(odmd_t h, const void* x_k, const void* x_k1);
 

@@ -434,6 +434,133 @@ __device__ bool secular_svd(double* A, double* V, const double* sig, const doubl
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
+// General pairs (B = Y W held as T R): the right-factor bookkeeping of one
+// update, in place of the chained pairs' shifted product.  With
+// U' = [U q] U_k and B' = [B y] V_k (kept columns),
+//     G' = U'^T B' = U_k^T E V_k,   E = [[G, U^T y], [q^T B, q^T y]],
+//     R' = [[R, 0], [0, 1]] V_k,    A~ = G' diag(sigma')^-1.
+// U_k(i, a) = sA[perm[a] * LDK + i] / sd[perm[a]], V_k(i, a) = sV[perm[a] *
+// LDK + i]; sQ is free here (Q' is written) and receives E V_k.
+__device__ __noinline__ void general_tail(const CoreArgs& c, int r, int rn, int M, double qy,
+                                          const double* sA, const double* sV, const double* sC,
+                                          double* sQ, const double* sd, const double* sgn,
+                                          const double* pyr, const double* qB, const int* perm) {
+  DevState* __restrict__ st = c.st;
+  DevState* __restrict__ tst = c.tst;
+  const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+  const int trefold = tst->refold;            // the T sweep left T[:, :r] = B (R = I)
+  const int mTe = trefold ? r : tst->m;       // stored T columns before y; y sits in column mTe
+  // E V_k[:, kept] (M x rn, K = M) into sQ[b * MMAX + i]
+  {
+    const int ntr = (M + 15) / 16, ntc = (rn + 15) / 16;
+    for (int tile = wv; tile < ntr * ntc; tile += CORE_THREADS / 64) {
+      const int i0 = 16 * (tile % ntr), b0 = 16 * (tile / ntr);
+      const int ia = i0 + (l & 15), bb = b0 + (l & 15);
+      const int pb = bb < rn ? perm[bb] : 0;
+      d4_t d = {0.0, 0.0, 0.0, 0.0};
+      for (int j0 = 0; j0 < M; j0 += 4) {
+        const int j = j0 + (l >> 4);
+        double av = 0.0, bv = 0.0;
+        if (j < M) {
+          if (ia < r) av = j < r ? sC[j * RMAX + ia] : pyr[ia];
+          else if (ia == r) av = j < r ? qB[j] : qy;
+          bv = bb < rn ? sV[pb * LDK + j] : 0.0;
+        }
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v + (l >> 4);
+        if (i < M && bb < rn) sQ[bb * MMAX + i] = d[v];
+      }
+    }
+  }
+  // R' tiles in registers (R is read from the T state, rewritten in place
+  // after the barrier below)
+  constexpr int NRT = 4 * ((CMAX + 15) / 16);
+  d4_t rt[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int tile = wv + 16 * h;
+    d4_t d = {0.0, 0.0, 0.0, 0.0};
+    if (tile < NRT) {
+      const int c0 = 16 * (tile >> 2), k0 = 16 * (tile & 3);
+      const int kb = k0 + (l & 15);
+      const int pk = kb < rn ? perm[kb] : 0;
+      if (!trefold) {
+        for (int j0 = 0; j0 < r; j0 += 4) {
+          const int j = j0 + (l >> 4);
+          const int ca = c0 + (l & 15);
+          const double av = (j < r && ca < mTe) ? tst->Q[ca * RMAX + j] : 0.0;
+          const double bv = (j < r && kb < rn) ? sV[pk * LDK + j] : 0.0;
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cr = c0 + 4 * v + (l >> 4);
+        double out = 0.0;
+        if (kb < rn) {
+          if (cr < mTe) out = trefold ? sV[pk * LDK + cr] : d[v];
+          else if (cr == mTe) out = sV[pk * LDK + r];
+        }
+        d[v] = out;
+      }
+    }
+    rt[h] = d;
+  }
+  __syncthreads();
+  // G' = U_k^T (E V_k) (rn x rn, K = M) and A~ = G' diag(sigma')^-1
+  {
+    const int nt = (rn + 15) / 16;
+    for (int tile = wv; tile < nt * nt; tile += CORE_THREADS / 64) {
+      const int i0 = 16 * (tile % nt), j0 = 16 * (tile / nt);
+      const int ia = i0 + (l & 15), jb = j0 + (l & 15);
+      const int pa = ia < rn ? perm[ia] : 0;
+      d4_t d = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < M; k0 += 4) {
+        const int k = k0 + (l >> 4);
+        double av = 0.0, bv = 0.0;
+        if (k < M) {
+          av = ia < rn ? sA[pa * LDK + k] : 0.0;
+          bv = jb < rn ? sQ[jb * MMAX + k] : 0.0;
+        }
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v + (l >> 4);
+        if (i < rn && jb < rn) {
+          const double g = d[v] / sd[perm[i]];
+          st->C[jb * RMAX + i] = g;
+          st->At[jb * RMAX + i] = g / sgn[jb];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int tile = wv + 16 * h;
+    if (tile < NRT) {
+      const int c0 = 16 * (tile >> 2), k0 = 16 * (tile & 3);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cr = c0 + 4 * v + (l >> 4);
+        if (cr >= CMAX) continue;
+        const int idx = cr * RMAX + k0 + (l & 15);
+        tst->Q[idx] = rt[h][v];
+        if (c.basis_f32) tst->Q32[idx] = (float)rt[h][v];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    tst->m = mTe + 1;
+    tst->r = rn;
+    tst->refold = mTe + 1 >= c.ct;   // no free T column for the next y
+  }
+}
+
 __device__ __forceinline__ void core_update(const CoreArgs& c) {
   DevState* __restrict__ st = c.st;
   __shared__ double sA[MMAX * LDK];
@@ -444,7 +571,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __shared__ double p2[RMAX], pyr[RMAX], pyn[RMAX], wn[RMAX], sgn[RMAX], ssig[RMAX], pvec[RMAX];
   __shared__ SecShared sec;
   __shared__ double sC[RMAX * RMAX];
-  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX];
+  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX], qB[RMAX];
   __shared__ int perm[MMAX + 1];
   __shared__ int flag;
   __shared__ double sc[8];
@@ -545,7 +672,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
           isfinite(py2))) {
       skip = ST_NONFINITE;
-    } else if (st->m_acc > 0 && xx != st->yy_prev) {
+    } else if (!c.tst && st->m_acc > 0 && xx != st->yy_prev) {
       skip = ST_SEQ;
     }
     double rho = sqrt(fmax(ee - pp, 0.0));
@@ -571,11 +698,26 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       }
       if (tid < CMAX) st->a[tid] = tid < r ? st->py[tid] : 0.0;
     }
+    // Likewise for B = T R after a refolding T sweep: R = I, r columns.
+    if (c.tst && c.tst->refold) {
+      DevState* __restrict__ tst = c.tst;
+      for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
+        const int c0 = idx / RMAX, j = idx % RMAX;
+        const double v = (c0 == j && j < r) ? 1.0 : 0.0;
+        tst->Q[idx] = v;
+        if (c.basis_f32) tst->Q32[idx] = (float)v;
+      }
+    }
+    __syncthreads();
     if (tid == 0) {
       st->status |= skip;
       if (refolded) {
         st->m = r;
         st->refold = 0;
+      }
+      if (c.tst && c.tst->refold) {
+        c.tst->m = r;
+        c.tst->refold = 0;
       }
     }
     return;
@@ -583,13 +725,21 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int grow = si[1];
   const double rho = sc[0], qy = sc[1];
 
-  // 4. core K = [[diag(sigma), p], [0, rho]], p = p1 + p2 with p1 = cached p_y
+  // 4. core K = [[diag(sigma), p], [0, rho]], p = p1 + p2 with p1 the
+  //    cached p_y (chained pairs) or U^T x from the projection sweep
   const int M = r + 1;
   if (tid < r) {
     ssig[tid] = st->sigma[tid];
-    pvec[tid] = st->py[tid] + p2[tid];
+    pvec[tid] = (c.tst ? st->p1[tid] : st->py[tid]) + p2[tid];
   }
   __syncthreads();
+  // general pairs: q^T B = (x^T B - p^T G) / rho with G = U^T B (in sC,
+  // G(i, j) at sC[j * RMAX + i]); zero when no direction is added
+  if (c.tst && tid < r) {
+    double t = 0.0;
+    for (int i = 0; i < r; ++i) t += pvec[i] * sC[tid * RMAX + i];
+    qB[tid] = si[1] ? (st->xB[tid] - t) / sc[0] : 0.0;
+  }
 
   // 5. SVD of the core: secular equation, one-sided Jacobi if that fails
   int sweeps = 0;
@@ -627,6 +777,11 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int rn = min(above, c.r_max);
   if (rn == 0) {   // nothing kept (zero snapshots so far)
     if (tid < CMAX) st->a[tid] = 0.0;
+    if (tid == 0 && c.tst) {
+      c.tst->m = 0;
+      c.tst->r = 0;
+      c.tst->refold = 0;
+    }
     if (tid == 0) {
       st->r = 0;
       st->m = 0;
@@ -762,6 +917,9 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
 
+  if (c.tst) {
+    general_tail(c, r, rn, M, qy, sA, sV, sC, sQ, sd, sgn, pyr, qB, perm);
+  } else {
   // 9. T = E V_k[:, kept] with E = [[C, 0], [w^T, 0]] (M x r, the zero
   //    last column dropped), on the matrix cores: 16 x 16 tiles of T, K = r,
   //    written into sA (U_k is no longer read)
@@ -820,6 +978,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       }
     }
   }
+  }
   if (tid < rn) {
     st->sigma[tid] = sgn[tid];
     st->w[tid] = wn[tid];
@@ -863,6 +1022,64 @@ hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s) {
 
 hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   hipExtLaunchKernelGGL(k_core, dim3(1), dim3(CORE_THREADS), 0, s, e0, e1, 0, c);
+  return hipGetLastError();
+}
+
+// General pairs, before the streaming pass: p1 = U^T x = Q^T S^T x,
+// a = Q p1 (the pass's first-projection coefficients) and xB = x^T B =
+// R^T T^T x, from the projection sweep's and the T sweep's per-workgroup
+// records (fixed-order sums, as in the small-state kernel).
+__global__ __launch_bounds__(CORE_THREADS) void k_coef(CoefArgs c) {
+  DevState* __restrict__ st = c.st;
+  const DevState* __restrict__ tst = c.tst;
+  constexpr int NI = 2 * CMAX;               // S^T x (CMAX) then T^T x (CMAX)
+  constexpr int NSL = CORE_THREADS / NI;     // partial-sum slots per item
+  __shared__ double part[NSL][NI];
+  __shared__ double v[NI];
+  __shared__ double p1[RMAX];
+  const int tid = threadIdx.x;
+  const int r = st->r, m = st->m, mT = tst->m;
+  if (tid < NSL * NI) {
+    const int it = tid % NI, sl = tid / NI;
+    double t = 0.0;
+    if (it < CMAX) {
+      if (it < m)
+        for (int b = sl; b < c.nblk; b += NSL) t += c.pproj[(int64_t)b * PW + it];
+    } else {
+      const int k = it - CMAX;               // second record half: T^T x
+      if (k < mT)
+        for (int b = sl; b < c.nblk; b += NSL) t += c.pt[(int64_t)b * PW + c.rbt + k];
+    }
+    part[sl][it] = t;
+  }
+  __syncthreads();
+  if (tid < NI) {
+    double t = 0.0;
+    for (int sl = 0; sl < NSL; ++sl) t += part[sl][tid];
+    v[tid] = t;
+  }
+  __syncthreads();
+  if (tid < RMAX) {
+    double a1 = 0.0, b1 = 0.0;
+    if (tid < r) {
+      for (int c0 = 0; c0 < m; ++c0) a1 += st->Q[c0 * RMAX + tid] * v[c0];
+      for (int c0 = 0; c0 < mT; ++c0) b1 += tst->Q[c0 * RMAX + tid] * v[CMAX + c0];
+    }
+    p1[tid] = a1;
+    st->p1[tid] = a1;
+    st->xB[tid] = b1;
+  }
+  __syncthreads();
+  if (tid < CMAX) {
+    double t = 0.0;
+    if (tid < m)
+      for (int j = 0; j < r; ++j) t += st->Q[tid * RMAX + j] * p1[j];
+    st->a[tid] = t;
+  }
+}
+
+hipError_t launch_coef(const CoefArgs& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_coef, dim3(1), dim3(CORE_THREADS), 0, s, c);
   return hipGetLastError();
 }
 

@@ -39,6 +39,13 @@ struct odmd_s {
   DevState* st = nullptr;
   double* partials = nullptr;
   void* Us = nullptr;
+  // general pairs: B = Y W held as T R (stored y columns T, R in tst->Q),
+  // records of the projection sweep and of the T sweep
+  bool general = false;
+  DevState* tst = nullptr;
+  void* Ts = nullptr;
+  double* pproj = nullptr;
+  double* pt = nullptr;
   int nblk = 0;
   int64_t units = 0;
   bool prof = false;
@@ -57,6 +64,7 @@ namespace {
 
 struct Layout {
   size_t st = 0, partials = 0, Us = 0, total = 0;
+  size_t tst = 0, pproj = 0, pt = 0, Ts = 0;   // general pairs only
   int64_t ntiles = 0, units = 0;
   int nblk = 0, ct = 0;
 };
@@ -82,7 +90,7 @@ int col_bucket(int cols) { return (cols + 7) / 8 * 8; }
 
 // Stored basis: 64-row tiles, column-major inside a tile, fold_capacity(r_max)
 // columns per tile.
-Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis) {
+Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis, bool general = false) {
   Layout L;
   L.ct = fold_capacity(r_max);
   L.ntiles = (n + 63) / 64;
@@ -95,6 +103,16 @@ Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis) {
   off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
   L.Us = off;
   off += round_up(L.ntiles * L.ct * 64 * elem_bytes(basis), 256);
+  if (general) {
+    L.tst = off;
+    off += round_up(sizeof(DevState), 256);
+    L.pproj = off;
+    off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
+    L.pt = off;
+    off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
+    L.Ts = off;
+    off += round_up(L.ntiles * L.ct * 64 * elem_bytes(basis), 256);
+  }
   L.total = off;
   return L;
 }
@@ -169,6 +187,30 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.nblk = h->nblk;
   p.ct = h->ct;
   const int kb = live_bucket(h);
+  if (h->general) {
+    // U^T x from a projection sweep, then the T sweep (appends y to T,
+    // refolding T when it is full; its records carry T^T x), then the
+    // coefficients of the streaming pass
+    PassArgs pp = p;
+    pp.partials = h->pproj;
+    HIP_OK(launch_proj(pp, (int)h->basis, kb, h->stream));
+    PassArgs pt = p;
+    pt.Us = h->Ts;
+    pt.x = y;
+    pt.y = x;
+    pt.partials = h->pt;
+    pt.st = h->tst;
+    HIP_OK(launch_pass(pt, (int)h->basis, h->ct, h->stream));
+    CoefArgs ca;
+    ca.st = h->st;
+    ca.tst = h->tst;
+    ca.pproj = h->pproj;
+    ca.pt = h->pt;
+    ca.nblk = h->nblk;
+    ca.rb = kb;
+    ca.rbt = h->ct;
+    HIP_OK(launch_coef(ca, h->stream));
+  }
   HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
   CoreArgs c;
@@ -182,6 +224,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.ct = h->ct;
   c.fb = h->fb_dev;
   c.seq = h->seq;
+  c.tst = h->general ? h->tst : nullptr;
   HIP_OK(launch_core(c, h->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
   return ODMD_OK;
 }
@@ -360,12 +403,18 @@ size_t odmd_state_bytes(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype i
   return make_layout(n, r_max, basis).total;
 }
 
-odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dtype io,
-                           void* hip_stream, void* workspace, size_t workspace_bytes, odmd_t* h) {
+size_t odmd_state_bytes_general(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io) {
+  if (!valid_args(n, r_max, 0.0, basis, io)) return 0;
+  return make_layout(n, r_max, basis, true).total;
+}
+
+static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
+                               odmd_dtype io, void* hip_stream, void* workspace,
+                               size_t workspace_bytes, bool general, odmd_t* h) {
   if (!h) return ODMD_EINVAL;
   *h = nullptr;
   if (!valid_args(n, r_max, tol, basis, io)) return ODMD_EINVAL;
-  const Layout L = make_layout(n, r_max, basis);
+  const Layout L = make_layout(n, r_max, basis, general);
   if (workspace) {
     if (workspace_bytes < L.total) return ODMD_ENOMEM;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return ODMD_EINVAL;
@@ -420,9 +469,19 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   s->st = reinterpret_cast<DevState*>(s->mem + L.st);
   s->partials = reinterpret_cast<double*>(s->mem + L.partials);
   s->Us = s->mem + L.Us;
+  s->general = general;
+  if (general) {
+    s->tst = reinterpret_cast<DevState*>(s->mem + L.tst);
+    s->pproj = reinterpret_cast<double*>(s->mem + L.pproj);
+    s->pt = reinterpret_cast<double*>(s->mem + L.pt);
+    s->Ts = s->mem + L.Ts;
+  }
   const double tol_eff = s->tol_eff;
+  const int gflag = general ? 1 : 0;
   if (hipMemsetAsync(s->mem, 0, L.total, s->stream) != hipSuccess ||
       hipMemcpyAsync(&s->st->tol, &tol_eff, sizeof(double), hipMemcpyHostToDevice, s->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(&s->st->general, &gflag, sizeof(int), hipMemcpyHostToDevice, s->stream) !=
           hipSuccess ||
       hipStreamSynchronize(s->stream) != hipSuccess) {
     (void)hipGetLastError();
@@ -433,6 +492,17 @@ odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basi
   }
   *h = s;
   return ODMD_OK;
+}
+
+odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dtype io,
+                           void* hip_stream, void* workspace, size_t workspace_bytes, odmd_t* h) {
+  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes, false, h);
+}
+
+odmd_status odmd_create_general(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
+                                odmd_dtype io, void* hip_stream, void* workspace,
+                                size_t workspace_bytes, odmd_t* h) {
+  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes, true, h);
 }
 
 odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h) {
@@ -451,7 +521,7 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
   if (count == 0) return ODMD_OK;
   std::unordered_set<odmd_t> seen;
   for (int32_t i = 0; i < count; ++i) {
-    if (!hs[i] || !xs[i] || !ys[i]) return ODMD_EINVAL;
+    if (!hs[i] || !xs[i] || !ys[i] || hs[i]->general) return ODMD_EINVAL;
     if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return ODMD_EINVAL;
     if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
   }

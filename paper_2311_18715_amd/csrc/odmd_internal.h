@@ -61,7 +61,7 @@ struct DevState {
   int r;          // logical rank
   int m;          // stored columns in use (U = S[:, :m] Q), r <= m
   int refold;     // the next pass rewrites S[:, :r] = S Q (no free column left)
-  int pad0_;
+  int general;    // general pairs: B = Y W kept as B = T R (second state)
   int status;     // latched error bits
   int sweeps;     // Jacobi sweeps of the last core SVD
   int eig_valid;  // eigen cache belongs to the current model
@@ -75,10 +75,13 @@ struct DevState {
   double sigma[RMAX];
   double w[RMAX];
   double py[RMAX];      // U^T y_last: cached projection of the next x
-  double a[CMAX];       // Q p_y: coefficients of the next pass's first projection
-  double Q[RMAX * CMAX];      // m x r, column j at Q + j*CMAX
+  double a[CMAX];       // Q p1: coefficients of the next pass's first projection
+  double p1[RMAX];      // U^T x of a general pair (chained pairs use py)
+  double xB[RMAX];      // x^T B of a general pair
+  double Q[RMAX * CMAX];      // m x r, row c (stored column c) at Q + c*RMAX
   float Q32[RMAX * CMAX];     // FP32 copy for FP32 storage
-  double C[RMAX * RMAX];      // r x r shifted product W[2:]^T W[:-1]
+  double C[RMAX * RMAX];      // r x r: shifted product W[2:]^T W[:-1] (chained
+                              // pairs) or G = U^T B (general pairs)
   double At[RMAX * RMAX];     // A~ (r x r)
   // eigen cache
   double lam_re[RMAX], lam_im[RMAX];

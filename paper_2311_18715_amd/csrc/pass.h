@@ -24,6 +24,9 @@ struct PassArgs {
 // that take the kernel's own start and end timestamps.
 hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s,
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Projection-only sweep of a general pair (same records with e = x: S^T x,
+// S^T y, x.x, x.y, x.x, y.y; stores nothing, never refolds).
+hipError_t launch_proj(const PassArgs& p, int basis, int rb, hipStream_t s);
 
 // One stream of a batched pass launch (device-resident table, sorted by blk0).
 struct PassDesc {
@@ -51,7 +54,22 @@ struct CoreArgs {
   int ct;               // stored-column capacity of the stream
   unsigned* fb;         // host-visible word: (seq << 8) | stored columns after this update
   unsigned seq;         // update sequence number (24 bits) of this launch
+  DevState* tst;        // general pairs: state of B = T R (R in its Q), else null
 };
+
+// General pairs, between the two sweeps and the streaming pass: reduces the
+// projection records (S^T x) and the T sweep's records (T^T x), and sets
+// p1 = U^T x = Q^T S^T x, the pass coefficients a = Q p1 and xB = R^T T^T x.
+struct CoefArgs {
+  DevState* st;
+  const DevState* tst;
+  const double* pproj;  // projection records (compact, 2 rb + 4 per workgroup)
+  const double* pt;     // T sweep records (compact, 2 ct + 4 per workgroup)
+  int nblk;
+  int rb;               // bucket of the projection sweep
+  int rbt;              // bucket of the T sweep
+};
+hipError_t launch_coef(const CoefArgs& c, hipStream_t s);
 hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0 = nullptr,
                        hipEvent_t e1 = nullptr);
 // one workgroup per entry of a device-resident CoreArgs table

@@ -14,6 +14,9 @@
 //     p2 = U^T e = Q^T S^T e and U^T y (CGS2);
 //   * on a refold pass (no free column left), S[:, :r] <- S Q in place on the
 //     matrix cores, with e then stored as column r.
+// For general (unchained) pairs the same sweep also serves as the projection
+// of x (k_proj: e = x, nothing stored) and, run on the stored columns T of
+// B = Y W = T R with zero coefficients, appends y to T.
 //
 // Layout and mapping (CDNA4): S is stored in tiles of 64 rows, each tile
 // column-major (element (i, c) at ((i/64)*ct + c)*64 + i%64), so one column of
@@ -63,7 +66,9 @@ template <> struct Mfma<float> {
   __device__ static int dsub(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-template <typename TS, typename TIO, int RB>
+// PROJ: projection-only sweep of a general pair (e = x: the sums S^T x,
+// S^T y, x.x, x.y; nothing is stored and no refold happens)
+template <typename TS, typename TIO, int RB, bool PROJ = false>
 __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr int UR = 16;                  // rows per unit
   constexpr int UPT = 64 / UR;            // units per 64-row tile
@@ -75,7 +80,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   typedef typename Mfma<TC>::acc_t acc_t;
 
   const DevState* __restrict__ st = p.st;
-  const int m = st->m, r = st->r, refold = st->refold;
+  const int m = st->m, r = st->r, refold = PROJ ? 0 : st->refold;
   const int slot = refold ? r : m;        // the column that receives e
   TS* __restrict__ Us = static_cast<TS*>(p.Us);
   const TIO* __restrict__ X = static_cast<const TIO*>(p.x);
@@ -162,15 +167,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     if (row >= p.n) xv = yv = 0.0;
 
     // e = x - S a, in FP64, stored as column `slot`
-    double s = 0.0;
+    double ed = xv;
+    if constexpr (!PROJ) {
+      double s = 0.0;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) s = __builtin_fma(SC::to_double(A[kk]), sa[4 * kk + q], s);
-    s = add_half_pair(add_row_pair(s));
-    const TS es = SC::from_double(xv - s);
-    const double ed = SC::to_double(es);    // the stored value, which the sums see
-    // a non-finite residual (rejected by the small-state kernel, which sees
-    // it in the sums below) is stored as zero: stored columns stay finite
-    if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(ed) ? es : SC::from_double(0.0);
+      for (int kk = 0; kk < KK; ++kk) s = __builtin_fma(SC::to_double(A[kk]), sa[4 * kk + q], s);
+      s = add_half_pair(add_row_pair(s));
+      const TS es = SC::from_double(xv - s);
+      ed = SC::to_double(es);    // the stored value, which the sums see
+      // a non-finite residual (rejected by the small-state kernel, which
+      // sees it in the sums below) is stored as zero: stored columns stay
+      // finite
+      if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(ed) ? es : SC::from_double(0.0);
+    }
 
     // projections, accumulated in-lane
 #pragma unroll
@@ -256,6 +265,11 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
   pass_body<TS, TIO, RB>(p, blockIdx.x);
 }
 
+template <typename TS, typename TIO, int RB>
+__global__ __launch_bounds__(PASS_THREADS) void k_proj(PassArgs p) {
+  pass_body<TS, TIO, RB, true>(p, blockIdx.x);
+}
+
 // Many streams of one storage type and live-column bucket in one launch: workgroup b
 // belongs to the stream whose block range [blk0, blk0 + nblk) contains b, and
 // runs exactly the work that workgroup b - blk0 of that stream's own launch
@@ -312,33 +326,48 @@ hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis, 
   return hipErrorInvalidValue;
 }
 
-template <typename TS, typename TIO>
-static hipError_t launch_rb(const PassArgs& p, int rb, hipStream_t s, hipEvent_t e0,
-                            hipEvent_t e1) {
+template <typename TS, typename TIO, int RB>
+static void launch_one(const PassArgs& p, bool proj, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid(p.nblk), block(PASS_THREADS);
+  if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB>), grid, block, 0, s, e0, e1, 0, p);
+  else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB>), grid, block, 0, s, e0, e1, 0, p);
+}
+
+template <typename TS, typename TIO>
+static hipError_t launch_rb(const PassArgs& p, int rb, bool proj, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
   switch (rb) {
-    case 8: hipExtLaunchKernelGGL((k_pass<TS, TIO, 8>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 16: hipExtLaunchKernelGGL((k_pass<TS, TIO, 16>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 24: hipExtLaunchKernelGGL((k_pass<TS, TIO, 24>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 32: hipExtLaunchKernelGGL((k_pass<TS, TIO, 32>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 40: hipExtLaunchKernelGGL((k_pass<TS, TIO, 40>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 48: hipExtLaunchKernelGGL((k_pass<TS, TIO, 48>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 56: hipExtLaunchKernelGGL((k_pass<TS, TIO, 56>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 64: hipExtLaunchKernelGGL((k_pass<TS, TIO, 64>), grid, block, 0, s, e0, e1, 0, p); break;
-    case 72: hipExtLaunchKernelGGL((k_pass<TS, TIO, 72>), grid, block, 0, s, e0, e1, 0, p); break;
+    case 8: launch_one<TS, TIO, 8>(p, proj, s, e0, e1); break;
+    case 16: launch_one<TS, TIO, 16>(p, proj, s, e0, e1); break;
+    case 24: launch_one<TS, TIO, 24>(p, proj, s, e0, e1); break;
+    case 32: launch_one<TS, TIO, 32>(p, proj, s, e0, e1); break;
+    case 40: launch_one<TS, TIO, 40>(p, proj, s, e0, e1); break;
+    case 48: launch_one<TS, TIO, 48>(p, proj, s, e0, e1); break;
+    case 56: launch_one<TS, TIO, 56>(p, proj, s, e0, e1); break;
+    case 64: launch_one<TS, TIO, 64>(p, proj, s, e0, e1); break;
+    case 72: launch_one<TS, TIO, 72>(p, proj, s, e0, e1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s, hipEvent_t e0,
-                       hipEvent_t e1) {
+static hipError_t launch_any(const PassArgs& p, int basis, int rb, bool proj, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
   switch (basis) {
-    case 0: return launch_rb<double, double>(p, rb, s, e0, e1);
-    case 1: return launch_rb<float, float>(p, rb, s, e0, e1);
-    case 2: return launch_rb<bf16, float>(p, rb, s, e0, e1);
+    case 0: return launch_rb<double, double>(p, rb, proj, s, e0, e1);
+    case 1: return launch_rb<float, float>(p, rb, proj, s, e0, e1);
+    case 2: return launch_rb<bf16, float>(p, rb, proj, s, e0, e1);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass(const PassArgs& p, int basis, int rb, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1) {
+  return launch_any(p, basis, rb, false, s, e0, e1);
+}
+
+hipError_t launch_proj(const PassArgs& p, int basis, int rb, hipStream_t s) {
+  return launch_any(p, basis, rb, true, s, nullptr, nullptr);
 }
 
 }  // namespace odmd

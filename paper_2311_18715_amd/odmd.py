@@ -24,7 +24,7 @@ EXPORTS = [
     "odmd_create", "odmd_create_ex", "odmd_state_bytes", "odmd_update", "odmd_update_batch",
     "odmd_eigs", "odmd_predict", "odmd_predict_batch", "odmd_sync", "odmd_destroy", "odmd_status_str",
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
-    "odmd_profile_samples",
+    "odmd_profile_samples", "odmd_create_general", "odmd_state_bytes_general",
 ]
 
 
@@ -60,6 +60,9 @@ def lib() -> ctypes.CDLL:
             "odmd_create_ex": ([i64, i32, dbl, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_size_t,
                                 ctypes.POINTER(vp)], ctypes.c_int),
             "odmd_state_bytes": ([i64, i32, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+            "odmd_create_general": ([i64, i32, dbl, ctypes.c_int, ctypes.c_int, vp, vp,
+                                     ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
+            "odmd_state_bytes_general": ([i64, i32, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
             "odmd_update": ([vp, vp, vp], ctypes.c_int),
             "odmd_update_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32],
                                   ctypes.c_int),
@@ -105,13 +108,15 @@ class ODMD:
     """One online-DMD stream on the GPU (a handle of the C library).
 
     Parameters mirror ``odmd_create_ex``: state size n, rank cap r_max,
-    relative tolerance tol, basis storage ('f64' | 'f32'), snapshot type
-    (defaults to the basis type), torch stream (defaults to the current
-    one) and an optional caller-owned uint8 device workspace.
+    relative tolerance tol, basis storage ('f64' | 'f32' | 'bf16'),
+    snapshot type (defaults to the basis type, FP32 for BF16), torch stream
+    (defaults to the current one) and an optional caller-owned uint8 device
+    workspace.  pairs='general' creates a handle for pairs that need not
+    chain (``odmd_create_general``).
     """
 
     def __init__(self, n: int, r_max: int, tol: float, basis: str = "f64", io: str | None = None,
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, pairs: str = "chained"):
         import torch
         self._torch = torch
         io = io or ("f32" if basis == "bf16" else basis)     # a BF16 basis takes FP32 snapshots
@@ -126,18 +131,24 @@ class ODMD:
         ws, wsb = None, 0
         if workspace is not None:
             ws, wsb = _dptr(workspace), workspace.numel() * workspace.element_size()
-        _check(lib().odmd_create_ex(self.n, self.r_max, float(tol), bt, it,
+        if pairs not in ("chained", "general"):
+            raise ValueError("pairs must be 'chained' or 'general'")
+        self.pairs = pairs
+        name = "odmd_create_ex" if pairs == "chained" else "odmd_create_general"
+        _check(getattr(lib(), name)(self.n, self.r_max, float(tol), bt, it,
                                     ctypes.c_void_p(stream.cuda_stream), ws, wsb,
-                                    ctypes.byref(h)), "odmd_create_ex")
+                                    ctypes.byref(h)), name)
         self._h = h
         self._workspace = workspace
 
     @staticmethod
-    def state_bytes(n: int, r_max: int, basis: str = "f64", io: str | None = None) -> int:
+    def state_bytes(n: int, r_max: int, basis: str = "f64", io: str | None = None,
+                    pairs: str = "chained") -> int:
         io = io or ("f32" if basis == "bf16" else basis)
         bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
         it = {"f64": F64, "f32": F32}[io]
-        return int(lib().odmd_state_bytes(int(n), int(r_max), bt, it))
+        fn = lib().odmd_state_bytes if pairs == "chained" else lib().odmd_state_bytes_general
+        return int(fn(int(n), int(r_max), bt, it))
 
     @property
     def handle(self) -> ctypes.c_void_p:

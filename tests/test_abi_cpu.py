@@ -51,6 +51,21 @@ def test_state_bytes_is_host_only():
     assert L.odmd_state_bytes(100, 8, B.F64, B.F32) == 0        # io must match basis
     assert L.odmd_state_bytes(100, 8, B.BF16, B.F32) > 0        # BF16 basis, FP32 snapshots
     assert L.odmd_state_bytes(100, 8, B.BF16, B.BF16) == 0      # BF16 snapshots are not offered
+    # general pairs: a second stored-column set (B = T R), its state and records
+    g64 = L.odmd_state_bytes_general(160000, 40, B.F64, B.F64)
+    assert g64 - n64 >= 160000 * 56 * 8
+    assert L.odmd_state_bytes_general(100, 65, B.F64, B.F64) == 0
+    assert L.odmd_state_bytes_general(100, 8, B.BF16, B.F32) > L.odmd_state_bytes(100, 8, B.BF16, B.F32)
+
+
+@needs_lib
+def test_create_general_rejects_bad_arguments():
+    L = B.lib()
+    h = ctypes.c_void_p(12345)
+    assert L.odmd_create_general(100, 65, 1e-8, B.F64, B.F64, None, None, 0, ctypes.byref(h)) == 1
+    assert h.value is None
+    assert L.odmd_create_general(100, 4, 1e-8, B.F64, B.F32, None, None, 0, ctypes.byref(h)) == 1
+    assert L.odmd_create_general(100, 4, 1e-8, B.F64, B.F64, None, None, 0, None) == 1
 
 
 @needs_lib
