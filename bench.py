@@ -72,9 +72,14 @@ def measured_traffic():
     return int(m_bytes.group(1))
 
 
-def cpu_baseline(X, seconds: float = 15.0):
+def cpu_baseline(X, seconds: float = 15.0, threads_limit=None):
     """The FP64 oracle on this host: warm up to the saturated rank, then time
-    as many updates as fit in about `seconds` (at least 5)."""
+    as many updates as fit in about `seconds` (at least 5).  threads_limit
+    caps the BLAS threads (None: the library's default)."""
+    if threads_limit is not None:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=threads_limit):
+            return cpu_baseline(X, seconds)
     from oracle import odmd_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -101,6 +106,28 @@ def cpu_baseline(X, seconds: float = 15.0):
 # (ii) S independent n = 160k streams through the batched update
 CONC_S = (8, 32, 128)
 CONC_WARM, CONC_STEPS, CONC_OFFSET = 100, 200, 7
+
+
+def copy_baseline(torch, mib: int = 1024, reps: int = 20):
+    """Device-to-device copy of `mib` MiB (torch's copy kernel), read +
+    written bytes over the median event time: the bandwidth a plain
+    streaming kernel reaches on this GPU, beside the 8 TB/s peak."""
+    a = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    t = float(np.median(times))
+    res = {"bytes": 2 * a.numel() * 8, "median_us": round(t * 1e6, 1),
+           "gbps": round(2 * a.numel() * 8 / t / 1e9, 1)}
+    del a, b
+    torch.cuda.empty_cache()
+    return res
 
 
 def general_pairs(torch, Xd, bytes_upd):
@@ -569,6 +596,7 @@ def main():
     if not args.no_extra:
         del models
         torch.cuda.empty_cache()
+        result["hbm_copy_baseline"] = copy_baseline(torch)
         result["general_pairs_n160k"] = general_pairs(torch, Xd, bytes_upd)
         torch.cuda.empty_cache()
         result["concurrent_n160k"] = concurrent_streams(torch, Xd, bytes_upd)
@@ -588,6 +616,7 @@ def main():
         result["calibration_copy_bytes"] = 2 * a.numel() * 8
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(X)
+        result["cpu_baseline_1thread"] = cpu_baseline(X, seconds=8.0, threads_limit=1)
     print(json.dumps(result), flush=True)
 
 

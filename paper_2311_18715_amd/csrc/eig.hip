@@ -179,13 +179,16 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   // 2. Francis double-shift QR to real Schur form
   int hi = n - 1, its = 0, total = 0;
   while (hi >= 0) {
-    int l = hi;
-    while (l > 0) {
-      double s = fabs(Hm(l - 1, l - 1)) + fabs(Hm(l, l));
+    // l = the largest index in [1, hi] whose subdiagonal entry is
+    // negligible, else 0: every lane tests one entry, one ballot
+    bool neg = false;
+    if (t >= 1 && t <= hi) {
+      double s = fabs(Hm(t - 1, t - 1)) + fabs(Hm(t, t));
       if (s == 0.0) s = hn;
-      if (fabs(Hm(l, l - 1)) <= EPS * s) break;
-      --l;
+      neg = fabs(Hm(t, t - 1)) <= EPS * s;
     }
+    const unsigned long long mask = __ballot(neg);
+    const int l = mask ? 63 - __builtin_clzll(mask) : 0;
     __syncthreads();
     if (l > 0 && t == 0) Hm(l, l - 1) = 0.0;
     __syncthreads();

@@ -176,7 +176,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
     ev = &h->ev[h->ev_used];
     h->ev_used += EV_PER_UPDATE;
   }
-  PassArgs p;
+  PassArgs p{};
   p.Us = h->Us;
   p.x = x;
   p.y = y;
@@ -201,7 +201,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
     pt.partials = h->pt;
     pt.st = h->tst;
     HIP_OK(launch_pass(pt, (int)h->basis, h->ct, h->stream));
-    CoefArgs ca;
+    CoefArgs ca{};
     ca.st = h->st;
     ca.tst = h->tst;
     ca.pproj = h->pproj;
@@ -213,7 +213,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   }
   HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
-  CoreArgs c;
+  CoreArgs c{};
   c.st = h->st;
   c.partials = h->partials;
   c.nblk = h->nblk;
@@ -307,6 +307,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     for (int32_t i : g.second) {
       odmd_t h = hs[i];
       PassDesc& d = pd[k++];
+      d = PassDesc{};
       d.Us = h->Us;
       d.x = xs[i];
       d.y = ys[i];
@@ -324,6 +325,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   for (int32_t i = 0; i < count; ++i) {
     odmd_t h = hs[i];
     CoreArgs& c = cd[i];
+    c = CoreArgs{};   // every field set below or zero (tst: chained handles only here)
     c.st = h->st;
     c.partials = h->partials;
     c.nblk = h->nblk;
@@ -350,7 +352,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
 }
 
 odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool out_f32) {
-  CombineArgs c;
+  CombineArgs c{};
   c.st = h->st;
   c.Us = h->Us;
   c.out = out;

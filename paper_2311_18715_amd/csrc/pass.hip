@@ -285,7 +285,7 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass_batch(const PassDesc* __r
     if (D[mid].blk0 <= b) lo = mid;
     else hi = mid - 1;
   }
-  PassArgs p;
+  PassArgs p{};
   p.Us = D[lo].Us;
   p.x = D[lo].x;
   p.y = D[lo].y;
