@@ -571,7 +571,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __shared__ double p2[RMAX], pyr[RMAX], pyn[RMAX], wn[RMAX], sgn[RMAX], ssig[RMAX], pvec[RMAX];
   __shared__ SecShared sec;
   __shared__ double sC[RMAX * RMAX];
-  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX], qB[RMAX];
+  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX], qB[RMAX], eB[RMAX];
   __shared__ int perm[MMAX + 1];
   __shared__ int flag;
   __shared__ double sc[8];
@@ -634,6 +634,36 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       const int rb = c.rb;
       const int at = tid < rb ? P_SUE + tid : (tid < 2 * rb ? P_SUY + (tid - rb) : P_EE + (tid - 2 * rb));
       tot[at] = t;
+    }
+    __syncthreads();
+  }
+
+  // general pairs: e^T B = R^T T^T e from the T sweep's records (second
+  // half, fixed-order sums; R and the T columns as that sweep read them)
+  if (c.tst) {
+    const DevState* __restrict__ tst = c.tst;
+    const int mT = tst->m;
+    constexpr int NSL = CORE_THREADS / CMAX;
+    double* part = sV;                       // scratch, as in step 1
+    if (tid < NSL * CMAX) {
+      const int it = tid % CMAX, sl = tid / CMAX;
+      double t = 0.0;
+      if (it < mT)
+        for (int b = sl; b < c.nblk; b += NSL) t += c.pt[(int64_t)b * PW + c.rbt + it];
+      part[sl * CMAX + it] = t;
+    }
+    __syncthreads();
+    if (tid < CMAX) {
+      double t = 0.0;
+      for (int sl = 0; sl < NSL; ++sl) t += part[sl * CMAX + tid];
+      red[tid] = t;
+    }
+    __syncthreads();
+    if (tid < RMAX) {
+      double t = 0.0;
+      if (tid < r)
+        for (int c0 = 0; c0 < mT; ++c0) t += tst->Q[c0 * RMAX + tid] * red[c0];
+      eB[tid] = t;
     }
     __syncthreads();
   }
@@ -733,12 +763,14 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     pvec[tid] = (c.tst ? st->p1[tid] : st->py[tid]) + p2[tid];
   }
   __syncthreads();
-  // general pairs: q^T B = (x^T B - p^T G) / rho with G = U^T B (in sC,
-  // G(i, j) at sC[j * RMAX + i]); zero when no direction is added
+  // general pairs: q^T B = (e^T B - p2^T G) / rho with G = U^T B (in sC,
+  // G(i, j) at sC[j * RMAX + i]), from the stored residual e = x - U p1
+  // itself (no cancellation between x^T B and p^T G); zero when no
+  // direction is added
   if (c.tst && tid < r) {
     double t = 0.0;
-    for (int i = 0; i < r; ++i) t += pvec[i] * sC[tid * RMAX + i];
-    qB[tid] = si[1] ? (st->xB[tid] - t) / sc[0] : 0.0;
+    for (int i = 0; i < r; ++i) t += p2[i] * sC[tid * RMAX + i];
+    qB[tid] = si[1] ? (eB[tid] - t) / sc[0] : 0.0;
   }
 
   // 5. SVD of the core: secular equation, one-sided Jacobi if that fails
@@ -1025,49 +1057,37 @@ hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0, hipEvent
   return hipGetLastError();
 }
 
-// General pairs, before the streaming pass: p1 = U^T x = Q^T S^T x,
-// a = Q p1 (the pass's first-projection coefficients) and xB = x^T B =
-// R^T T^T x, from the projection sweep's and the T sweep's per-workgroup
+// General pairs, before the streaming pass: p1 = U^T x = Q^T S^T x and the
+// pass coefficients a = Q p1, from the projection sweep's per-workgroup
 // records (fixed-order sums, as in the small-state kernel).
 __global__ __launch_bounds__(CORE_THREADS) void k_coef(CoefArgs c) {
   DevState* __restrict__ st = c.st;
-  const DevState* __restrict__ tst = c.tst;
-  constexpr int NI = 2 * CMAX;               // S^T x (CMAX) then T^T x (CMAX)
-  constexpr int NSL = CORE_THREADS / NI;     // partial-sum slots per item
-  __shared__ double part[NSL][NI];
-  __shared__ double v[NI];
+  constexpr int NSL = CORE_THREADS / CMAX;   // partial-sum slots per column
+  __shared__ double part[NSL][CMAX];
+  __shared__ double v[CMAX];
   __shared__ double p1[RMAX];
   const int tid = threadIdx.x;
-  const int r = st->r, m = st->m, mT = tst->m;
-  if (tid < NSL * NI) {
-    const int it = tid % NI, sl = tid / NI;
+  const int r = st->r, m = st->m;
+  if (tid < NSL * CMAX) {
+    const int it = tid % CMAX, sl = tid / CMAX;
     double t = 0.0;
-    if (it < CMAX) {
-      if (it < m)
-        for (int b = sl; b < c.nblk; b += NSL) t += c.pproj[(int64_t)b * PW + it];
-    } else {
-      const int k = it - CMAX;               // second record half: T^T x
-      if (k < mT)
-        for (int b = sl; b < c.nblk; b += NSL) t += c.pt[(int64_t)b * PW + c.rbt + k];
-    }
+    if (it < m)
+      for (int b = sl; b < c.nblk; b += NSL) t += c.pproj[(int64_t)b * PW + it];
     part[sl][it] = t;
   }
   __syncthreads();
-  if (tid < NI) {
+  if (tid < CMAX) {
     double t = 0.0;
     for (int sl = 0; sl < NSL; ++sl) t += part[sl][tid];
     v[tid] = t;
   }
   __syncthreads();
   if (tid < RMAX) {
-    double a1 = 0.0, b1 = 0.0;
-    if (tid < r) {
+    double a1 = 0.0;
+    if (tid < r)
       for (int c0 = 0; c0 < m; ++c0) a1 += st->Q[c0 * RMAX + tid] * v[c0];
-      for (int c0 = 0; c0 < mT; ++c0) b1 += tst->Q[c0 * RMAX + tid] * v[CMAX + c0];
-    }
     p1[tid] = a1;
     st->p1[tid] = a1;
-    st->xB[tid] = b1;
   }
   __syncthreads();
   if (tid < CMAX) {

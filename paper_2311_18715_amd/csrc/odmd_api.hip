@@ -46,6 +46,7 @@ struct odmd_s {
   void* Ts = nullptr;
   double* pproj = nullptr;
   double* pt = nullptr;
+  void* eout = nullptr;         // the residual e as a contiguous vector (io type)
   int nblk = 0;
   int64_t units = 0;
   bool prof = false;
@@ -64,7 +65,7 @@ namespace {
 
 struct Layout {
   size_t st = 0, partials = 0, Us = 0, total = 0;
-  size_t tst = 0, pproj = 0, pt = 0, Ts = 0;   // general pairs only
+  size_t tst = 0, pproj = 0, pt = 0, Ts = 0, eout = 0;   // general pairs only
   int64_t ntiles = 0, units = 0;
   int nblk = 0, ct = 0;
 };
@@ -112,6 +113,8 @@ Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis, bool general = fa
     off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
     L.Ts = off;
     off += round_up(L.ntiles * L.ct * 64 * elem_bytes(basis), 256);
+    L.eout = off;
+    off += round_up(n * 8, 256);
   }
   L.total = off;
   return L;
@@ -188,30 +191,32 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.ct = h->ct;
   const int kb = live_bucket(h);
   if (h->general) {
-    // U^T x from a projection sweep, then the T sweep (appends y to T,
-    // refolding T when it is full; its records carry T^T x), then the
-    // coefficients of the streaming pass
+    // U^T x from a projection sweep, then the coefficients of the streaming
+    // pass (which also writes e contiguously for the T sweep below)
     PassArgs pp = p;
     pp.partials = h->pproj;
     HIP_OK(launch_proj(pp, (int)h->basis, kb, h->stream));
+    CoefArgs ca{};
+    ca.st = h->st;
+    ca.pproj = h->pproj;
+    ca.nblk = h->nblk;
+    ca.rb = kb;
+    HIP_OK(launch_coef(ca, h->stream));
+    p.eout = h->eout;
+  }
+  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+  if (h->general) {
+    // the T sweep: appends y to T (refolding T when it is full) with zero
+    // coefficients; its records carry T^T e
     PassArgs pt = p;
     pt.Us = h->Ts;
     pt.x = y;
-    pt.y = x;
+    pt.y = h->eout;
     pt.partials = h->pt;
     pt.st = h->tst;
+    pt.eout = nullptr;
     HIP_OK(launch_pass(pt, (int)h->basis, h->ct, h->stream));
-    CoefArgs ca{};
-    ca.st = h->st;
-    ca.tst = h->tst;
-    ca.pproj = h->pproj;
-    ca.pt = h->pt;
-    ca.nblk = h->nblk;
-    ca.rb = kb;
-    ca.rbt = h->ct;
-    HIP_OK(launch_coef(ca, h->stream));
   }
-  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
   CoreArgs c{};
   c.st = h->st;
@@ -225,6 +230,8 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.fb = h->fb_dev;
   c.seq = h->seq;
   c.tst = h->general ? h->tst : nullptr;
+  c.pt = h->general ? h->pt : nullptr;
+  c.rbt = h->ct;
   HIP_OK(launch_core(c, h->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
   return ODMD_OK;
 }
@@ -477,6 +484,7 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
     s->pproj = reinterpret_cast<double*>(s->mem + L.pproj);
     s->pt = reinterpret_cast<double*>(s->mem + L.pt);
     s->Ts = s->mem + L.Ts;
+    s->eout = s->mem + L.eout;
   }
   const double tol_eff = s->tol_eff;
   const int gflag = general ? 1 : 0;

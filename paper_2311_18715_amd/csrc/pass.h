@@ -13,9 +13,11 @@ struct PassArgs {
   double* partials;     // nblk records (stride PW) of 2 rb + 4 values
   const DevState* st;
   int64_t n;
-  int64_t units;        // 32-row units, ceil(n / 32)
+  int64_t units;        // (unused by the kernels; kept for the host)
   int nblk;             // workgroups
   int ct;               // column capacity of a basis tile (rank bucket of r_max)
+  void* eout;           // general pairs: the stored residual e also written here
+                        // as a contiguous n-vector of the io type (else null)
 };
 
 // basis: storage type (0 double, 1 float, 2 bf16; the odmd_dtype codes);
@@ -55,19 +57,18 @@ struct CoreArgs {
   unsigned* fb;         // host-visible word: (seq << 8) | stored columns after this update
   unsigned seq;         // update sequence number (24 bits) of this launch
   DevState* tst;        // general pairs: state of B = T R (R in its Q), else null
+  const double* pt;     // general pairs: T sweep records, T^T e in the second half
+  int rbt;              // general pairs: bucket of the T sweep
 };
 
-// General pairs, between the two sweeps and the streaming pass: reduces the
-// projection records (S^T x) and the T sweep's records (T^T x), and sets
-// p1 = U^T x = Q^T S^T x, the pass coefficients a = Q p1 and xB = R^T T^T x.
+// General pairs, between the projection sweep and the streaming pass:
+// reduces the projection records (S^T x) and sets p1 = U^T x = Q^T S^T x and
+// the pass coefficients a = Q p1.
 struct CoefArgs {
   DevState* st;
-  const DevState* tst;
   const double* pproj;  // projection records (compact, 2 rb + 4 per workgroup)
-  const double* pt;     // T sweep records (compact, 2 ct + 4 per workgroup)
   int nblk;
   int rb;               // bucket of the projection sweep
-  int rbt;              // bucket of the T sweep
 };
 hipError_t launch_coef(const CoefArgs& c, hipStream_t s);
 hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0 = nullptr,

@@ -15,8 +15,9 @@
 //   * on a refold pass (no free column left), S[:, :r] <- S Q in place on the
 //     matrix cores, with e then stored as column r.
 // For general (unchained) pairs the same sweep also serves as the projection
-// of x (k_proj: e = x, nothing stored) and, run on the stored columns T of
-// B = Y W = T R with zero coefficients, appends y to T.
+// of x (k_proj: e = x, nothing stored), writes e contiguously for the next
+// sweep, and, run on the stored columns T of B = Y W = T R with zero
+// coefficients, appends y to T and forms T^T e.
 //
 // Layout and mapping (CDNA4): S is stored in tiles of 64 rows, each tile
 // column-major (element (i, c) at ((i/64)*ct + c)*64 + i%64), so one column of
@@ -179,6 +180,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
       // sees it in the sums below) is stored as zero: stored columns stay
       // finite
       if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(ed) ? es : SC::from_double(0.0);
+      if (p.eout && q == 0 && row < p.n) static_cast<TIO*>(p.eout)[row] = (TIO)ed;
     }
 
     // projections, accumulated in-lane

@@ -85,11 +85,12 @@ def test_noisy_wake_restarted_pairs(nx, ny, r_max, segments, length):
     g, o = run_pairs(X, Y, r_max, 1e-8, check_every=7)
     lam, _ = g.eigs()
     lo, _ = o.eigs()
-    # leading eigenvalues (the planted modes dominate; noise directions
-    # differ only at the truncation boundary)
+    # the eigenvalues of the planted modes (noise directions, some of them
+    # larger in modulus than the weakest transients, differ at the
+    # truncation boundary and are not compared)
     pl = s.planted_eigs()
-    k = len(pl)
-    assert rel_eig_err(lo[:k], lam) < 1e-10
+    mg, mo = O.match_eigs(pl, lam), O.match_eigs(pl, lo)
+    assert np.max(np.abs(mg - mo) / np.abs(mo)) < 1e-10
     st = g.state()
     np.testing.assert_allclose(st["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
     U = g.basis_matrix().cpu().numpy()
