@@ -42,7 +42,7 @@ __device__ __forceinline__ void rr_pair(int k, int i, int Mp, int& a, int& b) {
 // One-sided Jacobi on the M columns of A (LDS, column-major, ld LDK), with
 // the rotations accumulated in V.  On return the columns of A are mutually
 // orthogonal: A = (A_in V) with ||A_j|| the singular values.
-__device__ int jacobi_sweeps(double* A, double* V, double* d, int M, int* flag) {
+__device__ __forceinline__ int jacobi_sweeps(double* A, double* V, double* d, int M, int* flag) {
   const int tid = threadIdx.x, hw = tid >> 5, hl = tid & 31;
   const int nhw = CORE_THREADS / 32;
   const int Mp = M + (M & 1);
@@ -154,7 +154,7 @@ __device__ __forceinline__ double lam_minus_d(const SecShared& S, int i, double 
 
 // Returns true on success; fills A (columns U_k * sigma'), V (V_k), column
 // order arbitrary (the caller sorts by column norm).
-__device__ bool secular_svd(double* A, double* V, const double* sig, const double* pv, double rho,
+__device__ __forceinline__ bool secular_svd(double* A, double* V, const double* sig, const double* pv, double rho,
                             int r, SecShared& S) {
   const int tid = threadIdx.x;
   const int n = r + 1;
@@ -441,7 +441,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 //     R' = [[R, 0], [0, 1]] V_k,    A~ = G' diag(sigma')^-1.
 // U_k(i, a) = sA[perm[a] * LDK + i] / sd[perm[a]], V_k(i, a) = sV[perm[a] *
 // LDK + i]; sQ is free here (Q' is written) and receives E V_k.
-__device__ __noinline__ void general_tail(const CoreArgs& c, int r, int rn, int M, double qy,
+__device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, int M, double qy,
                                           const double* sA, const double* sV, const double* sC,
                                           double* sQ, const double* sd, const double* sgn,
                                           const double* pyr, const double* qB, const int* perm) {
@@ -561,6 +561,7 @@ __device__ __noinline__ void general_tail(const CoreArgs& c, int r, int rn, int 
   }
 }
 
+template <bool GENERAL>
 __device__ __forceinline__ void core_update(const CoreArgs& c) {
   DevState* __restrict__ st = c.st;
   __shared__ double sA[MMAX * LDK];
@@ -640,7 +641,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 
   // general pairs: e^T B = R^T T^T e from the T sweep's records (second
   // half, fixed-order sums; R and the T columns as that sweep read them)
-  if (c.tst) {
+  if constexpr (GENERAL) {
     const DevState* __restrict__ tst = c.tst;
     const int mT = tst->m;
     constexpr int NSL = CORE_THREADS / CMAX;
@@ -702,7 +703,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
           isfinite(py2))) {
       skip = ST_NONFINITE;
-    } else if (!c.tst && st->m_acc > 0 && xx != st->yy_prev) {
+    } else if (!GENERAL && st->m_acc > 0 && xx != st->yy_prev) {
       skip = ST_SEQ;
     }
     double rho = sqrt(fmax(ee - pp, 0.0));
@@ -729,7 +730,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       if (tid < CMAX) st->a[tid] = tid < r ? st->py[tid] : 0.0;
     }
     // Likewise for B = T R after a refolding T sweep: R = I, r columns.
-    if (c.tst && c.tst->refold) {
+    if (GENERAL && c.tst->refold) {
       DevState* __restrict__ tst = c.tst;
       for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
         const int c0 = idx / RMAX, j = idx % RMAX;
@@ -745,7 +746,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
         st->m = r;
         st->refold = 0;
       }
-      if (c.tst && c.tst->refold) {
+      if (GENERAL && c.tst->refold) {
         c.tst->m = r;
         c.tst->refold = 0;
       }
@@ -760,14 +761,14 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int M = r + 1;
   if (tid < r) {
     ssig[tid] = st->sigma[tid];
-    pvec[tid] = (c.tst ? st->p1[tid] : st->py[tid]) + p2[tid];
+    pvec[tid] = (GENERAL ? st->p1[tid] : st->py[tid]) + p2[tid];
   }
   __syncthreads();
   // general pairs: q^T B = (e^T B - p2^T G) / rho with G = U^T B (in sC,
   // G(i, j) at sC[j * RMAX + i]), from the stored residual e = x - U p1
   // itself (no cancellation between x^T B and p^T G); zero when no
   // direction is added
-  if (c.tst && tid < r) {
+  if (GENERAL && tid < r) {
     double t = 0.0;
     for (int i = 0; i < r; ++i) t += p2[i] * sC[tid * RMAX + i];
     qB[tid] = si[1] ? (eB[tid] - t) / sc[0] : 0.0;
@@ -809,7 +810,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int rn = min(above, c.r_max);
   if (rn == 0) {   // nothing kept (zero snapshots so far)
     if (tid < CMAX) st->a[tid] = 0.0;
-    if (tid == 0 && c.tst) {
+    if (GENERAL && tid == 0) {
       c.tst->m = 0;
       c.tst->r = 0;
       c.tst->refold = 0;
@@ -949,7 +950,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
 
-  if (c.tst) {
+  if constexpr (GENERAL) {
     general_tail(c, r, rn, M, qy, sA, sV, sC, sQ, sd, sgn, pyr, qB, perm);
   } else {
   // 9. T = E V_k[:, kept] with E = [[C, 0], [w^T, 0]] (M x r, the zero
@@ -1032,19 +1033,23 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 // One update of the small state, then the stored-column count it leaves,
 // tagged with the update's sequence number, to the host-visible feedback
 // word (the host sizes later launches from it).
+template <bool GENERAL>
 __device__ __forceinline__ void core_body(const CoreArgs& c) {
-  core_update(c);
+  core_update<GENERAL>(c);
   if (threadIdx.x == 0 && c.fb) {
     const unsigned mm = (unsigned)c.st->m;
     *reinterpret_cast<volatile unsigned*>(c.fb) = ((c.seq & 0xFFFFFFu) << 8) | (mm & 0xFFu);
   }
 }
 
-__global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) { core_body(c); }
+// chained pairs and general pairs (B = T R) as separate kernels, so that the
+// chained kernel carries none of the general pairs' code
+__global__ __launch_bounds__(CORE_THREADS) void k_core(CoreArgs c) { core_body<false>(c); }
+__global__ __launch_bounds__(CORE_THREADS) void k_core_general(CoreArgs c) { core_body<true>(c); }
 
 __global__ __launch_bounds__(CORE_THREADS) void k_core_batch(const CoreArgs* __restrict__ cs) {
   const CoreArgs c = cs[blockIdx.x];
-  core_body(c);
+  core_body<false>(c);
 }
 
 hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s) {
@@ -1053,7 +1058,8 @@ hipError_t launch_core_batch(const CoreArgs* cs, int count, hipStream_t s) {
 }
 
 hipError_t launch_core(const CoreArgs& c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  hipExtLaunchKernelGGL(k_core, dim3(1), dim3(CORE_THREADS), 0, s, e0, e1, 0, c);
+  if (c.tst) hipExtLaunchKernelGGL(k_core_general, dim3(1), dim3(CORE_THREADS), 0, s, e0, e1, 0, c);
+  else hipExtLaunchKernelGGL(k_core, dim3(1), dim3(CORE_THREADS), 0, s, e0, e1, 0, c);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <unordered_set>
+#include <tuple>
 #include <vector>
 
 #include "odmd.h"
@@ -48,6 +49,7 @@ struct odmd_s {
   double* pt = nullptr;
   void* eout = nullptr;         // the residual e as a contiguous vector (io type)
   int nblk = 0;
+  int threads = 0;              // workgroup size of the stream's pass launch shape
   int64_t units = 0;
   bool prof = false;
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
@@ -67,7 +69,7 @@ struct Layout {
   size_t st = 0, partials = 0, Us = 0, total = 0;
   size_t tst = 0, pproj = 0, pt = 0, Ts = 0, eout = 0;   // general pairs only
   int64_t ntiles = 0, units = 0;
-  int nblk = 0, ct = 0;
+  int nblk = 0, ct = 0, threads = 0;
 };
 
 int elem_bytes(odmd_dtype t) { return t == ODMD_F64 ? 8 : (t == ODMD_F32 ? 4 : 2); }
@@ -95,8 +97,10 @@ Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis, bool general = fa
   Layout L;
   L.ct = fold_capacity(r_max);
   L.ntiles = (n + 63) / 64;
-  L.units = (n + PASS_ROWS_PER_BLOCK - 1) / PASS_ROWS_PER_BLOCK;
-  L.nblk = (int)std::min<int64_t>(L.units, PASS_MAX_BLOCKS);
+  const PassShape sh = n >= PASS_WIDE_MIN_N ? PASS_WIDE : PASS_DEEP;
+  L.threads = sh.threads;
+  L.units = (n + sh.rows_per_block - 1) / sh.rows_per_block;
+  L.nblk = (int)std::min<int64_t>(L.units, sh.max_blocks);
   size_t off = 0;
   L.st = off;
   off += round_up(sizeof(DevState), 256);
@@ -189,6 +193,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.units = h->units;
   p.nblk = h->nblk;
   p.ct = h->ct;
+  p.threads = h->threads;
   const int kb = live_bucket(h);
   if (h->general) {
     // U^T x from a projection sweep, then the coefficients of the streaming
@@ -288,12 +293,13 @@ odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>&
 
 odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
   hipStream_t stream = hs[0]->stream;
-  // group streams by (storage type, live-column bucket): one pass launch per group
+  // group streams by (launch shape, storage type, live-column bucket): one
+  // pass launch per group
   std::vector<int> kb(count);
-  std::map<std::pair<int, int>, std::vector<int32_t>> groups;
+  std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
   for (int32_t i = 0; i < count; ++i) {
     kb[i] = live_bucket(hs[i]);
-    groups[{(int)hs[i]->basis, kb[i]}].push_back(i);
+    groups[{hs[i]->threads, (int)hs[i]->basis, kb[i]}].push_back(i);
   }
   const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
   const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
@@ -306,11 +312,11 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   BatchSlot& sl = *slp;
   PassDesc* pd = static_cast<PassDesc*>(sl.host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
-  struct Launch { int first, nd, nblocks, basis, rb; };
+  struct Launch { int first, nd, nblocks, threads, basis, rb; };
   std::vector<Launch> launches;
   int k = 0;
   for (auto& g : groups) {
-    Launch L{k, 0, 0, g.first.first, g.first.second};
+    Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first)};
     for (int32_t i : g.second) {
       odmd_t h = hs[i];
       PassDesc& d = pd[k++];
@@ -348,7 +354,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   HIP_OK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
   const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
   for (const Launch& L : launches)
-    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.basis, L.rb, stream));
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb, stream));
   HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(static_cast<char*>(sl.dev) + pass_bytes),
                            count, stream));
   // the slot (host staging and device table) is free again once the
@@ -445,6 +451,7 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
   s->io = io;
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->nblk = L.nblk;
+  s->threads = L.threads;
   s->units = L.units;
   {
     const char* alg = std::getenv("ODMD_CORE_SVD");

@@ -24,21 +24,20 @@ constexpr int MMAX = RMAX + 1;    // core size (r + 1)
 constexpr int CMAX = 72;          // stored columns per tile, at most
 constexpr int FOLD_SLACK = 16;    // stored columns beyond r_max before a refold
 constexpr int PW = 2 * CMAX + 4;  // partial-sum record per workgroup
-#ifndef ODMD_PASS_THREADS
-#define ODMD_PASS_THREADS 512
-#endif
-constexpr int PASS_THREADS = ODMD_PASS_THREADS;
-#ifndef ODMD_PASS_MAX_BLOCKS
-#define ODMD_PASS_MAX_BLOCKS 256
-#endif
-#ifndef ODMD_PASS_ROWS_PER_BLOCK
-#define ODMD_PASS_ROWS_PER_BLOCK 256
-#endif
-// Streaming-pass workgroups of a stream: one per PASS_ROWS_PER_BLOCK rows,
-// at most PASS_MAX_BLOCKS.  Fixed at creation: the partition sets the order
-// of the pass's sums, so it never changes for a handle.
-constexpr int PASS_MAX_BLOCKS = ODMD_PASS_MAX_BLOCKS;
-constexpr int PASS_ROWS_PER_BLOCK = ODMD_PASS_ROWS_PER_BLOCK;
+// Streaming-pass launch shape of a stream, fixed at creation (the
+// partition sets the order of the pass's sums, so it never changes for a
+// handle, batched or not):
+//   wide (n >= PASS_WIDE_MIN_N): 512-thread workgroups, one per 256 rows, at
+//        most 256 of them: one workgroup per CU for a stream that runs alone;
+//   deep (smaller n): 256-thread workgroups, one per 512 rows, at most 512:
+//        more 16-row units per wave, so that the one-unit-ahead prefetch
+//        hides the load latency of short row ranges.
+struct PassShape {
+  int threads, rows_per_block, max_blocks;
+};
+constexpr PassShape PASS_WIDE = {512, 256, 256};
+constexpr PassShape PASS_DEEP = {256, 512, 512};
+constexpr int64_t PASS_WIDE_MIN_N = 131072;
 constexpr int CORE_THREADS = 1024;
 constexpr int COEF_CHUNK = 512;   // prediction steps per coefficient chunk
 

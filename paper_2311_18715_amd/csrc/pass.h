@@ -18,6 +18,7 @@ struct PassArgs {
   int ct;               // column capacity of a basis tile (rank bucket of r_max)
   void* eout;           // general pairs: the stored residual e also written here
                         // as a contiguous n-vector of the io type (else null)
+  int threads;          // workgroup size of the stream's launch shape
 };
 
 // basis: storage type (0 double, 1 float, 2 bf16; the odmd_dtype codes);
@@ -42,8 +43,9 @@ struct PassDesc {
   int blk0;             // its first workgroup in the launch
   int ct;               // column capacity of its basis tiles
 };
-hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis, int rb,
-                             hipStream_t s);
+// threads: the launch shape's workgroup size, common to the streams of d
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int basis,
+                             int rb, hipStream_t s);
 
 struct CoreArgs {
   DevState* st;

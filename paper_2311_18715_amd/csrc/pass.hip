@@ -69,13 +69,13 @@ template <> struct Mfma<float> {
 
 // PROJ: projection-only sweep of a general pair (e = x: the sums S^T x,
 // S^T y, x.x, x.y; nothing is stored and no refold happens)
-template <typename TS, typename TIO, int RB, bool PROJ = false>
+template <typename TS, typename TIO, int RB, int NTH, bool PROJ = false>
 __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr int UR = 16;                  // rows per unit
   constexpr int UPT = 64 / UR;            // units per 64-row tile
   constexpr int KK = RB / 4;              // k-steps over the RB live stored columns
   constexpr int NT = ((RB < RMAX ? RB : RMAX) + 15) / 16;   // 16-column output blocks of a refold (r <= RMAX)
-  constexpr int NWAVE = PASS_THREADS / 64;
+  constexpr int NWAVE = NTH / 64;           // waves of the workgroup
   typedef Storage<TS> SC;
   typedef typename SC::tc TC;             // compute type of the matrix-core refold
   typedef typename Mfma<TC>::acc_t acc_t;
@@ -137,7 +137,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
   // Q[4 kk + lane/16][16 nt + lane%16]) for a refold.  a is loaded before
   // the first unit, so that waiting for it leaves the unit's loads in flight.
-  static_assert(PASS_THREADS >= 4 * KK, "one thread per coefficient");
+  static_assert(NTH >= 4 * KK, "one thread per coefficient");
   __shared__ TC sG[KK][NT][64];
   __shared__ double sa[4 * KK];          // a, zero past the m stored columns
   const int ca = threadIdx.x;
@@ -150,7 +150,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   if (ca < 4 * KK) sa[ca] = a_c;
   if (refold) {
     cptr<TC> Q = Mfma<TC>::Q(st);
-    for (int idx = threadIdx.x; idx < KK * NT * 64; idx += PASS_THREADS) {
+    for (int idx = threadIdx.x; idx < KK * NT * 64; idx += NTH) {
       const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
       const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
       sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TC(0);
@@ -254,7 +254,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   }
   __syncthreads();
   double* __restrict__ out = p.partials + (int64_t)blk * PW;
-  for (int idx = threadIdx.x; idx < 2 * RB + 4; idx += PASS_THREADS) {
+  for (int idx = threadIdx.x; idx < 2 * RB + 4; idx += NTH) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < NWAVE; ++w) t += red[w][idx];
@@ -262,22 +262,22 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   }
 }
 
-template <typename TS, typename TIO, int RB>
-__global__ __launch_bounds__(PASS_THREADS) void k_pass(PassArgs p) {
-  pass_body<TS, TIO, RB>(p, blockIdx.x);
+template <typename TS, typename TIO, int RB, int NTH>
+__global__ __launch_bounds__(NTH) void k_pass(PassArgs p) {
+  pass_body<TS, TIO, RB, NTH>(p, blockIdx.x);
 }
 
-template <typename TS, typename TIO, int RB>
-__global__ __launch_bounds__(PASS_THREADS) void k_proj(PassArgs p) {
-  pass_body<TS, TIO, RB, true>(p, blockIdx.x);
+template <typename TS, typename TIO, int RB, int NTH>
+__global__ __launch_bounds__(NTH) void k_proj(PassArgs p) {
+  pass_body<TS, TIO, RB, NTH, true>(p, blockIdx.x);
 }
 
 // Many streams of one storage type and live-column bucket in one launch: workgroup b
 // belongs to the stream whose block range [blk0, blk0 + nblk) contains b, and
 // runs exactly the work that workgroup b - blk0 of that stream's own launch
 // would (same partition, same reduction order: results are bitwise equal).
-template <typename TS, typename TIO, int RB>
-__global__ __launch_bounds__(PASS_THREADS) void k_pass_batch(const PassDesc* __restrict__ d, int nd) {
+template <typename TS, typename TIO, int RB, int NTH>
+__global__ __launch_bounds__(NTH) void k_pass_batch(const PassDesc* __restrict__ d, int nd) {
   typedef const __attribute__((address_space(4))) PassDesc* cdesc;
   cdesc D = (cdesc)d;
   const int b = blockIdx.x;
@@ -297,57 +297,67 @@ __global__ __launch_bounds__(PASS_THREADS) void k_pass_batch(const PassDesc* __r
   p.units = 0;
   p.nblk = D[lo].nblk;
   p.ct = D[lo].ct;
-  pass_body<TS, TIO, RB>(p, b - D[lo].blk0);
+  pass_body<TS, TIO, RB, NTH>(p, b - D[lo].blk0);
 }
 
+// Launchers: storage type and live-column bucket select the instantiation,
+// the stream's launch shape (PassShape::threads) the workgroup size.
+template <typename TS, typename TIO, int RB>
+static void batch_one(const PassDesc* d, int nd, int nblocks, int threads, hipStream_t s) {
+  if (threads == PASS_WIDE.threads)
+    hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, PASS_WIDE.threads>), dim3(nblocks),
+                       dim3(PASS_WIDE.threads), 0, s, d, nd);
+  else
+    hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, PASS_DEEP.threads>), dim3(nblocks),
+                       dim3(PASS_DEEP.threads), 0, s, d, nd);
+}
+
+template <typename TS, typename TIO, int RB>
+static void launch_one(const PassArgs& p, bool proj, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(p.nblk);
+  constexpr int W = PASS_WIDE.threads, D = PASS_DEEP.threads;
+  if (p.threads == W) {
+    if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
+    else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
+  } else {
+    if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
+    else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
+  }
+}
+
+#define ODMD_BUCKETS(CASE) CASE(8) CASE(16) CASE(24) CASE(32) CASE(40) CASE(48) CASE(56) CASE(64) CASE(72)
+
 template <typename TS, typename TIO>
-static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int rb, hipStream_t s) {
-  const dim3 grid(nblocks), block(PASS_THREADS);
+static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int threads, int rb,
+                                  hipStream_t s) {
   switch (rb) {
-    case 8: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 8>), grid, block, 0, s, d, nd); break;
-    case 16: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 16>), grid, block, 0, s, d, nd); break;
-    case 24: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 24>), grid, block, 0, s, d, nd); break;
-    case 32: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 32>), grid, block, 0, s, d, nd); break;
-    case 40: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 40>), grid, block, 0, s, d, nd); break;
-    case 48: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 48>), grid, block, 0, s, d, nd); break;
-    case 56: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 56>), grid, block, 0, s, d, nd); break;
-    case 64: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 64>), grid, block, 0, s, d, nd); break;
-    case 72: hipLaunchKernelGGL((k_pass_batch<TS, TIO, 72>), grid, block, 0, s, d, nd); break;
+#define ODMD_CASE(RB) \
+  case RB: batch_one<TS, TIO, RB>(d, nd, nblocks, threads, s); break;
+    ODMD_BUCKETS(ODMD_CASE)
+#undef ODMD_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int basis, int rb,
-                             hipStream_t s) {
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int basis,
+                             int rb, hipStream_t s) {
   switch (basis) {
-    case 0: return launch_batch_rb<double, double>(d, nd, nblocks, rb, s);
-    case 1: return launch_batch_rb<float, float>(d, nd, nblocks, rb, s);
-    case 2: return launch_batch_rb<bf16, float>(d, nd, nblocks, rb, s);
+    case 0: return launch_batch_rb<double, double>(d, nd, nblocks, threads, rb, s);
+    case 1: return launch_batch_rb<float, float>(d, nd, nblocks, threads, rb, s);
+    case 2: return launch_batch_rb<bf16, float>(d, nd, nblocks, threads, rb, s);
   }
   return hipErrorInvalidValue;
-}
-
-template <typename TS, typename TIO, int RB>
-static void launch_one(const PassArgs& p, bool proj, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const dim3 grid(p.nblk), block(PASS_THREADS);
-  if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB>), grid, block, 0, s, e0, e1, 0, p);
-  else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB>), grid, block, 0, s, e0, e1, 0, p);
 }
 
 template <typename TS, typename TIO>
 static hipError_t launch_rb(const PassArgs& p, int rb, bool proj, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1) {
   switch (rb) {
-    case 8: launch_one<TS, TIO, 8>(p, proj, s, e0, e1); break;
-    case 16: launch_one<TS, TIO, 16>(p, proj, s, e0, e1); break;
-    case 24: launch_one<TS, TIO, 24>(p, proj, s, e0, e1); break;
-    case 32: launch_one<TS, TIO, 32>(p, proj, s, e0, e1); break;
-    case 40: launch_one<TS, TIO, 40>(p, proj, s, e0, e1); break;
-    case 48: launch_one<TS, TIO, 48>(p, proj, s, e0, e1); break;
-    case 56: launch_one<TS, TIO, 56>(p, proj, s, e0, e1); break;
-    case 64: launch_one<TS, TIO, 64>(p, proj, s, e0, e1); break;
-    case 72: launch_one<TS, TIO, 72>(p, proj, s, e0, e1); break;
+#define ODMD_CASE(RB) \
+  case RB: launch_one<TS, TIO, RB>(p, proj, s, e0, e1); break;
+    ODMD_BUCKETS(ODMD_CASE)
+#undef ODMD_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
