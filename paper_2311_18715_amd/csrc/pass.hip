@@ -68,8 +68,9 @@ template <> struct Mfma<float> {
 };
 
 // PROJ: projection-only sweep of a general pair (e = x: the sums S^T x,
-// S^T y, x.x, x.y; nothing is stored and no refold happens)
-template <typename TS, typename TIO, int RB, int NTH, bool PROJ = false>
+// S^T y, x.x, x.y; nothing is stored and no refold happens).  EOUT: the
+// stored residual is also written to p.eout (general pairs).
+template <typename TS, typename TIO, int RB, int NTH, bool PROJ = false, bool EOUT = false>
 __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr int UR = 16;                  // rows per unit
   constexpr int UPT = 64 / UR;            // units per 64-row tile
@@ -180,7 +181,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
       // sees it in the sums below) is stored as zero: stored columns stay
       // finite
       if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(ed) ? es : SC::from_double(0.0);
-      if (p.eout && q == 0 && row < p.n) static_cast<TIO*>(p.eout)[row] = (TIO)ed;
+      if constexpr (EOUT) {
+        if (q == 0 && row < p.n) static_cast<TIO*>(p.eout)[row] = (TIO)ed;
+      }
     }
 
     // projections, accumulated in-lane
@@ -272,6 +275,11 @@ __global__ __launch_bounds__(NTH) void k_proj(PassArgs p) {
   pass_body<TS, TIO, RB, NTH, true>(p, blockIdx.x);
 }
 
+template <typename TS, typename TIO, int RB, int NTH>
+__global__ __launch_bounds__(NTH) void k_pass_eout(PassArgs p) {
+  pass_body<TS, TIO, RB, NTH, false, true>(p, blockIdx.x);
+}
+
 // Many streams of one storage type and live-column bucket in one launch: workgroup b
 // belongs to the stream whose block range [blk0, blk0 + nblk) contains b, and
 // runs exactly the work that workgroup b - blk0 of that stream's own launch
@@ -318,9 +326,11 @@ static void launch_one(const PassArgs& p, bool proj, hipStream_t s, hipEvent_t e
   constexpr int W = PASS_WIDE.threads, D = PASS_DEEP.threads;
   if (p.threads == W) {
     if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
+    else if (p.eout) hipExtLaunchKernelGGL((k_pass_eout<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
     else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
   } else {
     if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
+    else if (p.eout) hipExtLaunchKernelGGL((k_pass_eout<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
     else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
   }
 }
