@@ -488,12 +488,22 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
       const int kb = k0 + (l & 15);
       const int pk = kb < rn ? perm[kb] : 0;
       if (!trefold) {
-        for (int j0 = 0; j0 < r; j0 += 4) {
-          const int j = j0 + (l >> 4);
-          const int ca = c0 + (l & 15);
-          const double av = (j < r && ca < mTe) ? tst->Q[ca * RMAX + j] : 0.0;
-          const double bv = (j < r && kb < rn) ? sV[pk * LDK + j] : 0.0;
-          d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+        // R (global, L2) for all k-steps first: one round of latency
+        constexpr int KS = RMAX / 4;
+        const int ca = c0 + (l & 15);
+        double av[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int j = 4 * ks + (l >> 4);
+          av[ks] = (j < r && ca < mTe) ? tst->Q[ca * RMAX + j] : 0.0;
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          if (4 * ks < r) {
+            const int j = 4 * ks + (l >> 4);
+            const double bv = (j < r && kb < rn) ? sV[pk * LDK + j] : 0.0;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv, d, 0, 0, 0);
+          }
         }
       }
 #pragma unroll
@@ -649,8 +659,10 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (tid < NSL * CMAX) {
       const int it = tid % CMAX, sl = tid / CMAX;
       double t = 0.0;
-      if (it < mT)
+      if (it < mT) {
+#pragma unroll 16
         for (int b = sl; b < c.nblk; b += NSL) t += c.pt[(int64_t)b * PW + c.rbt + it];
+      }
       part[sl * CMAX + it] = t;
     }
     __syncthreads();
@@ -663,6 +675,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (tid < RMAX) {
       double t = 0.0;
       if (tid < r)
+#pragma unroll 24
         for (int c0 = 0; c0 < mT; ++c0) t += tst->Q[c0 * RMAX + tid] * red[c0];
       eB[tid] = t;
     }
@@ -1072,13 +1085,30 @@ __global__ __launch_bounds__(CORE_THREADS) void k_coef(CoefArgs c) {
   __shared__ double part[NSL][CMAX];
   __shared__ double v[CMAX];
   __shared__ double p1[RMAX];
+  __shared__ double sQ[CMAX * RMAX];
   const int tid = threadIdx.x;
   const int r = st->r, m = st->m;
+  // Q to LDS (all of a thread's loads issued together), record sums with
+  // the loads of a slot overlapped
+  {
+    constexpr int NQ = (CMAX * RMAX + CORE_THREADS - 1) / CORE_THREADS;
+    double qv[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int idx = tid + i * CORE_THREADS;
+      qv[i] = (idx < CMAX * RMAX && idx / RMAX < m && idx % RMAX < r) ? st->Q[idx] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+      if (tid + i * CORE_THREADS < CMAX * RMAX) sQ[tid + i * CORE_THREADS] = qv[i];
+  }
   if (tid < NSL * CMAX) {
     const int it = tid % CMAX, sl = tid / CMAX;
     double t = 0.0;
-    if (it < m)
+    if (it < m) {
+#pragma unroll 16
       for (int b = sl; b < c.nblk; b += NSL) t += c.pproj[(int64_t)b * PW + it];
+    }
     part[sl][it] = t;
   }
   __syncthreads();
@@ -1091,7 +1121,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_coef(CoefArgs c) {
   if (tid < RMAX) {
     double a1 = 0.0;
     if (tid < r)
-      for (int c0 = 0; c0 < m; ++c0) a1 += st->Q[c0 * RMAX + tid] * v[c0];
+      for (int c0 = 0; c0 < m; ++c0) a1 += sQ[c0 * RMAX + tid] * v[c0];
     p1[tid] = a1;
     st->p1[tid] = a1;
   }
@@ -1099,7 +1129,7 @@ __global__ __launch_bounds__(CORE_THREADS) void k_coef(CoefArgs c) {
   if (tid < CMAX) {
     double t = 0.0;
     if (tid < m)
-      for (int j = 0; j < r; ++j) t += st->Q[tid * RMAX + j] * p1[j];
+      for (int j = 0; j < r; ++j) t += sQ[tid * RMAX + j] * p1[j];
     st->a[tid] = t;
   }
 }
