@@ -251,10 +251,16 @@ struct BatchSlot {
   hipEvent_t done = nullptr;
   bool used = false;
 };
+constexpr int NSIDE = 4;   // side streams for the pass launches of one batch
 struct BatchRing {
   std::mutex mu;
   BatchSlot slot[4];
   int next = 0;
+  // The pass launches of a batch's groups are independent: they go to side
+  // streams (default priority) so that one launch's tail overlaps the next
+  // launch; the core launch on the caller's stream waits for all of them.
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t fork = nullptr, join[NSIDE] = {};
 };
 std::mutex g_ring_mu;
 std::map<int, std::unique_ptr<BatchRing>> g_rings;
@@ -268,9 +274,20 @@ BatchRing* ring_for(int device) {
 
 // Next staging slot of the device's ring, grown to at least `bytes`; the
 // ring stays locked (lk) until the caller has recorded the slot's event.
-odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>& lk, BatchSlot*& out) {
+odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>& lk, BatchSlot*& out,
+                         BatchRing** ring_out = nullptr) {
   BatchRing* ring = ring_for(device);
   lk = std::unique_lock<std::mutex>(ring->mu);
+  if (ring_out) {
+    if (!ring->fork) {
+      HIP_OK(hipEventCreateWithFlags(&ring->fork, hipEventDisableTiming));
+      for (int i = 0; i < NSIDE; ++i) {
+        HIP_OK(hipStreamCreateWithFlags(&ring->side[i], hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&ring->join[i], hipEventDisableTiming));
+      }
+    }
+    *ring_out = ring;
+  }
   BatchSlot& sl = ring->slot[ring->next];
   ring->next = (ring->next + 1) % 4;
   if (sl.used) HIP_OK(hipEventSynchronize(sl.done));
@@ -305,8 +322,9 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
   std::unique_lock<std::mutex> lk;
   BatchSlot* slp = nullptr;
+  BatchRing* ring = nullptr;
   {
-    const odmd_status s = acquire_slot(hs[0]->device, bytes, lk, slp);
+    const odmd_status s = acquire_slot(hs[0]->device, bytes, lk, slp, &ring);
     if (s != ODMD_OK) return s;
   }
   BatchSlot& sl = *slp;
@@ -316,6 +334,12 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   std::vector<Launch> launches;
   int k = 0;
   for (auto& g : groups) {
+    // the longest workgroups (largest streams) first: workgroups are started
+    // in index order, so the short ones fill in behind them instead of
+    // leaving a tail of long ones at the end of the launch
+    std::stable_sort(g.second.begin(), g.second.end(), [&](int32_t a, int32_t b) {
+      return hs[a]->n * hs[b]->nblk > hs[b]->n * hs[a]->nblk;
+    });
     Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first)};
     for (int32_t i : g.second) {
       odmd_t h = hs[i];
@@ -353,8 +377,23 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   }
   HIP_OK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
   const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
-  for (const Launch& L : launches)
+  if (launches.size() == 1) {
+    const Launch& L = launches[0];
     HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb, stream));
+  } else {
+    const int nside = std::min<int>(NSIDE, (int)launches.size());
+    HIP_OK(hipEventRecord(ring->fork, stream));
+    for (int i = 0; i < nside; ++i) HIP_OK(hipStreamWaitEvent(ring->side[i], ring->fork, 0));
+    for (size_t i = 0; i < launches.size(); ++i) {
+      const Launch& L = launches[i];
+      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb,
+                               ring->side[i % nside]));
+    }
+    for (int i = 0; i < nside; ++i) {
+      HIP_OK(hipEventRecord(ring->join[i], ring->side[i]));
+      HIP_OK(hipStreamWaitEvent(stream, ring->join[i], 0));
+    }
+  }
   HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(static_cast<char*>(sl.dev) + pass_bytes),
                            count, stream));
   // the slot (host staging and device table) is free again once the
