@@ -210,22 +210,10 @@ def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 
     from paper_2311_18715_amd import synth
     from paper_2311_18715_amd.odmd import ODMD
     s = synth.wake(nx=3000, ny=1000, harmonics=10, transients=10, noise=1e-5)
-    n, p = s.modes.shape
-    Mre = torch.from_numpy(np.ascontiguousarray(s.modes.real.T)).cuda()
-    Mim = torch.from_numpy(np.ascontiguousarray(s.modes.imag.T)).cuda()
+    gen = synth.DeviceSnapshots(torch, s)
+    n = gen.n
     del s.modes
-    tg = torch.Generator(device="cuda")
-
-    def snapshots(k0, count):
-        t = s.coeffs(k0, k0 + count).T                          # (count, p)
-        cre = torch.from_numpy(np.ascontiguousarray(t.real)).cuda()
-        cim = torch.from_numpy(np.ascontiguousarray(t.imag)).cuda()
-        X = cre @ Mre - cim @ Mim
-        for c in range(count):
-            tg.manual_seed(int(s.seed) * 1000003 + k0 + c)
-            sc = s.noise * float(torch.linalg.norm(X[c])) / math.sqrt(n)
-            X[c] += sc * torch.randn(n, generator=tg, device="cuda", dtype=torch.float64)
-        return X
+    snapshots = gen.chunk
 
     models = {b: ODMD(n, 64, 1e-8, basis=b) for b in ("f64", "f32", "bf16")}
     # the same FP64 algorithm at the BF16 storage's effective tolerance 2^-8:

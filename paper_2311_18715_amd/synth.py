@@ -230,3 +230,36 @@ def restarted_pairs(s: PlantedStream, segments: int, length: int, seed: int):
         ys.append(z[:, 1:])
     return np.hstack(xs), np.hstack(ys)
 
+
+class DeviceSnapshots:
+    """Snapshots of a PlantedStream formed on the device, for sizes where the
+    host cannot hold them (n in the millions): the modes go to the device
+    once, snapshot k is Re(sum_j phi_j lam_j^k b_j) plus relative noise from
+    a device generator seeded by (seed, k), so any snapshot can again be
+    regenerated on its own.  The noise values differ from ``snapshots``'s
+    host PCG64 draws (same distribution and level)."""
+
+    def __init__(self, torch, s: PlantedStream, device: str = "cuda"):
+        self.t, self.s, self.device = torch, s, device
+        self.re = torch.from_numpy(np.ascontiguousarray(s.modes.real.T)).to(device)
+        self.im = torch.from_numpy(np.ascontiguousarray(s.modes.imag.T)).to(device)
+        self.gen = torch.Generator(device=device)
+
+    @property
+    def n(self) -> int:
+        return self.re.shape[1]
+
+    def chunk(self, k0: int, count: int):
+        """Snapshots k0 .. k0+count-1 as rows of a (count, n) FP64 tensor."""
+        t = self.s.coeffs(k0, k0 + count).T
+        cre = self.t.from_numpy(np.ascontiguousarray(t.real)).to(self.device)
+        cim = self.t.from_numpy(np.ascontiguousarray(t.imag)).to(self.device)
+        X = cre @ self.re - cim @ self.im
+        if self.s.noise > 0.0:
+            for c in range(count):
+                self.gen.manual_seed(int(self.s.seed) * 1000003 + k0 + c)
+                sc = self.s.noise * float(self.t.linalg.norm(X[c])) / math.sqrt(self.n)
+                X[c] += sc * self.t.randn(self.n, generator=self.gen, device=self.device,
+                                          dtype=X.dtype)
+        return X
+

@@ -97,3 +97,38 @@ def test_bf16_rollout_against_fp64_oracle():
     assert np.max(np.abs(m - lo[big]) / np.abs(lo[big])) < 1e-2
     U = g.basis_matrix().cpu().numpy()
     assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) < 1e-2
+
+
+def test_fp32_full_size_properties():
+    """The precision form at its full size (wake generator on a 3000 x 1000
+    grid, n = 6,000,000, 10 harmonics + 10 transients, noise 1e-5, r_max 64,
+    FP32 storage) in the benchmark's launch configuration, 300 snapshots
+    formed on the device.  The oracle cannot run at this size; properties
+    that hold at any size are checked instead: the eigenvalues of the modes
+    on the unit circle against the planted values (1e-4 relative), the
+    orthogonality of the basis (FP32 level), and a rank that holds every
+    planted persistent direction."""
+    s = synth.wake(nx=3000, ny=1000, harmonics=10, transients=10, noise=1e-5)
+    gen = synth.DeviceSnapshots(torch, s)
+    n = gen.n
+    g = ODMD(n, 64, 1e-8, basis="f32")
+    k0 = 0
+    while k0 < 299:
+        cnt = min(50, 299 - k0)
+        X = gen.chunk(k0, cnt + 1).float()
+        for k in range(cnt):
+            g.update(X[k], X[k + 1])
+        k0 += cnt
+        del X
+    g.sync()
+    assert g.info().r >= 21
+    lam, _ = g.eigs()
+    pl = s.planted_eigs()
+    persist = pl[np.abs(np.abs(pl) - 1.0) < 1e-12]
+    assert len(persist) == 21
+    m = O.match_eigs(persist, lam)
+    assert np.max(np.abs(m - persist) / np.abs(persist)) < 1e-4
+    U = g.basis_matrix()
+    G = U.T @ U
+    assert float(torch.linalg.norm(G - torch.eye(G.shape[0], dtype=G.dtype, device=G.device))) < 1e-4
+    g.close()
