@@ -87,14 +87,15 @@ __device__ __forceinline__ bool make_reflector(double x, double y, double z, dou
                                                double& v1, double& v2, double& alpha) {
   const double sc = fmax(fabs(x), fmax(fabs(y), fabs(z)));
   if (sc == 0.0 || (y == 0.0 && z == 0.0)) return false;
-  x /= sc;
-  y /= sc;
-  z /= sc;
+  const double isc = 1.0 / sc;     // one division per quantity, not per entry
+  x *= isc;
+  y *= isc;
+  z *= isc;
   const double nrm = sqrt(x * x + y * y + z * z);
   const double al = x >= 0.0 ? -nrm : nrm;
-  const double den = x - al;
-  v1 = y / den;
-  v2 = z / den;
+  const double iden = 1.0 / (x - al);
+  v1 = y * iden;
+  v2 = z * iden;
   tau = (al - x) / al;
   alpha = al * sc;
   return true;
@@ -108,7 +109,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   __shared__ double Xi[(RMAX + 1) * LDH];
   __shared__ double wr[RMAX], wi[RMAX], hv[RMAX];
   __shared__ int srank[RMAX];
-  __shared__ int sfail, spiv;
+  __shared__ int sfail;
   const int t = threadIdx.x;
   const int n = st->r;
   if (n == 0) {
@@ -437,20 +438,24 @@ __device__ __forceinline__ void eig_body(DevState* st) {
     }
     __syncthreads();
     for (int cidx = 0; cidx < n; ++cidx) {
-      if (t == 0) {
-        int piv = cidx;
-        double best = -1.0;
-        for (int i = cidx; i < n; ++i) {
-          const double m = hypot(Xr[cidx * LDH + i], Xi[cidx * LDH + i]);
-          if (m > best) {
-            best = m;
-            piv = i;
-          }
+      // pivot: the largest modulus in rows cidx.., the first of equals
+      // (one row per lane, then a butterfly over the wavefront)
+      double best = -1.0;
+      int piv = n;
+      if (t >= cidx && t < n) {
+        best = hypot(Xr[cidx * LDH + t], Xi[cidx * LDH + t]);
+        piv = t;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int op = __shfl_xor(piv, o, 64);
+        if (ob > best || (ob == best && op < piv)) {
+          best = ob;
+          piv = op;
         }
-        spiv = piv;
       }
       __syncthreads();
-      const int piv = spiv;
       if (piv != cidx) {
         for (int j = t; j <= n; j += 64) {
           const double ar = Xr[j * LDH + cidx], ai = Xi[j * LDH + cidx];
