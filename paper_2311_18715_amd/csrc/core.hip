@@ -327,19 +327,21 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
       const double cq = w - Dlo * dpsi - Dhi * dphi;
       const double aq = (Dlo + Dhi) * w - Dlo * Dhi * dw;
       const double bq = Dlo * Dhi * w;
+      // (the step only steers the iteration; the tests above decide
+      // convergence, so reciprocals stand in for the divisions)
       double r1 = NAN, r2 = NAN;
       if (cq == 0.0) {
-        if (aq != 0.0) r1 = bq / aq;
+        if (aq != 0.0) r1 = bq * recip(aq);
       } else {
         const double disc = sqrt(fabs(aq * aq - 4.0 * bq * cq));
         const double qv = 0.5 * (aq + (aq >= 0.0 ? disc : -disc));
-        r1 = qv / cq;
-        if (qv != 0.0) r2 = bq / qv;
+        r1 = qv * recip(cq);
+        if (qv != 0.0) r2 = bq * recip(qv);
       }
       double eta;
       if (i == 0) eta = (r1 > Dhi) ? r1 : ((r2 > Dhi) ? r2 : NAN);
       else eta = (r1 > Dlo && r1 < Dhi) ? r1 : ((r2 > Dlo && r2 < Dhi) ? r2 : NAN);
-      if (!(eta == eta) || w * eta >= 0.0) eta = -w / dw;
+      if (!(eta == eta) || w * eta >= 0.0) eta = -w * recip(dw);
       double nw = mu + eta;
       if (!(nw > lo && nw < hi)) nw = 0.5 * (lo + hi);
       mu = nw;
