@@ -16,10 +16,14 @@ read x and y), divided by the pass's average duration from HIP events that
 the pass's own dispatch records on the handle's stream (the kernel's begin
 and end timestamps), against 8 TB/s; the measured HBM traffic per pass
 comes from the committed rocprofv3 counter summary), p50/p99 device latency
-of one update (pass start to core end), S = 8/32/128
-concurrent n = 160k streams through the batched update, the 256-stream FP32
-batched form against a per-stream FP64 loop, and the CPU oracle timed on a
-bounded sample on this host.
+of one update (pass start to core end), a plain device-copy rate, S =
+8/32/128 concurrent n = 160k streams through the batched update, the
+256-stream FP32 batched form against a per-stream FP64 loop, the serving
+loop at swept request rates, general (unchained) pairs, the hybrid
+full-order/DMD workflow, the n = 6,000,000 precision form (FP64, FP32,
+BF16), and the CPU oracle timed on a bounded sample on this host (all
+threads and one).  --no-extra keeps only the main measurement; the
+--*-only flags run one section alone.
 """
 from __future__ import annotations
 
