@@ -262,10 +262,10 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
       continue;
     }
     int K = 0;
+    double fm = 0.0, half = 0.0;   // f at the midpoint of (d_i^2, d_{i-1}^2), half the gap
     if (i > 0) {
       const double dI = S.dj[i];
-      const double half = 0.5 * (S.dj[i - 1] - dI) * (S.dj[i - 1] + dI);
-      double fm = 0.0;
+      half = 0.5 * (S.dj[i - 1] - dI) * (S.dj[i - 1] + dI);
 #pragma unroll
       for (int m = 0; m < SEC_TERMS; ++m)
         if (ql + 16 * m < nd) fm += tzz[m] / ((tdj[m] - dI) * (tdj[m] + dI) - half);
@@ -293,6 +293,27 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
 #pragma unroll
     for (int m = 0; m < SEC_TERMS; ++m) dsh[m] = (tdj[m] - dK) * (tdj[m] + dK);
     double mu = 0.5 * (lo + hi);
+    if (i > 0) {
+      // Start from the root of the two-pole model: the two nearest terms
+      // exact, the others frozen at their midpoint value c,
+      //   c - z_K^2 / mu + z_O^2 / (del - mu) = 0
+      //   <=>  c mu^2 - (c del + z_K^2 + z_O^2) mu + z_K^2 del = 0,
+      // taken when it falls inside the bracket (else the midpoint).  A root
+      // far from the bracket's middle (a wide gap between the kept and the
+      // dropped directions) then needs a few iterations instead of ~9.
+      const double zK = S.zz[K], zO = S.zz[K == i ? i - 1 : i];
+      const double del = K == i ? dhi : dlo;
+      const double c0 = fm + (S.zz[i] - S.zz[i - 1]) / half;
+      const double qa = c0, qb = -(c0 * del + zK + zO), qc = zK * del;
+      const double disc = qb * qb - 4.0 * qa * qc;
+      if (disc >= 0.0) {
+        const double qq = -0.5 * (qb + (qb >= 0.0 ? sqrt(disc) : -sqrt(disc)));
+        const double g1 = qa != 0.0 ? qq / qa : NAN;
+        const double g2 = qq != 0.0 ? qc / qq : NAN;
+        if (g1 > lo && g1 < hi) mu = g1;
+        else if (g2 > lo && g2 < hi) mu = g2;
+      }
+    }
     int it = 0;
     const int nterm = (nd + 15) >> 4;   // term slots holding a live pole
     for (; it < SEC_MAXIT; ++it) {
