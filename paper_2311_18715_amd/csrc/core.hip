@@ -915,10 +915,12 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
   __syncthreads();
-  // Q' tiles: CMAX/16 (rounded up) row blocks (c) x 4 column blocks (k) of
-  // 16 x 16, at most two per wave
+  // Q' tiles: 16 x 16 blocks over the rows < mnew and the columns < r'
+  // (readers of Q mask rows >= m and columns >= r, so the rest keeps stale
+  // values), at most two per wave
   constexpr int NQT = 4 * ((CMAX + 15) / 16);
   static_assert(NQT <= 2 * (CORE_THREADS / 64), "two Q' tiles per wave at most");
+  const int ncb = (rn + 15) >> 4, ntile = ((mnew + 15) >> 4) * ncb;
   d4_t qt[2];
   {
     const int wv = tid >> 6, l = tid & 63;
@@ -926,8 +928,8 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     for (int h = 0; h < 2; ++h) {
       const int tile = wv + 16 * h;
       d4_t d = {0.0, 0.0, 0.0, 0.0};
-      if (tile < NQT) {
-        const int c0 = 16 * (tile >> 2), k0 = 16 * (tile & 3);
+      if (tile < ntile) {
+        const int c0 = 16 * (tile / ncb), k0 = 16 * (tile % ncb);
         const int kb = k0 + (l & 15);
         const int pk = kb < rn ? perm[kb] : 0;
         for (int j0 = 0; j0 < r; j0 += 4) {
@@ -972,8 +974,8 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int tile = wv + 16 * h;
-      if (tile < NQT) {
-        const int c0 = 16 * (tile >> 2), k0 = 16 * (tile & 3);
+      if (tile < ntile) {
+        const int c0 = 16 * (tile / ncb), k0 = 16 * (tile % ncb);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int cr = c0 + 4 * v + (l >> 4);
