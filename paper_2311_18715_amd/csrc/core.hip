@@ -12,8 +12,9 @@
 //     A~_ij = (sigma_i C_ij + p_y,i w_j) / sigma_j,
 //     C <- V_k^T [[C, 0], [w^T, 0]] V_k,   w <- last row of V_k,
 //     p_y <- U_k^T [U^T y; q^T y].
-// The SVD of K is a one-sided (Hestenes) Jacobi iteration with a
-// round-robin pair order, one 32-lane half-wavefront per column pair.
+// The SVD of K comes from its secular equation (below); a one-sided
+// (Hestenes) Jacobi iteration with a round-robin pair order, one 32-lane
+// half-wavefront per column pair, is the fallback.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -120,8 +121,9 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, double* V, double* d, in
 // (the pair (d_j, e_j) is already singular), as are poles closer than that
 // (a Givens rotation moves their z weight onto one of them); the zero pole
 // is never deflated: a zero rho is raised to that tolerance.  Each root is
-// found by one 32-lane half-wavefront: bracketed iteration on the two-pole
-// rational model of f (Li's "middle way"), falling back to bisection.
+// found by one 16-lane quarter-wavefront: bracketed iteration on the
+// two-pole rational model of f (Li's "middle way"), from the root of a
+// two-pole model with the other terms frozen, falling back to bisection.
 constexpr int SEC_MAXIT = 64;
 constexpr double SEC_EPS = 2.220446049250313e-16;
 constexpr int SEC_TERMS = (MMAX + 15) / 16;   // secular terms per lane of a quarter-wave
@@ -727,29 +729,31 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   }
   const int meff = refolded ? r : m;   // stored columns U is built from; e sits in column meff
 
-  // 3. checks, residual norm, growth test
-  if (tid == 0) {
-    const double ee = tot[P_EE], xx = tot[P_XX], ey = tot[P_EY], yy = tot[P_YY];
-    double pp = 0.0, py2 = 0.0;
-    for (int j = 0; j < r; ++j) {
-      pp += p2[j] * p2[j];
-      py2 += p2[j] * pyr[j];
+  // 3. checks, residual norm, growth test (|p2|^2 and p2 . U^T y summed
+  //    across the first wavefront, one entry per lane)
+  if (tid < 64) {
+    double pp = tid < r ? p2[tid] * p2[tid] : 0.0;
+    double py2 = tid < r ? p2[tid] * pyr[tid] : 0.0;
+    pp = add_half_pair(add_row_pair(row_sum(pp)));
+    py2 = add_half_pair(add_row_pair(row_sum(py2)));
+    if (tid == 0) {
+      const double ee = tot[P_EE], xx = tot[P_XX], ey = tot[P_EY], yy = tot[P_YY];
+      int skip = 0;
+      if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
+            isfinite(py2))) {
+        skip = ST_NONFINITE;
+      } else if (!GENERAL && st->m_acc > 0 && xx != st->yy_prev) {
+        skip = ST_SEQ;
+      }
+      double rho = sqrt(fmax(ee - pp, 0.0));
+      const int grow = !skip && rho > 0.0 && rho > st->tol * sqrt(xx);
+      if (!grow) rho = 0.0;
+      sc[0] = rho;
+      sc[1] = grow ? (ey - py2) / rho : 0.0;   // q^T y
+      sc[2] = yy;
+      si[0] = skip;
+      si[1] = grow;
     }
-    int skip = 0;
-    if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
-          isfinite(py2))) {
-      skip = ST_NONFINITE;
-    } else if (!GENERAL && st->m_acc > 0 && xx != st->yy_prev) {
-      skip = ST_SEQ;
-    }
-    double rho = sqrt(fmax(ee - pp, 0.0));
-    const int grow = !skip && rho > 0.0 && rho > st->tol * sqrt(xx);
-    if (!grow) rho = 0.0;
-    sc[0] = rho;
-    sc[1] = grow ? (ey - py2) / rho : 0.0;   // q^T y
-    sc[2] = yy;
-    si[0] = skip;
-    si[1] = grow;
   }
   __syncthreads();
   const int skip = si[0];
