@@ -413,19 +413,26 @@ def many_streams(torch):
     """256 streams (n log-uniform in [1e4, 1e6], planted rank in {6..30},
     r_max in {16..64}): the FP32-basis batched update against a loop of
     per-stream FP64 updates over the same snapshots; eigenvalue agreement
-    between the two and against the planted values."""
+    between the two and against the planted values.  The FP32 batch runs
+    twice: with the library's default launch shapes and with the shapes of
+    the shipped tuned table (throughput objective)."""
     import ctypes
-    from paper_2311_18715_amd import synth
+    from paper_2311_18715_amd import synth, autotune
     from paper_2311_18715_amd.odmd import ODMD, handle_array, update_batch_ptrs, lib
     descs = synth.batched_streams(MANY_COUNT)
     gens = [_DeviceStream(torch, n, rank, seed) for (n, rank, _, seed) in descs]
+    table = autotune.load_table()
+    shapes = [autotune.lookup(n, rmax, "f32", objective="throughput", table=table)
+              for (n, _, rmax, _) in descs]
     m32 = [ODMD(n, rmax, MANY_TOL, basis="f32") for (n, _, rmax, _) in descs]
+    m32t = [ODMD(n, rmax, MANY_TOL, basis="f32", shape=sh)
+            for (n, _, rmax, _), sh in zip(descs, shapes)]
     m64 = [ODMD(n, rmax, MANY_TOL, basis="f64") for (n, _, rmax, _) in descs]
-    H32 = handle_array(m32)
+    H32, H32t = handle_array(m32), handle_array(m32t)
     L = lib()
     ns = np.array([d[0] for d in descs], dtype=np.uint64)
     total = MANY_WARM + MANY_STEPS
-    t_batch = t_loop = 0.0
+    t_batch = t_loop = t_tuned = 0.0
     timed = 0
     for k0 in range(0, total, MANY_CHUNK):
         T = min(MANY_CHUNK, total - k0)
@@ -446,11 +453,18 @@ def many_streams(torch):
                               ctypes.c_void_p(x.data_ptr() + (k + 1) * row))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        for k in range(T):
+            xp = b32 + np.uint64(k) * ns * np.uint64(4)
+            update_batch_ptrs(H32t, xp, xp + ns * np.uint64(4))
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         print(f"many streams: steps {k0}..{k0 + T - 1} batched {t1 - t0:.3f} s, "
-              f"per-stream loop {t2 - t1:.3f} s", file=sys.stderr, flush=True)
+              f"per-stream loop {t2 - t1:.3f} s, batched (tuned shapes) {t3 - t2:.3f} s",
+              file=sys.stderr, flush=True)
         if k0 >= MANY_WARM:
             t_batch += t1 - t0
             t_loop += t2 - t1
+            t_tuned += t3 - t2
             timed += T
         del X64, X32
     # Eigenvalues: FP32 batched against FP64 where both kept the same rank
@@ -459,6 +473,13 @@ def many_streams(torch):
     worst_pair = worst_planted32 = worst_planted64 = 0.0
     same_rank = full32 = full64 = 0
     pair_diffs = []
+    tuned_diffs, tuned_rank_differs = [], 0
+    for a, t in zip(m32, m32t):
+        la, lt = a.eigs(vectors=False)[0], t.eigs(vectors=False)[0]
+        if len(la) == len(lt):
+            tuned_diffs.append(_rel_eig_diff(la, lt))
+        else:
+            tuned_rank_differs += 1
     for g, a, b, (n, rank, rmax, _) in zip(gens, m32, m64, descs):
         la, _ = a.eigs(vectors=False)
         lb, _ = b.eigs(vectors=False)
@@ -474,10 +495,18 @@ def many_streams(torch):
             worst_planted64 = max(worst_planted64, _rel_eig_diff(g.planted, lb))
     ups32 = MANY_COUNT * timed / t_batch
     ups64 = MANY_COUNT * timed / t_loop
+    ups32t = MANY_COUNT * timed / t_tuned
     res = {"streams": MANY_COUNT, "steps_timed": timed, "warmup_steps": MANY_WARM,
            "fp32_batched_stream_updates_per_s": round(ups32, 1),
            "fp64_per_stream_loop_updates_per_s": round(ups64, 1),
            "speedup": round(ups32 / ups64, 2),
+           "fp32_batched_tuned_shapes_stream_updates_per_s": round(ups32t, 1),
+           "speedup_tuned_shapes": round(ups32t / ups64, 2),
+           "streams_with_tuned_shape": int(sum(sh is not None for sh in shapes)),
+           "eig_rel_diff_tuned_vs_default_shapes": {
+               "median": float(f"{np.median(tuned_diffs):.3e}"),
+               "max": float(f"{np.max(tuned_diffs):.3e}"),
+               "streams_rank_differs": tuned_rank_differs},
            "eig_rel_diff_fp32_vs_fp64_max": float(f"{worst_pair:.3e}"),
            "streams_same_rank_fp32_fp64": same_rank,
            "eig_rel_diff_fp32_vs_fp64_median": float(f"{np.median(pair_diffs):.3e}"),
@@ -486,7 +515,7 @@ def many_streams(torch):
                                           "fp64": float(f"{worst_planted64:.3e}")},
            "streams_with_full_planted_rank": {"fp32": full32, "fp64": full64},
            "n_total": int(ns.sum())}
-    for m in m32 + m64:
+    for m in m32 + m32t + m64:
         m.close()
     return res
 

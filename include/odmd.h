@@ -120,6 +120,74 @@ odmd_status odmd_create_general(int64_t n, int32_t r_max, double tol, odmd_dtype
 size_t odmd_state_bytes_general(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io);
 
 /*
+ * Launch shape of the streaming pass (the sweep over the n rows that does
+ * the projections and CGS2 of Sec. 2.3 on the GPU): threads per workgroup
+ * (256 or 512, the sizes the pass is compiled for) and one workgroup per
+ * rows_per_block rows (a multiple of 16, at least 16, at most 2^24), at
+ * most max_blocks workgroups (1..65536).  The partition of the rows sets
+ * the order of the pass's sums, so a handle keeps its shape for life and
+ * two handles fed the same pairs give bitwise equal results exactly when
+ * their shapes give the same workgroup count and size.  Results of any two
+ * shapes agree to rounding.
+ *
+ * odmd_default_shape: the shape odmd_create_ex / odmd_create_general use
+ * for n (512 x 256 rows, at most 256 workgroups, for n >= 131072; else
+ * 256 x 512 rows, at most 512).  Host only.  ODMD_EINVAL for n < 1 or a
+ * NULL output.
+ */
+odmd_status odmd_default_shape(int64_t n, int32_t* threads, int32_t* rows_per_block,
+                               int32_t* max_blocks);
+
+/*
+ * As odmd_create_ex (general = 0) or odmd_create_general (general = 1),
+ * with the pass's launch shape given explicitly (a tuned one, see
+ * odmd_autotune).  ODMD_EINVAL for a shape outside the bounds above or a
+ * general flag other than 0/1; memory and other errors as for
+ * odmd_create_ex.
+ */
+odmd_status odmd_create_shaped(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
+                               odmd_dtype io, void* hip_stream, int32_t threads,
+                               int32_t rows_per_block, int32_t max_blocks, int32_t general,
+                               void* workspace, size_t workspace_bytes, odmd_t* h);
+
+/* Device bytes of a handle with that shape (0 for invalid arguments). */
+size_t odmd_state_bytes_shaped(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io,
+                               int32_t threads, int32_t rows_per_block, int32_t max_blocks,
+                               int32_t general);
+
+/*
+ * Autotuner of the pass's launch shape (not part of the method: it picks
+ * how the sweep of Sec. 2.3's update is cut into workgroups).  It times
+ * every candidate shape (threads 256 and 512; rows per workgroup 128 to
+ * 2048; at most 256, 512 or 1024 workgroups; candidates that give the same
+ * workgroup count and size are timed once) on chained handles of size n
+ * and rank cap r_max fed seeded uniform random snapshots, so that the rank
+ * saturates at r_max, the case that moves the most bytes:
+ *   streams == 1: one handle, odmd_update calls one at a time; the figure
+ *                 is the time per update (pass, core and the gap between);
+ *   streams > 1 (at most 1024): that many handles of the same size
+ *                 advanced by odmd_update_batch; the figure is the time
+ *                 per batched step (a throughput objective).
+ * Each candidate runs its warm-up (r_max + 24 updates) and then 48 timed
+ * steps (three refold cycles at r = r_max) between HIP events on
+ * hip_stream (NULL: the default stream); the shape with the least time
+ * wins if it beats the default shape by more than 2 % (else the default
+ * stays: a shape fixes the order of the sums, and smaller differences are
+ * within the timing noise).  Outputs (host pointers): the
+ * winning shape; *us_best its time and *us_default that of the default
+ * shape (µs per update or per step).  Synchronous; allocates and frees its
+ * own device memory (snapshots and handles), so it must not be called
+ * while the stream is being captured.  ODMD_EINVAL for invalid sizes or
+ * types or a NULL output, ODMD_ENOMEM when the handles or the
+ * (r_max + 24) x n snapshots do not fit, ODMD_EDEVICE for runtime errors,
+ * or the first error a timed handle reports.
+ */
+odmd_status odmd_autotune(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io,
+                          int32_t streams, void* hip_stream, int32_t* threads,
+                          int32_t* rows_per_block, int32_t* max_blocks, double* us_best,
+                          double* us_default);
+
+/*
  * Append one snapshot pair: x_k (a new column of U-) and x_k+1 (a new
  * column of U+); Sec. 2.3 grows each snapshot matrix by one column per
  * iteration, a rank-1 update.  x_k, x_k1: device, n elements of the io
@@ -196,6 +264,7 @@ typedef struct {
   double last_rho;    /* residual norm of the last accepted update      */
   int32_t last_sweeps;/* Jacobi sweeps of the last small SVD            */
   int32_t nblocks;    /* workgroups of the streaming pass               */
+  int32_t threads;    /* threads per workgroup of the streaming pass    */
 } odmd_info;
 
 odmd_status odmd_get_info(odmd_t h, odmd_info* info);

@@ -93,11 +93,12 @@ int col_bucket(int cols) { return (cols + 7) / 8 * 8; }
 
 // Stored basis: 64-row tiles, column-major inside a tile, fold_capacity(r_max)
 // columns per tile.
-Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis, bool general = false) {
+// The pass's workgroups: one per rows_per_block rows, at most max_blocks;
+// each gets at least one 16-row unit (rows_per_block >= 16).
+Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis, bool general, const PassShape& sh) {
   Layout L;
   L.ct = fold_capacity(r_max);
   L.ntiles = (n + 63) / 64;
-  const PassShape sh = n >= PASS_WIDE_MIN_N ? PASS_WIDE : PASS_DEEP;
   L.threads = sh.threads;
   L.units = (n + sh.rows_per_block - 1) / sh.rows_per_block;
   L.nblk = (int)std::min<int64_t>(L.units, sh.max_blocks);
@@ -454,21 +455,41 @@ const char* odmd_status_str(odmd_status s) {
 
 size_t odmd_state_bytes(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io) {
   if (!valid_args(n, r_max, 0.0, basis, io)) return 0;
-  return make_layout(n, r_max, basis).total;
+  return make_layout(n, r_max, basis, false, default_shape(n)).total;
 }
 
 size_t odmd_state_bytes_general(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io) {
   if (!valid_args(n, r_max, 0.0, basis, io)) return 0;
-  return make_layout(n, r_max, basis, true).total;
+  return make_layout(n, r_max, basis, true, default_shape(n)).total;
+}
+
+size_t odmd_state_bytes_shaped(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype io,
+                               int32_t threads, int32_t rows_per_block, int32_t max_blocks,
+                               int32_t general) {
+  const PassShape sh = {threads, rows_per_block, max_blocks};
+  if (!valid_args(n, r_max, 0.0, basis, io) || !valid_shape(sh) || (general != 0 && general != 1))
+    return 0;
+  return make_layout(n, r_max, basis, general != 0, sh).total;
+}
+
+odmd_status odmd_default_shape(int64_t n, int32_t* threads, int32_t* rows_per_block,
+                               int32_t* max_blocks) {
+  if (n < 1 || !threads || !rows_per_block || !max_blocks) return ODMD_EINVAL;
+  const PassShape sh = default_shape(n);
+  *threads = sh.threads;
+  *rows_per_block = sh.rows_per_block;
+  *max_blocks = sh.max_blocks;
+  return ODMD_OK;
 }
 
 static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
                                odmd_dtype io, void* hip_stream, void* workspace,
-                               size_t workspace_bytes, bool general, odmd_t* h) {
+                               size_t workspace_bytes, bool general, const PassShape& sh,
+                               odmd_t* h) {
   if (!h) return ODMD_EINVAL;
   *h = nullptr;
-  if (!valid_args(n, r_max, tol, basis, io)) return ODMD_EINVAL;
-  const Layout L = make_layout(n, r_max, basis, general);
+  if (!valid_args(n, r_max, tol, basis, io) || !valid_shape(sh)) return ODMD_EINVAL;
+  const Layout L = make_layout(n, r_max, basis, general, sh);
   if (workspace) {
     if (workspace_bytes < L.total) return ODMD_ENOMEM;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return ODMD_EINVAL;
@@ -552,13 +573,25 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
 
 odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dtype io,
                            void* hip_stream, void* workspace, size_t workspace_bytes, odmd_t* h) {
-  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes, false, h);
+  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes, false,
+                     default_shape(n), h);
 }
 
 odmd_status odmd_create_general(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
                                 odmd_dtype io, void* hip_stream, void* workspace,
                                 size_t workspace_bytes, odmd_t* h) {
-  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes, true, h);
+  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes, true,
+                     default_shape(n), h);
+}
+
+odmd_status odmd_create_shaped(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
+                               odmd_dtype io, void* hip_stream, int32_t threads,
+                               int32_t rows_per_block, int32_t max_blocks, int32_t general,
+                               void* workspace, size_t workspace_bytes, odmd_t* h) {
+  if (h) *h = nullptr;
+  if (general != 0 && general != 1) return ODMD_EINVAL;
+  return create_impl(n, r_max, tol, basis, io, hip_stream, workspace, workspace_bytes,
+                     general != 0, PassShape{threads, rows_per_block, max_blocks}, h);
 }
 
 odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h) {
@@ -687,6 +720,7 @@ odmd_status odmd_get_info(odmd_t h, odmd_info* info) {
   info->last_rho = hdr.last_rho;
   info->last_sweeps = hdr.sweeps;
   info->nblocks = h->nblk;
+  info->threads = h->threads;
   return ODMD_OK;
 }
 

@@ -38,6 +38,14 @@ struct PassShape {
 constexpr PassShape PASS_WIDE = {512, 256, 256};
 constexpr PassShape PASS_DEEP = {256, 512, 512};
 constexpr int64_t PASS_WIDE_MIN_N = 131072;
+// the built-in rule; a caller may give any valid shape instead (tuned ones)
+inline PassShape default_shape(int64_t n) { return n >= PASS_WIDE_MIN_N ? PASS_WIDE : PASS_DEEP; }
+// workgroup sizes the pass is compiled for, and the bounds a shape must keep
+inline bool valid_shape(const PassShape& sh) {
+  return (sh.threads == PASS_WIDE.threads || sh.threads == PASS_DEEP.threads) &&
+         sh.rows_per_block >= 16 && sh.rows_per_block <= (1 << 24) && sh.rows_per_block % 16 == 0 &&
+         sh.max_blocks >= 1 && sh.max_blocks <= 65536;
+}
 constexpr int CORE_THREADS = 1024;
 constexpr int COEF_CHUNK = 512;   // prediction steps per coefficient chunk
 

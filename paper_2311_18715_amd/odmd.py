@@ -25,6 +25,7 @@ EXPORTS = [
     "odmd_eigs", "odmd_predict", "odmd_predict_batch", "odmd_sync", "odmd_destroy", "odmd_status_str",
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
     "odmd_profile_samples", "odmd_create_general", "odmd_state_bytes_general",
+    "odmd_default_shape", "odmd_create_shaped", "odmd_state_bytes_shaped", "odmd_autotune",
 ]
 
 
@@ -40,6 +41,7 @@ class Info(ctypes.Structure):
         ("r", ctypes.c_int32), ("r_max", ctypes.c_int32), ("n", ctypes.c_int64),
         ("m", ctypes.c_int64), ("tol_eff", ctypes.c_double), ("last_rho", ctypes.c_double),
         ("last_sweeps", ctypes.c_int32), ("nblocks", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
     ]
 
 
@@ -63,6 +65,14 @@ def lib() -> ctypes.CDLL:
             "odmd_create_general": ([i64, i32, dbl, ctypes.c_int, ctypes.c_int, vp, vp,
                                      ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
             "odmd_state_bytes_general": ([i64, i32, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+            "odmd_default_shape": ([i64, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)], ctypes.c_int),
+            "odmd_create_shaped": ([i64, i32, dbl, ctypes.c_int, ctypes.c_int, vp, i32, i32, i32,
+                                    i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
+            "odmd_state_bytes_shaped": ([i64, i32, ctypes.c_int, ctypes.c_int, i32, i32, i32, i32],
+                                        ctypes.c_size_t),
+            "odmd_autotune": ([i64, i32, ctypes.c_int, ctypes.c_int, i32, vp, ctypes.POINTER(i32),
+                               ctypes.POINTER(i32), ctypes.POINTER(i32), pd, pd], ctypes.c_int),
             "odmd_update": ([vp, vp, vp], ctypes.c_int),
             "odmd_update_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32],
                                   ctypes.c_int),
@@ -112,11 +122,16 @@ class ODMD:
     snapshot type (defaults to the basis type, FP32 for BF16), torch stream
     (defaults to the current one) and an optional caller-owned uint8 device
     workspace.  pairs='general' creates a handle for pairs that need not
-    chain (``odmd_create_general``).
+    chain (``odmd_create_general``).  shape=(threads, rows_per_block,
+    max_blocks) sets the streaming pass's launch shape
+    (``odmd_create_shaped``; None keeps the library's default rule);
+    shape='latency' or 'throughput' takes the tuned shape of the shipped
+    table for that objective (``autotune.lookup``), the default where the
+    table has none.
     """
 
     def __init__(self, n: int, r_max: int, tol: float, basis: str = "f64", io: str | None = None,
-                 stream=None, workspace=None, pairs: str = "chained"):
+                 stream=None, workspace=None, pairs: str = "chained", shape=None):
         import torch
         self._torch = torch
         io = io or ("f32" if basis == "bf16" else basis)     # a BF16 basis takes FP32 snapshots
@@ -134,19 +149,34 @@ class ODMD:
         if pairs not in ("chained", "general"):
             raise ValueError("pairs must be 'chained' or 'general'")
         self.pairs = pairs
-        name = "odmd_create_ex" if pairs == "chained" else "odmd_create_general"
-        _check(getattr(lib(), name)(self.n, self.r_max, float(tol), bt, it,
-                                    ctypes.c_void_p(stream.cuda_stream), ws, wsb,
-                                    ctypes.byref(h)), name)
+        if isinstance(shape, str):
+            from . import autotune
+            shape = autotune.lookup(self.n, self.r_max, basis, io, objective=shape)
+        self.shape = shape
+        if shape is not None:
+            t, rpb, cap = (int(v) for v in shape)
+            _check(lib().odmd_create_shaped(self.n, self.r_max, float(tol), bt, it,
+                                            ctypes.c_void_p(stream.cuda_stream), t, rpb, cap,
+                                            int(pairs == "general"), ws, wsb, ctypes.byref(h)),
+                   "odmd_create_shaped")
+        else:
+            name = "odmd_create_ex" if pairs == "chained" else "odmd_create_general"
+            _check(getattr(lib(), name)(self.n, self.r_max, float(tol), bt, it,
+                                        ctypes.c_void_p(stream.cuda_stream), ws, wsb,
+                                        ctypes.byref(h)), name)
         self._h = h
         self._workspace = workspace
 
     @staticmethod
     def state_bytes(n: int, r_max: int, basis: str = "f64", io: str | None = None,
-                    pairs: str = "chained") -> int:
+                    pairs: str = "chained", shape=None) -> int:
         io = io or ("f32" if basis == "bf16" else basis)
         bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
         it = {"f64": F64, "f32": F32}[io]
+        if shape is not None:
+            t, rpb, cap = (int(v) for v in shape)
+            return int(lib().odmd_state_bytes_shaped(int(n), int(r_max), bt, it, t, rpb, cap,
+                                                     int(pairs == "general")))
         fn = lib().odmd_state_bytes if pairs == "chained" else lib().odmd_state_bytes_general
         return int(fn(int(n), int(r_max), bt, it))
 
@@ -283,3 +313,32 @@ def update_batch_ptrs(handles: np.ndarray, xptrs: np.ndarray, yptrs: np.ndarray)
     vpp = ctypes.POINTER(ctypes.c_void_p)
     _check(lib().odmd_update_batch(h.ctypes.data_as(vpp), x.ctypes.data_as(vpp),
                                    y.ctypes.data_as(vpp), count), "odmd_update_batch")
+
+
+def default_shape(n: int) -> tuple[int, int, int]:
+    """The library's default pass launch shape for n (``odmd_default_shape``)."""
+    t, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().odmd_default_shape(int(n), ctypes.byref(t), ctypes.byref(r), ctypes.byref(c)),
+           "odmd_default_shape")
+    return t.value, r.value, c.value
+
+
+def autotune(n: int, r_max: int, basis: str = "f64", io: str | None = None, streams: int = 1,
+             stream=None):
+    """Time the candidate pass launch shapes (``odmd_autotune``).
+
+    Returns ((threads, rows_per_block, max_blocks), us_best, us_default).
+    """
+    import torch
+    io = io or ("f32" if basis == "bf16" else basis)
+    bt = {"f64": F64, "f32": F32, "bf16": BF16}[basis]
+    it = {"f64": F64, "f32": F32}[io]
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    t, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    best, dflt = ctypes.c_double(), ctypes.c_double()
+    _check(lib().odmd_autotune(int(n), int(r_max), bt, it, int(streams),
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(t), ctypes.byref(r),
+                               ctypes.byref(c), ctypes.byref(best), ctypes.byref(dflt)),
+           "odmd_autotune")
+    return (t.value, r.value, c.value), best.value, dflt.value

@@ -60,6 +60,7 @@ class _Stream:
     workspace: object = None
     queue: Deque[Request] = dataclasses.field(default_factory=collections.deque)
     closing: bool = False
+    shape: Optional[tuple] = None     # pass launch shape; None: the library default
 
 
 class Server:
@@ -89,14 +90,20 @@ class Server:
         self.batch_sizes: List[int] = []
 
     # ---- streams -------------------------------------------------------
-    def open(self, sid: int, n: int, r_max: int, tol: float, basis: str = "f32") -> bool:
-        """Register a stream; returns True if it was admitted at once."""
+    def open(self, sid: int, n: int, r_max: int, tol: float, basis: str = "f32",
+             shape=None) -> bool:
+        """Register a stream; returns True if it was admitted at once.
+
+        shape: (threads, rows_per_block, max_blocks) of the stream's pass
+        (a tuned one), or None for the library's default."""
         if sid in self.streams:
             raise ValueError(f"stream {sid} already open")
-        nbytes = int(self.B.ODMD.state_bytes(n, r_max, basis))
+        kw = {} if shape is None else {"shape": tuple(shape)}
+        nbytes = int(self.B.ODMD.state_bytes(n, r_max, basis, **kw))
         if nbytes <= 0 or nbytes > self.budget:
             raise ValueError(f"stream {sid} cannot fit the budget ({nbytes} bytes)")
-        st = _Stream(sid, int(n), int(r_max), float(tol), basis, nbytes)
+        st = _Stream(sid, int(n), int(r_max), float(tol), basis, nbytes,
+                     shape=None if shape is None else tuple(shape))
         self.streams[sid] = st
         self.waiting.append(st)
         self._admit()
@@ -114,7 +121,8 @@ class Server:
             st = self.waiting.popleft()
             ws = self.torch.empty(st.bytes + 256, dtype=self.torch.uint8, device="cuda")
             st.workspace = ws
-            st.model = self.B.ODMD(st.n, st.r_max, st.tol, basis=st.basis, workspace=ws)
+            kw = {} if st.shape is None else {"shape": st.shape}
+            st.model = self.B.ODMD(st.n, st.r_max, st.tol, basis=st.basis, workspace=ws, **kw)
             self.used += st.bytes
             self.peak_used = max(self.peak_used, self.used)
 

@@ -123,3 +123,51 @@ def test_product_never_reaches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), f
                 assert "odmd_oracle" not in text, f
+
+
+@needs_lib
+def test_launch_shape_entry_points_are_host_checked():
+    L = B.lib()
+    t, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.odmd_default_shape(160000, ctypes.byref(t), ctypes.byref(r), ctypes.byref(c)) == 0
+    assert (t.value, r.value, c.value) == (512, 256, 256)
+    assert L.odmd_default_shape(131071, ctypes.byref(t), ctypes.byref(r), ctypes.byref(c)) == 0
+    assert (t.value, r.value, c.value) == (256, 512, 512)
+    assert L.odmd_default_shape(0, ctypes.byref(t), ctypes.byref(r), ctypes.byref(c)) == 1
+    assert L.odmd_default_shape(10, None, ctypes.byref(r), ctypes.byref(c)) == 1
+    # the default shape's bytes equal the plain entry points'
+    for n in (100, 160000):
+        d = B.default_shape(n)
+        assert L.odmd_state_bytes_shaped(n, 16, B.F32, B.F32, *d, 0) == \
+            L.odmd_state_bytes(n, 16, B.F32, B.F32)
+        assert L.odmd_state_bytes_shaped(n, 16, B.F64, B.F64, *d, 1) == \
+            L.odmd_state_bytes_general(n, 16, B.F64, B.F64)
+    # more workgroups, more partial-sum records
+    assert L.odmd_state_bytes_shaped(160000, 16, B.F64, B.F64, 256, 16, 65536, 0) > \
+        L.odmd_state_bytes_shaped(160000, 16, B.F64, B.F64, 256, 16, 1, 0)
+    bad = [(384, 256, 256, 0), (128, 256, 256, 0), (512, 8, 256, 0), (512, 24, 256, 0),
+           (512, 1 << 25, 256, 0), (512, 256, 0, 0), (512, 256, 65537, 0), (512, 256, 256, 2)]
+    h = ctypes.c_void_p(12345)
+    for shape in bad:
+        assert L.odmd_state_bytes_shaped(1000, 8, B.F64, B.F64, *shape) == 0, shape
+        assert L.odmd_create_shaped(1000, 8, 1e-8, B.F64, B.F64, None, *shape, None, 0,
+                                    ctypes.byref(h)) == 1, shape
+        assert h.value is None
+    # the size and type checks of odmd_create_ex still apply
+    assert L.odmd_create_shaped(1000, 65, 1e-8, B.F64, B.F64, None, 512, 256, 256, 0, None, 0,
+                                ctypes.byref(h)) == 1
+    assert L.odmd_create_shaped(1000, 8, 1e-8, B.F64, B.F64, None, 512, 256, 256, 0, None, 0,
+                                None) == 1
+
+
+@needs_lib
+def test_autotune_rejects_bad_arguments_before_device_use():
+    L = B.lib()
+    t, r, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    b, d = ctypes.c_double(), ctypes.c_double()
+    outs = [ctypes.byref(v) for v in (t, r, c, b, d)]
+    for n, rmax, basis, io, streams in [(0, 8, B.F64, B.F64, 1), (100, 65, B.F64, B.F64, 1),
+                                        (100, 8, B.F64, B.F32, 1), (100, 8, B.F64, B.F64, 0),
+                                        (100, 8, B.F64, B.F64, 1025)]:
+        assert L.odmd_autotune(n, rmax, basis, io, streams, None, *outs) == 1
+    assert L.odmd_autotune(100, 8, B.F64, B.F64, 1, None, None, *outs[1:]) == 1

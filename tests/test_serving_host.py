@@ -50,15 +50,16 @@ class FakeBackend:
         class ODMD:
             _next = itertools.count(1)
 
-            def __init__(self, n, r_max, tol, basis="f32", workspace=None):
-                self.n, self.id = n, next(ODMD._next)
+            def __init__(self, n, r_max, tol, basis="f32", workspace=None, shape=None):
+                self.n, self.id, self.shape = n, next(ODMD._next), shape
                 self.handle = type("H", (), {"value": self.id})()
                 B.live.add(self.id)
                 B.models[self.id] = self
 
             @staticmethod
-            def state_bytes(n, r_max, basis="f32", io=None):
-                return 8 * n * r_max
+            def state_bytes(n, r_max, basis="f32", io=None, shape=None):
+                # a shape with more workgroups holds more partial-sum records
+                return 8 * n * r_max + (0 if shape is None else 1024 * shape[2])
 
             def predict(self, steps):
                 B.log.append(("predict", self.id, steps))
@@ -148,3 +149,13 @@ def test_blocked_admission_is_reported():
     S.submit_update(2, _Ptr(), _Ptr())
     with pytest.raises(RuntimeError):
         S.drain()
+
+
+def test_stream_shapes_reach_the_handles():
+    S, B = make(budget=10 ** 9)
+    S.open(0, 100, 8, 1e-8)
+    S.open(1, 100, 8, 1e-8, shape=(256, 1024, 512))
+    assert B.models[S.streams[0].model.id].shape is None
+    assert B.models[S.streams[1].model.id].shape == (256, 1024, 512)
+    # the budget counts the shaped stream's own bytes
+    assert S.used == 2 * 8 * 100 * 8 + 1024 * 512
