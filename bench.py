@@ -18,7 +18,9 @@ and end timestamps), against 8 TB/s; the measured HBM traffic per pass
 comes from the committed rocprofv3 counter summary), p50/p99 device latency
 of one update (pass start to core end), a plain device-copy rate, S =
 8/32/128 concurrent n = 160k streams through the batched update, the
-256-stream FP32 batched form against a per-stream FP64 loop, the serving
+256-stream FP32 batched form against a per-stream FP64 loop (default and
+tuned launch shapes), the same mix stepped by a plan and by HIP-graph
+replay of the plan's launch, the serving
 loop at swept request rates, general (unchained) pairs, the hybrid
 full-order/DMD workflow, the n = 6,000,000 precision form (FP64, FP32,
 BF16), and the CPU oracle timed on a bounded sample on this host (all
@@ -520,6 +522,90 @@ def many_streams(torch):
     return res
 
 
+def graph_section(torch):
+    """The 256-stream FP32 mix of the many-stream section (tuned shapes),
+    each stream fed from two fixed snapshot buffers that one multi-tensor
+    copy refills before every step (pair k reads buffer k mod 2, then
+    buffer k+1 mod 2), advanced three ways on one stream: odmd_update_batch,
+    the plan launched eagerly (odmd_plan_launch), and the plan's launch
+    replayed from a captured HIP graph.  Each figure includes the refill;
+    the final states of the three are compared bit for bit."""
+    from paper_2311_18715_amd import synth, autotune
+    from paper_2311_18715_amd.odmd import ODMD, Plan, handle_array, update_batch_ptrs
+    descs = synth.batched_streams(MANY_COUNT)
+    gens = [_DeviceStream(torch, n, rank, seed) for (n, rank, _, seed) in descs]
+    table = autotune.load_table()
+    shapes = [autotune.lookup(n, rmax, "f32", objective="throughput", table=table)
+              for (n, _, rmax, _) in descs]
+    S = torch.cuda.Stream()
+    kinds = ("update_batch", "plan", "graph")
+    models = {v: [ODMD(n, rmax, MANY_TOL, basis="f32", stream=S, shape=sh)
+                  for (n, _, rmax, _), sh in zip(descs, shapes)] for v in kinds}
+    bufs = {v: [[torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(2)]
+                for (n, _, _, _) in descs] for v in kinds}
+    H = handle_array(models["update_batch"])
+    ptr = [np.array([b[j].data_ptr() for b in bufs["update_batch"]], dtype=np.uint64) for j in (0, 1)]
+    plans = {v: [Plan(models[v], [b[j] for b in bufs[v]], [b[1 - j] for b in bufs[v]])
+                 for j in (0, 1)] for v in ("plan", "graph")}
+    S.synchronize()
+    graphs = []
+    for p in plans["graph"]:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=S):
+            p.launch()
+        graphs.append(g)
+
+    def step(v, k):
+        if v == "update_batch":
+            update_batch_ptrs(H, ptr[k % 2], ptr[(k + 1) % 2])
+        elif v == "plan":
+            plans["plan"][k % 2].launch()
+        else:
+            graphs[k % 2].replay()
+
+    total = MANY_WARM + MANY_STEPS
+    elapsed = {v: 0.0 for v in kinds}
+    timed = 0
+    for k0 in range(0, total, MANY_CHUNK):
+        T = min(MANY_CHUNK, total - k0)
+        X32 = [g.chunk(k0, T + 1).float() for g in gens]
+        torch.cuda.synchronize()             # made on the current stream, read on S
+        for v in kinds:
+            with torch.cuda.stream(S):
+                S.synchronize()
+                t0 = time.perf_counter()
+                for j in range(T):
+                    k = k0 + j
+                    if k == 0:
+                        torch._foreach_copy_([b[0] for b in bufs[v]], [x[0] for x in X32])
+                    torch._foreach_copy_([b[(k + 1) % 2] for b in bufs[v]], [x[j + 1] for x in X32])
+                    step(v, k)
+                S.synchronize()
+                if k0 >= MANY_WARM:
+                    elapsed[v] += time.perf_counter() - t0
+        if k0 >= MANY_WARM:
+            timed += T
+        print(f"graph section: steps {k0}..{k0 + T - 1} done", file=sys.stderr, flush=True)
+        del X32
+    ref = models["update_batch"]
+    same = all(
+        np.array_equal(a.state()["atilde"], b.state()["atilde"]) and
+        np.array_equal(a.state()["atilde"], c.state()["atilde"]) and
+        torch.equal(a.basis_matrix(), c.basis_matrix())
+        for a, b, c in zip(ref, models["plan"], models["graph"]))
+    res = {"streams": MANY_COUNT, "steps_timed": timed, "warmup_steps": MANY_WARM,
+           "stream_updates_per_s": {v: round(MANY_COUNT * timed / elapsed[v], 1) for v in kinds},
+           "final_states_bitwise_equal": bool(same)}
+    graphs.clear()
+    for v in ("plan", "graph"):
+        for p in plans[v]:
+            p.close()
+    for v in kinds:
+        for m in models[v]:
+            m.close()
+    return res
+
+
 # serving form: Poisson arrivals over many streams, admission under a budget
 SERVE_COUNT, SERVE_N, SERVE_UPDATES, SERVE_PRED = 128, (1e4, 2e5), (100, 200), 100
 SERVE_RATES = (2e4, 6e4, 2e5)          # offered requests/s
@@ -625,6 +711,8 @@ def main():
                     help="run only the general-pair section and print it")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving section")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="run only the plan / HIP-graph section")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy MIB MiB once on the device (a reference "
                          "kernel of known traffic for hardware byte counters)")
@@ -643,6 +731,9 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_section(torch)}), flush=True)
+        return
+    if args.graph_only:
+        print(json.dumps({"graph_replay": graph_section(torch)}), flush=True)
         return
     if args.hybrid_only:
         print(json.dumps({"hybrid_heat_n160k": hybrid_section(torch)}), flush=True)
@@ -754,6 +845,8 @@ def main():
         del Xd, out
         torch.cuda.empty_cache()
         result["many_streams"] = many_streams(torch)
+        torch.cuda.empty_cache()
+        result["graph_replay"] = graph_section(torch)
         torch.cuda.empty_cache()
         result["serving"] = serving_section(torch)
         torch.cuda.empty_cache()

@@ -213,6 +213,39 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
                               int32_t count);
 
 /*
+ * Plans: one batched step (Sec. 2.3's rank-1 update of every handle, as
+ * odmd_update_batch) fixed once, so that it can be launched again and
+ * again with no host staging, host wait or allocation, and captured into
+ * a HIP graph (hipStreamBeginCapture on the handles' stream, or a
+ * framework's graph capture on that stream) and replayed.
+ *
+ * odmd_plan_create: hs, xs, ys, count as for odmd_update_batch (count >= 1,
+ *   one stream and device, no duplicates, chained handles only); the
+ *   pointers xs[i], ys[i] are fixed in the plan: the caller refills those
+ *   device buffers between launches, keeping each pair chained (e.g. two
+ *   plans over two buffers, used alternately: (A, B), then (B, A)).  The
+ *   plan copies its descriptor tables to the device here (synchronous).
+ *   Every pass of a plan is sized for the handle's full stored-column
+ *   capacity, since a graph cannot follow the live count; from then on
+ *   the handles size their other updates the same way (the host no longer
+ *   knows the count either).  Results equal odmd_update_batch's bit for
+ *   bit.  *plan is set to NULL on error; ODMD_EINVAL for invalid
+ *   arguments, ODMD_ENOMEM if the tables or side streams cannot be made.
+ * odmd_plan_launch: enqueue one step on the handles' stream (kernel
+ *   launches, and event records and waits between that stream and the
+ *   plan's own side streams, nothing else).  Asynchronous; errors latch in
+ *   the handles as for odmd_update.
+ * odmd_plan_destroy: wait for the stream, free the plan.  odmd_destroy of
+ *   a handle that a live plan holds returns ODMD_EINVAL.
+ */
+typedef struct odmd_plan_s* odmd_plan_t;
+
+odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* const* ys,
+                             int32_t count, odmd_plan_t* plan);
+odmd_status odmd_plan_launch(odmd_plan_t plan);
+odmd_status odmd_plan_destroy(odmd_plan_t plan);
+
+/*
  * Eigenpairs of A~ (synchronising).  cap: capacity of the output arrays
  * (eigenvalue count; V arrays hold cap*cap doubles).  Outputs (host):
  *   *r        current rank;
@@ -248,7 +281,8 @@ odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* ou
 /* Wait for the handle's stream; return and clear a latched error. */
 odmd_status odmd_sync(odmd_t h);
 
-/* Free the handle and (unless caller-owned) its device memory. */
+/* Free the handle and (unless caller-owned) its device memory; ODMD_EINVAL
+ * while a plan holds it. */
 odmd_status odmd_destroy(odmd_t h);
 
 const char* odmd_status_str(odmd_status s);

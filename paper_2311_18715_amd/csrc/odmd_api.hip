@@ -61,6 +61,11 @@ struct odmd_s {
   unsigned* fb_host = nullptr;
   unsigned* fb_dev = nullptr;
   unsigned seq = 0;
+  // Set once a plan holds the handle: plan launches (possibly replayed from
+  // a graph) advance the state without the host's count, so every later
+  // pass is sized for the full stored-column capacity.
+  bool full_bucket = false;
+  int plans = 0;                // live plans that hold the handle
 };
 
 namespace {
@@ -165,6 +170,7 @@ odmd_status copy_field(odmd_t h, T* dst, const T* src_dev, size_t count) {
 // issued since bounds them.  The bucket is a multiple of 8 and never exceeds
 // the tile capacity.
 int live_bucket(odmd_t h) {
+  if (h->full_bucket) return h->ct;
   const unsigned v = __atomic_load_n(h->fb_host, __ATOMIC_ACQUIRE);
   const unsigned lag = (h->seq - (v >> 8)) & 0xFFFFFFu;
   const int64_t bound = std::min<int64_t>(h->ct, (int64_t)(v & 0xFFu) + lag);
@@ -436,6 +442,34 @@ odmd_status launch_rollout(odmd_t h, int32_t steps, void* out) {
 }
 
 }  // namespace
+
+// ---- plans: a fixed batched step, launchable without host staging ----
+
+struct odmd_plan_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<odmd_t> hs;
+  void* dev = nullptr;          // PassDesc table, then the CoreArgs table
+  size_t pass_bytes = 0;
+  struct Launch { int first, nd, nblocks, threads, basis, rb; };
+  std::vector<Launch> launches;
+  int nside = 0;
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t fork = nullptr, join[NSIDE] = {};
+};
+
+static void plan_free(odmd_plan_t p) {
+  for (int i = 0; i < NSIDE; ++i) {
+    if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
+    if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->dev) (void)hipFree(p->dev);
+  (void)hipGetLastError();
+  for (odmd_t h : p->hs) --h->plans;
+  delete p;
+}
+
 
 extern "C" {
 
@@ -812,7 +846,7 @@ odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double*
 }
 
 odmd_status odmd_destroy(odmd_t h) {
-  if (!h) return ODMD_EINVAL;
+  if (!h || h->plans > 0) return ODMD_EINVAL;
   odmd_status s = ODMD_OK;
   if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
     s = ODMD_EDEVICE;
@@ -821,6 +855,126 @@ odmd_status odmd_destroy(odmd_t h) {
   if (h->fb_host && hipHostFree(h->fb_host) != hipSuccess) s = ODMD_EDEVICE;
   (void)hipGetLastError();
   delete h;
+  return s;
+}
+
+odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* const* ys,
+                             int32_t count, odmd_plan_t* plan) {
+  if (!plan) return ODMD_EINVAL;
+  *plan = nullptr;
+  if (!hs || !xs || !ys || count < 1) return ODMD_EINVAL;
+  std::unordered_set<odmd_t> seen;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i] || !xs[i] || !ys[i] || hs[i]->general) return ODMD_EINVAL;
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return ODMD_EINVAL;
+    if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
+  }
+  HIP_OK(hipSetDevice(hs[0]->device));
+  odmd_plan_s* p = new (std::nothrow) odmd_plan_s;
+  if (!p) return ODMD_ENOMEM;
+  p->device = hs[0]->device;
+  p->stream = hs[0]->stream;
+  // the same grouping and order as a batched update, with every pass sized
+  // for the full stored-column capacity
+  std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
+  for (int32_t i = 0; i < count; ++i)
+    groups[{hs[i]->threads, (int)hs[i]->basis, hs[i]->ct}].push_back(i);
+  p->pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
+  const size_t bytes = p->pass_bytes + (size_t)count * sizeof(CoreArgs);
+  std::vector<char> host(bytes, 0);
+  PassDesc* pd = reinterpret_cast<PassDesc*>(host.data());
+  CoreArgs* cd = reinterpret_cast<CoreArgs*>(host.data() + p->pass_bytes);
+  int k = 0;
+  for (auto& g : groups) {
+    std::stable_sort(g.second.begin(), g.second.end(), [&](int32_t a, int32_t b) {
+      return hs[a]->n * hs[b]->nblk > hs[b]->n * hs[a]->nblk;
+    });
+    odmd_plan_s::Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first)};
+    for (int32_t i : g.second) {
+      odmd_t h = hs[i];
+      PassDesc& d = pd[k++];
+      d = PassDesc{};
+      d.Us = h->Us;
+      d.x = xs[i];
+      d.y = ys[i];
+      d.partials = h->partials;
+      d.st = h->st;
+      d.n = h->n;
+      d.nblk = h->nblk;
+      d.ct = h->ct;
+      d.blk0 = L.nblocks;
+      L.nblocks += h->nblk;
+      ++L.nd;
+    }
+    p->launches.push_back(L);
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    odmd_t h = hs[i];
+    CoreArgs& c = cd[i];
+    c = CoreArgs{};   // fb stays null: a plan step reports nothing to the host
+    c.st = h->st;
+    c.partials = h->partials;
+    c.nblk = h->nblk;
+    c.r_max = h->r_max;
+    c.basis_f32 = h->basis != ODMD_F64;
+    c.jacobi_only = h->jacobi_only;
+    c.rb = h->ct;
+    c.ct = h->ct;
+  }
+  p->nside = p->launches.size() > 1 ? std::min<int>(NSIDE, (int)p->launches.size()) : 0;
+  bool ok = hipMalloc(&p->dev, bytes) == hipSuccess &&
+            hipMemcpy(p->dev, host.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && p->nside > 0) {
+    ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < p->nside; ++i)
+      ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming) == hipSuccess;
+  }
+  if (!ok) {
+    plan_free(p);
+    return ODMD_ENOMEM;
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    hs[i]->full_bucket = true;
+    ++hs[i]->plans;
+    p->hs.push_back(hs[i]);
+  }
+  *plan = p;
+  return ODMD_OK;
+}
+
+odmd_status odmd_plan_launch(odmd_plan_t p) {
+  if (!p) return ODMD_EINVAL;
+  HIP_OK(hipSetDevice(p->device));
+  const PassDesc* dpd = static_cast<const PassDesc*>(p->dev);
+  if (p->nside == 0) {
+    const odmd_plan_s::Launch& L = p->launches[0];
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb, p->stream));
+  } else {
+    HIP_OK(hipEventRecord(p->fork, p->stream));
+    for (int i = 0; i < p->nside; ++i) HIP_OK(hipStreamWaitEvent(p->side[i], p->fork, 0));
+    for (size_t i = 0; i < p->launches.size(); ++i) {
+      const odmd_plan_s::Launch& L = p->launches[i];
+      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb,
+                               p->side[i % p->nside]));
+    }
+    for (int i = 0; i < p->nside; ++i) {
+      HIP_OK(hipEventRecord(p->join[i], p->side[i]));
+      HIP_OK(hipStreamWaitEvent(p->stream, p->join[i], 0));
+    }
+  }
+  HIP_OK(launch_core_batch(
+      reinterpret_cast<const CoreArgs*>(static_cast<char*>(p->dev) + p->pass_bytes),
+      (int)p->hs.size(), p->stream));
+  return ODMD_OK;
+}
+
+odmd_status odmd_plan_destroy(odmd_plan_t p) {
+  if (!p) return ODMD_EINVAL;
+  odmd_status s = ODMD_OK;
+  if (hipSetDevice(p->device) != hipSuccess || hipStreamSynchronize(p->stream) != hipSuccess)
+    s = ODMD_EDEVICE;
+  plan_free(p);
   return s;
 }
 

@@ -26,6 +26,7 @@ EXPORTS = [
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
     "odmd_profile_samples", "odmd_create_general", "odmd_state_bytes_general",
     "odmd_default_shape", "odmd_create_shaped", "odmd_state_bytes_shaped", "odmd_autotune",
+    "odmd_plan_create", "odmd_plan_launch", "odmd_plan_destroy",
 ]
 
 
@@ -71,6 +72,10 @@ def lib() -> ctypes.CDLL:
                                     i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)], ctypes.c_int),
             "odmd_state_bytes_shaped": ([i64, i32, ctypes.c_int, ctypes.c_int, i32, i32, i32, i32],
                                         ctypes.c_size_t),
+            "odmd_plan_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
+                                  ctypes.POINTER(vp)], ctypes.c_int),
+            "odmd_plan_launch": ([vp], ctypes.c_int),
+            "odmd_plan_destroy": ([vp], ctypes.c_int),
             "odmd_autotune": ([i64, i32, ctypes.c_int, ctypes.c_int, i32, vp, ctypes.POINTER(i32),
                                ctypes.POINTER(i32), ctypes.POINTER(i32), pd, pd], ctypes.c_int),
             "odmd_update": ([vp, vp, vp], ctypes.c_int),
@@ -260,7 +265,8 @@ class ODMD:
     def close(self) -> None:
         if getattr(self, "_h", None):
             code = lib().odmd_destroy(self._h)
-            self._h = None
+            if code != 1:            # EINVAL: a live plan holds the handle, which stays valid
+                self._h = None
             _check(code, "odmd_destroy")
 
     def __del__(self):
@@ -277,6 +283,38 @@ def update_batch(models, xs, ys) -> None:
     X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
     Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
     _check(lib().odmd_update_batch(H, X, Y, n), "odmd_update_batch")
+
+
+class Plan:
+    """A fixed batched step (``odmd_plan_create``): the handles of ``models``
+    with the fixed snapshot buffers xs, ys (device tensors the caller
+    refills between launches).  ``launch()`` enqueues one step on the
+    handles' stream; capturing ``launch()`` in a torch.cuda.CUDAGraph on
+    that stream gives a graph that replays the step."""
+
+    def __init__(self, models, xs, ys):
+        n = len(models)
+        H = (ctypes.c_void_p * n)(*[m.handle for m in models])
+        X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
+        Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
+        p = ctypes.c_void_p()
+        _check(lib().odmd_plan_create(H, X, Y, n, ctypes.byref(p)), "odmd_plan_create")
+        self._p = p
+        self._keep = (list(models), list(xs), list(ys))    # the plan points into these
+
+    def launch(self) -> None:
+        _check(lib().odmd_plan_launch(self._p), "odmd_plan_launch")
+
+    def close(self) -> None:
+        if self._p is not None and self._p.value:
+            _check(lib().odmd_plan_destroy(self._p), "odmd_plan_destroy")
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def predict_batch(models, steps):

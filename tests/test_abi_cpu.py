@@ -171,3 +171,17 @@ def test_autotune_rejects_bad_arguments_before_device_use():
                                         (100, 8, B.F64, B.F64, 1025)]:
         assert L.odmd_autotune(n, rmax, basis, io, streams, None, *outs) == 1
     assert L.odmd_autotune(100, 8, B.F64, B.F64, 1, None, None, *outs[1:]) == 1
+
+
+@needs_lib
+def test_plan_entry_points_check_arguments_on_the_host():
+    L = B.lib()
+    p = ctypes.c_void_p(12345)
+    assert L.odmd_plan_create(None, None, None, 1, ctypes.byref(p)) == 1
+    assert p.value is None
+    assert L.odmd_plan_create(None, None, None, 1, None) == 1
+    H = (ctypes.c_void_p * 1)(None)
+    assert L.odmd_plan_create(H, H, H, 0, ctypes.byref(p)) == 1     # count >= 1
+    assert L.odmd_plan_create(H, H, H, 1, ctypes.byref(p)) == 1     # NULL handle
+    assert L.odmd_plan_launch(None) == 1
+    assert L.odmd_plan_destroy(None) == 1
