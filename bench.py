@@ -358,42 +358,10 @@ def concurrent_streams(torch, Xd, bytes_upd):
 MANY_COUNT, MANY_WARM, MANY_STEPS, MANY_CHUNK, MANY_TOL = 256, 40, 100, 20, 1e-8
 
 
-class _DeviceStream:
-    """Planted linear stream x_k = Re(sum_j phi_j lam_j^k b_j) generated on the
-    device: Gaussian i.i.d. modes from a seeded torch generator, eigenvalues
-    and amplitudes from the host PCG64 recipe of synth.random_planted."""
-
-    def __init__(self, torch, n, rank, seed):
-        import math
-        g = np.random.Generator(np.random.PCG64(seed))
-        npair, nreal = rank // 2, rank % 2
-        p = npair + nreal
-        lam = np.empty(p, np.complex128)
-        for j in range(npair):
-            lam[j] = g.uniform(0.97, 1.0) * np.exp(1j * g.uniform(2 * np.pi * 0.005, 2 * np.pi * 0.1))
-        if nreal:
-            lam[p - 1] = g.uniform(0.97, 1.0)
-        amp = (g.standard_normal(p) + 1j * g.standard_normal(p)) / math.sqrt(2.0)
-        if nreal:
-            amp[p - 1] = amp[p - 1].real
-        tg = torch.Generator(device="cuda")
-        tg.manual_seed(int(seed))
-        self.re = torch.randn((p, n), generator=tg, device="cuda", dtype=torch.float64) / math.sqrt(2 * n)
-        self.im = torch.randn((p, n), generator=tg, device="cuda", dtype=torch.float64) / math.sqrt(2 * n)
-        if nreal:
-            self.re[p - 1] *= math.sqrt(2.0)
-            self.im[p - 1] = 0.0
-        self.lam, self.amp, self.n = lam, amp, n
-        self.planted = np.concatenate([lam[:npair], np.conj(lam[:npair]), lam[npair:]])
-        self.torch = torch
-
-    def chunk(self, k0, count):
-        """Snapshots k0 .. k0+count-1 as rows of a (count, n) FP64 tensor."""
-        k = np.arange(k0, k0 + count)[:, None]
-        C = self.amp[None, :] * self.lam[None, :] ** k
-        cre = self.torch.from_numpy(np.ascontiguousarray(C.real)).cuda()
-        cim = self.torch.from_numpy(np.ascontiguousarray(C.imag)).cuda()
-        return cre @ self.re - cim @ self.im
+def _DeviceStream(torch, n, rank, seed):
+    """Planted stream generated on the device (synth.DevicePlanted)."""
+    from paper_2311_18715_amd import synth
+    return synth.DevicePlanted(torch, n, rank, seed)
 
 
 def _rel_eig_diff(ref, got):

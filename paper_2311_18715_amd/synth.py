@@ -263,3 +263,45 @@ class DeviceSnapshots:
                                           dtype=X.dtype)
         return X
 
+
+class DevicePlanted:
+    """The many-stream planted recipe (as ``random_planted``: |lam| in
+    U[0.97, 1], arg in U[2pi 0.005, 2pi 0.1], b ~ CN(0, 1), an odd rank with
+    one real mode) with the Gaussian mode vectors drawn on the device from a
+    torch generator seeded by ``seed``, for streams too large or too many to
+    build on the host.  Eigenvalues and amplitudes come from the host
+    PCG64(seed) draws; ``planted`` lists the rank's eigenvalues.  No noise."""
+
+    def __init__(self, torch, n: int, rank: int, seed: int, device: str = "cuda",
+                 dtype=None):
+        g = np.random.Generator(np.random.PCG64(seed))
+        npair, nreal = rank // 2, rank % 2
+        p = npair + nreal
+        lam = np.empty(p, np.complex128)
+        for j in range(npair):
+            lam[j] = g.uniform(0.97, 1.0) * np.exp(1j * g.uniform(2 * np.pi * 0.005, 2 * np.pi * 0.1))
+        if nreal:
+            lam[p - 1] = g.uniform(0.97, 1.0)
+        amp = (g.standard_normal(p) + 1j * g.standard_normal(p)) / math.sqrt(2.0)
+        if nreal:
+            amp[p - 1] = amp[p - 1].real
+        dtype = dtype or torch.float64
+        tg = torch.Generator(device=device)
+        tg.manual_seed(int(seed))
+        self.re = torch.randn((p, n), generator=tg, device=device, dtype=dtype) / math.sqrt(2 * n)
+        self.im = torch.randn((p, n), generator=tg, device=device, dtype=dtype) / math.sqrt(2 * n)
+        if nreal:
+            self.re[p - 1] *= math.sqrt(2.0)
+            self.im[p - 1] = 0.0
+        self.lam, self.amp, self.n, self.device = lam, amp, n, device
+        self.planted = np.concatenate([lam[:npair], np.conj(lam[:npair]), lam[npair:]])
+        self.torch = torch
+
+    def chunk(self, k0: int, count: int):
+        """Snapshots k0 .. k0+count-1 as rows of a (count, n) tensor."""
+        k = np.arange(k0, k0 + count)[:, None]
+        C = self.amp[None, :] * self.lam[None, :] ** k
+        t = self.torch
+        cre = t.from_numpy(np.ascontiguousarray(C.real)).to(self.device, self.re.dtype)
+        cim = t.from_numpy(np.ascontiguousarray(C.imag)).to(self.device, self.re.dtype)
+        return cre @ self.re - cim @ self.im
