@@ -26,6 +26,8 @@
 namespace odmd {
 
 constexpr int LDK = MMAX + 1;        // LDS leading dimension of the core
+constexpr int LDQ = RMAX + 1;        // LDS row stride of Q (rows read by 16 lanes at once
+                                     // fall in distinct banks)
 constexpr int MAX_SWEEPS = 40;
 
 // Round-robin (circle) schedule: in round k of Mp-1 rounds, pair i of Mp/2.
@@ -459,6 +461,31 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
+// One 16 x 16 FP64 tile D = sum_{k < K} A(row, k) B(k, col) on the matrix
+// cores, in the 16x16x4 operand layout: lane l holds row (and column) l % 16
+// and k-step offset l / 16, and reads its elements at pa[k * sa] and
+// pb[k * sb].  Every load is issued (a lane whose row or column is out of
+// range, use_a / use_b false, or whose k is past K, reads k = 0 of a valid
+// pointer and passes zero), so the loop has no divergent branches; two
+// accumulators over alternate k-steps keep two products in flight.
+__device__ __forceinline__ d4_t mfma_tile(const double* pa, int sa, bool use_a, const double* pb,
+                                          int sb, bool use_b, int K, int l) {
+  d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
+  const int kl = l >> 4;
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    const int ka = k0 + kl, kb = ka + 4;
+    const bool va = ka < K, vb = kb < K;
+    const int ia = va ? ka : 0, ib = vb ? kb : 0;
+    const double a0 = pa[ia * sa], b0 = pb[ia * sb];
+    const double a1 = pa[ib * sa], b1 = pb[ib * sb];
+    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(use_a && va ? a0 : 0.0, use_b && va ? b0 : 0.0, d0,
+                                              0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(use_a && vb ? a1 : 0.0, use_b && vb ? b1 : 0.0, d1,
+                                              0, 0, 0);
+  }
+  return d0 + d1;
+}
+
 // General pairs (B = Y W held as T R): the right-factor bookkeeping of one
 // update, in place of the chained pairs' shifted product.  With
 // U' = [U q] U_k and B' = [B y] V_k (kept columns),
@@ -612,13 +639,46 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __shared__ int flag;
   __shared__ double sc[8];
   __shared__ int si[4];
-  __shared__ double sQ[CMAX * RMAX];   // Q (m x r), row c at sQ + c*RMAX
+  __shared__ double sQ[CMAX * LDQ];    // Q (m x r), row c at sQ + c*LDQ
+  static_assert(MMAX * MMAX <= CMAX * LDQ, "sQ holds E V_k for general pairs");
 
   const int tid = threadIdx.x;
   const int r = st->r, m = st->m, refolded = st->refold;
 
   // 0. stage Q and the shifted product C in LDS with coalesced passes, all
-  //    of a thread's loads issued before its first store
+  //    of a thread's loads issued before its first store, and
+  // 1. fixed-order reduction of the per-workgroup partial sums (compact
+  //    records of pwc values, read as 16-byte pairs; sV is scratch here).
+  //    The slot count does not depend on the record length, so every value
+  //    is summed in the same order whatever bucket the pass ran with (x.x of
+  //    a pair is then bit-equal to y.y of the pair before it).  A thread's
+  //    records are read RU at a time, the first RU with Q and C, so that
+  //    their latencies overlap.
+  const int pwc = 2 * c.rb + 4, pw2 = pwc / 2;
+  constexpr int nslot = CORE_THREADS / (PW / 2);
+  constexpr int RU = 10;
+  const bool rth = tid < nslot * pw2;
+  const int rg = rth ? tid % pw2 : 0, rsl = rth ? tid / pw2 : 0;
+  const double2* __restrict__ rec = reinterpret_cast<const double2*>(c.partials);
+  double2 rv[RU];
+  double ax = 0.0, ay = 0.0;
+  // records rsl + (ch RU + i) nslot; past nblk a valid record is read and
+  // not added
+  auto load_records = [&](int ch) {
+#pragma unroll
+    for (int i = 0; i < RU; ++i) {
+      const int b = rsl + (ch * RU + i) * nslot;
+      rv[i] = rec[(int64_t)(b < c.nblk ? b : 0) * (PW / 2) + rg];
+    }
+  };
+  auto add_records = [&](int ch) {
+#pragma unroll
+    for (int i = 0; i < RU; ++i)
+      if (rsl + (ch * RU + i) * nslot < c.nblk) {
+        ax += rv[i].x;
+        ay += rv[i].y;
+      }
+  };
   {
     constexpr int NQ = (CMAX * RMAX + CORE_THREADS - 1) / CORE_THREADS;
     constexpr int NC = (RMAX * RMAX + CORE_THREADS - 1) / CORE_THREADS;
@@ -635,33 +695,25 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       const int j = idx % RMAX, k = idx / RMAX;
       cv[i] = (j < r && k < r) ? st->C[idx] : 0.0;
     }
+    load_records(0);
 #pragma unroll
-    for (int i = 0; i < NQ; ++i)
-      if (tid + i * CORE_THREADS < CMAX * RMAX) sQ[tid + i * CORE_THREADS] = qv[i];
+    for (int i = 0; i < NQ; ++i) {
+      const int idx = tid + i * CORE_THREADS;
+      if (idx < CMAX * RMAX) sQ[idx / RMAX * LDQ + idx % RMAX] = qv[i];
+    }
 #pragma unroll
     for (int i = 0; i < NC; ++i) sC[tid + i * CORE_THREADS] = cv[i];
   }
   if (tid < RMAX) sw[tid] = tid < r ? st->w[tid] : 0.0;
-
-  // 1. fixed-order reduction of the per-workgroup partial sums (compact
-  //    records of pwc values, read as 16-byte pairs; sV is scratch here).
-  //    The slot count does not depend on the record length, so every value
-  //    is summed in the same order whatever bucket the pass ran with (x.x of
-  //    a pair is then bit-equal to y.y of the pair before it).
   {
-    const int pwc = 2 * c.rb + 4, pw2 = pwc / 2;
-    constexpr int nslot = CORE_THREADS / (PW / 2);
-    if (tid < nslot * pw2) {
-      const int g = tid % pw2, sl = tid / pw2;
-      double ax = 0.0, ay = 0.0;
-#pragma unroll 8
-      for (int b = sl; b < c.nblk; b += nslot) {
-        const double2 v = reinterpret_cast<const double2*>(c.partials + (int64_t)b * PW)[g];
-        ax += v.x;
-        ay += v.y;
-      }
-      sV[sl * pwc + 2 * g] = ax;
-      sV[sl * pwc + 2 * g + 1] = ay;
+    add_records(0);
+    for (int ch = 1; ch * RU * nslot < c.nblk; ++ch) {   // uniform
+      load_records(ch);
+      add_records(ch);
+    }
+    if (rth) {
+      sV[rsl * pwc + 2 * rg] = ax;
+      sV[rsl * pwc + 2 * rg + 1] = ay;
     }
     __syncthreads();
     if (tid < pwc) {
@@ -713,8 +765,8 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     double a2 = 0.0, b2 = 0.0;
 #pragma unroll 8
     for (int c0 = 0; c0 < m; ++c0) {
-      a2 += sQ[c0 * RMAX + tid] * tot[P_SUE + c0];
-      b2 += sQ[c0 * RMAX + tid] * tot[P_SUY + c0];
+      a2 += sQ[c0 * LDQ + tid] * tot[P_SUE + c0];
+      b2 += sQ[c0 * LDQ + tid] * tot[P_SUY + c0];
     }
     p2[tid] = a2;
     pyr[tid] = b2;
@@ -724,7 +776,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   if (refolded) {
     for (int idx = tid; idx < CMAX * RMAX; idx += CORE_THREADS) {
       const int c0 = idx / RMAX, j = idx % RMAX;
-      sQ[idx] = (c0 == j && j < r) ? 1.0 : 0.0;
+      sQ[c0 * LDQ + j] = (c0 == j && j < r) ? 1.0 : 0.0;
     }
   }
   const int meff = refolded ? r : m;   // stored columns U is built from; e sits in column meff
@@ -905,7 +957,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       double t = 0.0;
       if (row < CMAX) {
         if (row < m || refolded)
-          for (int j = ql; j < r; j += 16) t += sQ[row * RMAX + j] * p2[j];
+          for (int j = ql; j < r; j += 16) t += sQ[row * LDQ + j] * p2[j];
         t = row_sum(t);
         if (ql == 0) red[row] = t;
       } else {
@@ -934,15 +986,9 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       d4_t d = {0.0, 0.0, 0.0, 0.0};
       if (tile < ntile) {
         const int c0 = 16 * (tile / ncb), k0 = 16 * (tile % ncb);
-        const int kb = k0 + (l & 15);
+        const int kb = k0 + (l & 15), ca = c0 + (l & 15);
         const int pk = kb < rn ? perm[kb] : 0;
-        for (int j0 = 0; j0 < r; j0 += 4) {
-          const int j = j0 + (l >> 4);
-          const int ca = c0 + (l & 15);
-          const double av = (j < r && ca < CMAX) ? sQ[ca * RMAX + j] : 0.0;
-          const double bv = (j < r && kb < rn) ? sA[pk * LDK + j] : 0.0;
-          d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
-        }
+        d = mfma_tile(sQ + (ca < CMAX ? ca : 0) * LDQ, 1, ca < CMAX, sA + pk * LDK, 1, kb < rn, r, l);
         // element v of lane l: row c0 + 4 v + l/16, column k0 + l%16
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -965,7 +1011,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   for (int row = qw; row < CMAX; row += CORE_THREADS / 16) {
     double t = 0.0;
     if (row < meff) {
-      for (int j = ql; j < r; j += 16) t += sQ[row * RMAX + j] * pvec[j];
+      for (int j = ql; j < r; j += 16) t += sQ[row * LDQ + j] * pvec[j];
     } else if (row == meff && grow) {
       for (int k = ql; k < rn; k += 16) t += urk[k] * pyn[k];
     }
@@ -1005,16 +1051,9 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       const int i0 = 16 * (tile % ntr), b0 = 16 * (tile / ntr);
       const int ia = i0 + (l & 15), bb = b0 + (l & 15);
       const int pb = bb < rn ? perm[bb] : 0;
-      d4_t d = {0.0, 0.0, 0.0, 0.0};
-      for (int j0 = 0; j0 < r; j0 += 4) {
-        const int j = j0 + (l >> 4);
-        double av = 0.0, bv = 0.0;
-        if (j < r) {
-          av = ia < r ? sC[j * RMAX + ia] : (ia == r ? sw[j] : 0.0);
-          bv = bb < rn ? sV[pb * LDK + j] : 0.0;
-        }
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
-      }
+      // row ia of E: row ia of C (stride RMAX along j) or w
+      const d4_t d = mfma_tile(ia < r ? sC + ia : sw, ia < r ? RMAX : 1, ia <= r, sV + pb * LDK, 1,
+                               bb < rn, r, l);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 4 * v + (l >> 4);
@@ -1033,16 +1072,8 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       const int i0 = 16 * (tile % nt), j0 = 16 * (tile / nt);
       const int ia = i0 + (l & 15), jb = j0 + (l & 15);
       const int pa = ia < rn ? perm[ia] : 0;
-      d4_t d = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < M; k0 += 4) {
-        const int k = k0 + (l >> 4);
-        double av = 0.0, bv = 0.0;
-        if (k < M) {
-          av = ia < rn ? sV[pa * LDK + k] : 0.0;
-          bv = jb < rn ? sA[jb * LDK + k] : 0.0;
-        }
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
-      }
+      const d4_t d = mfma_tile(sV + pa * LDK, 1, ia < rn, sA + (jb < rn ? jb : 0) * LDK, 1, jb < rn,
+                               M, l);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 4 * v + (l >> 4);
