@@ -197,7 +197,11 @@ odmd_status odmd_autotune(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype
  * chain: x_k must equal, element for element, the x_k1 of the previous
  * accepted update; otherwise the update is skipped and ODMD_ESEQ is
  * latched.  A general-pair handle (odmd_create_general) takes any pair.
- * Asynchronous.
+ * Asynchronous.  It may be captured into a HIP graph (stream capture on the
+ * handle's stream): the graph then reads the same x_k, x_k1 buffers at
+ * every replay, and from the capture on the handle sizes its passes for
+ * the full stored-column capacity, as under a plan (results unchanged);
+ * captured updates record no profiling events.
  */
 odmd_status odmd_update(odmd_t h, const void* x_k, const void* x_k1);
 
@@ -207,7 +211,9 @@ odmd_status odmd_update(odmd_t h, const void* x_k, const void* x_k1);
  * duplicates are not allowed.  hs, xs, ys: host arrays of length count;
  * xs[i], ys[i] are device pointers as in odmd_update.  Results are
  * identical, bit for bit, to calling odmd_update on each handle.
- * Asynchronous.
+ * Asynchronous.  Its descriptor tables are staged through host memory, so
+ * it returns ODMD_EINVAL while the stream is being captured: capture a
+ * plan's launch instead (odmd_plan_create below).
  */
 odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* const* ys,
                               int32_t count);
@@ -263,7 +269,8 @@ odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double*
  * last x_k1 (Sec. 2.3, u(t) = Phi Lambda^(t/dt) Phi^+ u(0), anchored at the
  * last snapshot: Phi^+ u(0) = V^-1 U^T x_a).  out: device, steps x n, row
  * k-1 holds state a+k, io type, row-major (row stride n).  steps >= 1.
- * Asynchronous (the eigendecomposition it may need runs on the device).
+ * Asynchronous (the eigendecomposition it may need runs on the device);
+ * kernel launches only, so it may be captured into a HIP graph.
  */
 odmd_status odmd_predict(odmd_t h, int32_t steps, void* out);
 
@@ -274,7 +281,9 @@ odmd_status odmd_predict(odmd_t h, int32_t steps, void* out);
  * device and HIP stream, steps[i] >= 1, outs[i] as odmd_predict's out (host
  * arrays of count entries, read during the call).  Asynchronous; results
  * equal those of odmd_predict bit for bit.  ODMD_EINVAL for a NULL entry,
- * steps < 1, a repeated handle or handles on different streams.
+ * steps < 1, a repeated handle or handles on different streams, and while
+ * the stream is being captured (the handle table is staged through host
+ * memory; odmd_predict itself may be captured).
  */
 odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* outs, int32_t count);
 

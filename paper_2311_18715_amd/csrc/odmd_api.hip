@@ -177,9 +177,24 @@ int live_bucket(odmd_t h) {
   return std::max(8, col_bucket((int)bound));
 }
 
+// True while the stream is being captured into a graph.
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
 odmd_status launch_update(odmd_t h, const void* x, const void* y) {
+  // a captured update is replayed without the host's count of stored
+  // columns: from here on the passes are sized for the full capacity (and
+  // no timing events are recorded into the graph)
+  const bool cap = capturing(h->stream);
+  if (cap) h->full_bucket = true;
   hipEvent_t* ev = nullptr;
-  if (h->prof) {
+  if (h->prof && !cap) {
     if (h->ev_used + EV_PER_UPDATE > h->ev.size()) {
       for (int k = 0; k < EV_PER_UPDATE; ++k) {
         hipEvent_t e;
@@ -649,6 +664,7 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
     if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
   }
   HIP_OK(hipSetDevice(hs[0]->device));
+  if (capturing(hs[0]->stream)) return ODMD_EINVAL;   // staged through host memory: use a plan
   return launch_batch(hs, xs, ys, count);
 }
 
@@ -712,6 +728,7 @@ odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* ou
     if (!seen.insert(hs[i]).second) return ODMD_EINVAL;
   }
   HIP_OK(hipSetDevice(hs[0]->device));
+  if (capturing(hs[0]->stream)) return ODMD_EINVAL;   // staged through host memory
   {
     std::unique_lock<std::mutex> lk;
     BatchSlot* sl = nullptr;

@@ -123,3 +123,50 @@ def test_graph_replay_equals_eager_launches():
         p.close()
     for m in E + G:
         m.close()
+
+
+def test_captured_single_stream_updates_and_prediction():
+    """odmd_update and odmd_predict captured directly (no plan): replays
+    equal eager calls bit for bit, and the batched entry points refuse
+    capture."""
+    n, rank, r_max, steps, pred = 20011, 12, 24, 40, 30
+    X = synth.random_planted(n, rank, seed=77).snapshots(0, steps + 1)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    S = torch.cuda.Stream()
+    e = ODMD(n, r_max, 1e-10, stream=S)
+    g = ODMD(n, r_max, 1e-10, stream=S)
+    buf = [torch.empty_like(Xd[0]) for _ in range(2)]
+    out_g = torch.empty((pred, n), dtype=torch.float64, device="cuda")
+    S.synchronize()
+    graphs = []
+    for j in (0, 1):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=S):
+            g.update(buf[j], buf[1 - j])
+        graphs.append(gr)
+    gp = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gp, stream=S):
+        with pytest.raises(OdmdError):           # refused before anything is enqueued
+            update_batch([g], [buf[0]], [buf[1]])
+        g.predict(pred, out=out_g)
+    for k in range(steps):
+        with torch.cuda.stream(S):
+            if k == 0:
+                buf[0].copy_(Xd[0])
+            buf[(k + 1) % 2].copy_(Xd[k + 1])
+            e.update(Xd[k], Xd[k + 1])
+            graphs[k % 2].replay()
+        S.synchronize()
+        if k % 7 == 6 or k == steps - 1:
+            assert _equal(e, g), k
+    with torch.cuda.stream(S):
+        out_e = e.predict(pred)
+        gp.replay()
+    S.synchronize()
+    assert torch.equal(out_e, out_g)
+    o = O.OnlineDMD(n, r_max, 1e-10)
+    for k in range(steps):
+        o.update(X[:, k], X[:, k + 1])
+    np.testing.assert_allclose(g.state()["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
+    e.close()
+    g.close()
