@@ -509,20 +509,17 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
       const int i0 = 16 * (tile % ntr), b0 = 16 * (tile / ntr);
       const int ia = i0 + (l & 15), bb = b0 + (l & 15);
       const int pb = bb < rn ? perm[bb] : 0;
-      d4_t d = {0.0, 0.0, 0.0, 0.0};
-      for (int j0 = 0; j0 < M; j0 += 4) {
-        const int j = j0 + (l >> 4);
-        double av = 0.0, bv = 0.0;
-        if (j < M) {
-          if (ia < r) av = j < r ? sC[j * RMAX + ia] : pyr[ia];
-          else if (ia == r) av = j < r ? qB[j] : qy;
-          bv = bb < rn ? sV[pb * LDK + j] : 0.0;
-        }
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
-      }
+      // columns j < r of E on the matrix cores (row ia: row ia of G, stride
+      // RMAX along j, or q^T B), then column r (U^T y, q^T y) times row r of
+      // V_k as an outer-product term
+      d4_t d = mfma_tile(ia < r ? sC + ia : qB, ia < r ? RMAX : 1, ia <= r, sV + pb * LDK, 1, bb < rn,
+                         r, l);
+      const double vr = bb < rn ? sV[pb * LDK + r] : 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 4 * v + (l >> 4);
+        const double er = i < r ? pyr[i < r ? i : 0] : (i == r ? qy : 0.0);
+        d[v] = __builtin_fma(er, vr, d[v]);
         if (i < M && bb < rn) sQ[bb * MMAX + i] = d[v];
       }
     }
@@ -579,16 +576,8 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
       const int i0 = 16 * (tile % nt), j0 = 16 * (tile / nt);
       const int ia = i0 + (l & 15), jb = j0 + (l & 15);
       const int pa = ia < rn ? perm[ia] : 0;
-      d4_t d = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < M; k0 += 4) {
-        const int k = k0 + (l >> 4);
-        double av = 0.0, bv = 0.0;
-        if (k < M) {
-          av = ia < rn ? sA[pa * LDK + k] : 0.0;
-          bv = jb < rn ? sQ[jb * MMAX + k] : 0.0;
-        }
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
-      }
+      const d4_t d = mfma_tile(sA + pa * LDK, 1, ia < rn, sQ + (jb < rn ? jb : 0) * MMAX, 1, jb < rn,
+                               M, l);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 4 * v + (l >> 4);
