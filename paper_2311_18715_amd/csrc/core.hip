@@ -650,6 +650,8 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const int rg = rth ? tid % pw2 : 0, rsl = rth ? tid / pw2 : 0;
   const double2* __restrict__ rec = reinterpret_cast<const double2*>(c.partials);
   double2 rv[RU];
+  int64_t macc0 = 0;
+  double yyprev0 = 0.0, tol0 = 0.0;
   double ax = 0.0, ay = 0.0;
   // records rsl + (ch RU + i) nslot; past nblk a valid record is read and
   // not added
@@ -685,6 +687,22 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       cv[i] = (j < r && k < r) ? st->C[idx] : 0.0;
     }
     load_records(0);
+    // the small state the later steps read, fetched with the rest: sigma
+    // and p1 (the cached p_y, or U^T x of a general pair) into ssig / pvec,
+    // and the scalars of the checks into tid 0's registers and sc[4]
+    const bool sth = tid < RMAX && tid < r;
+    const double sg = sth ? st->sigma[tid] : 0.0;
+    const double p1v = sth ? (GENERAL ? st->p1[tid] : st->py[tid]) : 0.0;
+    if (tid == 0) {
+      macc0 = st->m_acc;
+      yyprev0 = st->yy_prev;
+      tol0 = st->tol;
+    }
+    if (sth) {
+      ssig[tid] = sg;
+      pvec[tid] = p1v;
+    }
+    if (tid == 0) sc[4] = tol0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int idx = tid + i * CORE_THREADS;
@@ -783,11 +801,11 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
             isfinite(py2))) {
         skip = ST_NONFINITE;
-      } else if (!GENERAL && st->m_acc > 0 && xx != st->yy_prev) {
+      } else if (!GENERAL && macc0 > 0 && xx != yyprev0) {
         skip = ST_SEQ;
       }
       double rho = sqrt(fmax(ee - pp, 0.0));
-      const int grow = !skip && rho > 0.0 && rho > st->tol * sqrt(xx);
+      const int grow = !skip && rho > 0.0 && rho > tol0 * sqrt(xx);
       if (!grow) rho = 0.0;
       sc[0] = rho;
       sc[1] = grow ? (ey - py2) / rho : 0.0;   // q^T y
@@ -840,10 +858,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   // 4. core K = [[diag(sigma), p], [0, rho]], p = p1 + p2 with p1 the
   //    cached p_y (chained pairs) or U^T x from the projection sweep
   const int M = r + 1;
-  if (tid < r) {
-    ssig[tid] = st->sigma[tid];
-    pvec[tid] = (GENERAL ? st->p1[tid] : st->py[tid]) + p2[tid];
-  }
+  if (tid < r) pvec[tid] += p2[tid];   // sigma and p1 were staged with Q
   __syncthreads();
   // general pairs: q^T B = (e^T B - p2^T G) / rho with G = U^T B (in sC,
   // G(i, j) at sC[j * RMAX + i]), from the stored residual e = x - U p1
@@ -887,7 +902,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   }
   __syncthreads();
   const double smax = sd[perm[0]];
-  const int above = __syncthreads_count(tid < M && smax > 0.0 && sd[tid] > st->tol * smax);
+  const int above = __syncthreads_count(tid < M && smax > 0.0 && sd[tid] > sc[4] * smax);
   const int rn = min(above, c.r_max);
   if (rn == 0) {   // nothing kept (zero snapshots so far)
     if (tid < CMAX) st->a[tid] = 0.0;
