@@ -768,15 +768,23 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 
   // 2. second projection p2 = U^T e = Q^T S^T e and U^T y = Q^T S^T y, with
   //    the stored columns and the Q the pass read
-  if (tid < r) {
-    double a2 = 0.0, b2 = 0.0;
-#pragma unroll 8
-    for (int c0 = 0; c0 < m; ++c0) {
-      a2 += sQ[c0 * LDQ + tid] * tot[P_SUE + c0];
-      b2 += sQ[c0 * LDQ + tid] * tot[P_SUY + c0];
+  //    (one 16-lane quarter-wave per entry, the stored columns split over
+  //    its lanes)
+  {
+    const int j = tid >> 4, jl = tid & 15;
+    if (j < r) {
+      double a2 = 0.0, b2 = 0.0;
+      for (int c0 = jl; c0 < m; c0 += 16) {
+        a2 = __builtin_fma(sQ[c0 * LDQ + j], tot[P_SUE + c0], a2);
+        b2 = __builtin_fma(sQ[c0 * LDQ + j], tot[P_SUY + c0], b2);
+      }
+      a2 = row_sum(a2);
+      b2 = row_sum(b2);
+      if (jl == 0) {
+        p2[j] = a2;
+        pyr[j] = b2;
+      }
     }
-    p2[tid] = a2;
-    pyr[tid] = b2;
   }
   __syncthreads();
   // a refold pass left U = S[:, :r] (Q = I); the update below continues from it
@@ -886,19 +894,22 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   }
 
   // 6. singular values (exact column norms), descending order, truncation
-  if (tid < M) {
+  //    (one 16-lane quarter-wave per column for the norm and for the rank;
+  //    M = r + 1 may exceed the 64 quarter-waves)
+  const int qcl = tid & 15;
+  for (int col = tid >> 4; col < M; col += CORE_THREADS / 16) {
     double s = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < M; ++i) s += sA[tid * LDK + i] * sA[tid * LDK + i];
-    sd[tid] = sqrt(s);
+    for (int i = qcl; i < M; i += 16) s = __builtin_fma(sA[col * LDK + i], sA[col * LDK + i], s);
+    s = row_sum(s);
+    if (qcl == 0) sd[col] = sqrt(s);
   }
   __syncthreads();
-  if (tid < M) {
-    const double me = sd[tid];
-    int rank = 0;
-#pragma unroll 8
-    for (int k = 0; k < M; ++k) rank += (sd[k] > me) || (sd[k] == me && k < tid);
-    perm[rank] = tid;
+  for (int col = tid >> 4; col < M; col += CORE_THREADS / 16) {
+    const double me = sd[col];
+    double rank = 0.0;
+    for (int k = qcl; k < M; k += 16) rank += (sd[k] > me || (sd[k] == me && k < col)) ? 1.0 : 0.0;
+    rank = row_sum(rank);
+    if (qcl == 0) perm[(int)rank] = col;
   }
   __syncthreads();
   const double smax = sd[perm[0]];
@@ -927,17 +938,24 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 
   // 7. U_k = (K V_k) diag(sigma')^-1 for kept columns; new p_y and signs
   //    U_k(i, jj) = sA[perm[jj]*LDK + i] / sd[perm[jj]]
-  if (tid < rn) {
-    const int pj = perm[tid];
-    const double inv = 1.0 / sd[pj];
-    double s = sA[pj * LDK + r] * qy;
-#pragma unroll 8
-    for (int i = 0; i < r; ++i) s += sA[pj * LDK + i] * pyr[i];
-    pyn[tid] = s * inv;
-    wn[tid] = sV[pj * LDK + r];
-    sgn[tid] = sd[pj];
-    wk[tid] = s * inv * inv;                  // p_y,k / sigma'_k
-    urk[tid] = sA[pj * LDK + r] * inv;        // U_k(r, k)
+  //    (one 16-lane quarter-wave per kept column)
+  {
+    const int k = tid >> 4, kl = tid & 15;
+    if (k < rn) {
+      const int pj = perm[k];
+      double s = 0.0;
+      for (int i = kl; i < r; i += 16) s = __builtin_fma(sA[pj * LDK + i], pyr[i], s);
+      s = row_sum(s);
+      if (kl == 0) {
+        const double inv = 1.0 / sd[pj];
+        s = __builtin_fma(sA[pj * LDK + r], qy, s);
+        pyn[k] = s * inv;
+        wn[k] = sV[pj * LDK + r];
+        sgn[k] = sd[pj];
+        wk[k] = s * inv * inv;                  // p_y,k / sigma'_k
+        urk[k] = sA[pj * LDK + r] * inv;        // U_k(r, k)
+      }
+    }
   }
   __syncthreads();
 
