@@ -459,6 +459,14 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
   return !S.fail;
 }
 
+// Stored-column count at which the next pass refolds: the capacity, or
+// (fold_slack > 0) r' + fold_slack when that is smaller, so that a stream
+// whose rank sits below its cap does not carry the whole capacity's
+// pending columns through every pass.
+__device__ __forceinline__ int fold_limit(const CoreArgs& c, int rn) {
+  return c.fold_slack > 0 ? min(c.ct, rn + c.fold_slack) : c.ct;
+}
+
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 // One 16 x 16 FP64 tile D = sum_{k < K} A(row, k) B(k, col) on the matrix
@@ -608,7 +616,7 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
   if (tid == 0) {
     tst->m = mTe + 1;
     tst->r = rn;
-    tst->refold = mTe + 1 >= c.ct;   // no free T column for the next y
+    tst->refold = mTe + 1 >= fold_limit(c, rn);
   }
 }
 
@@ -1115,7 +1123,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   if (tid == 0) {
     st->r = rn;
     st->m = mnew;
-    st->refold = mnew >= c.ct;   // no free column for the next residual
+    st->refold = mnew >= fold_limit(c, rn);
     st->m_acc += 1;
     st->yy_prev = sc[2];
     st->last_rho = rho;

@@ -164,6 +164,11 @@ odmd_status copy_field(odmd_t h, T* dst, const T* src_dev, size_t count) {
   return ODMD_OK;
 }
 
+// Refold slack of the core (CoreArgs::fold_slack): FP64 and FP32 bases
+// refold once FOLD_SLACK columns are pending; a BF16 basis only at the
+// capacity, since every refold rounds the basis to BF16 again.
+int fold_slack(odmd_t h) { return h->basis == ODMD_BF16 ? 0 : FOLD_SLACK; }
+
 // Live-column bucket for the next pass: an upper bound on the stored
 // columns in use after the last issued update.  They grow by at most one per
 // update, so the last count the device reported plus the number of updates
@@ -254,6 +259,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.jacobi_only = h->jacobi_only;
   c.rb = kb;
   c.ct = h->ct;
+  c.fold_slack = fold_slack(h);
   c.fb = h->fb_dev;
   c.seq = h->seq;
   c.tst = h->general ? h->tst : nullptr;
@@ -393,6 +399,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     c.jacobi_only = h->jacobi_only;
     c.rb = kb[i];
     c.ct = h->ct;
+    c.fold_slack = fold_slack(h);
     h->seq = (h->seq + 1) & 0xFFFFFFu;
     c.fb = h->fb_dev;
     c.seq = h->seq;
@@ -937,6 +944,7 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
     c.jacobi_only = h->jacobi_only;
     c.rb = h->ct;
     c.ct = h->ct;
+    c.fold_slack = fold_slack(h);
   }
   p->nside = p->launches.size() > 1 ? std::min<int>(NSIDE, (int)p->launches.size()) : 0;
   bool ok = hipMalloc(&p->dev, bytes) == hipSuccess &&

@@ -56,6 +56,8 @@ struct CoreArgs {
   int jacobi_only;      // skip the secular solver (diagnostics)
   int rb;               // live-column bucket of the pass (compact partial records)
   int ct;               // stored-column capacity of the stream
+  int fold_slack;       // refold once the stored columns reach r' + fold_slack
+                        // (or the capacity); 0: only at the capacity
   unsigned* fb;         // host-visible word: (seq << 8) | stored columns after this update
   unsigned seq;         // update sequence number (24 bits) of this launch
   DevState* tst;        // general pairs: state of B = T R (R in its Q), else null

@@ -12,8 +12,10 @@
 //   * per-workgroup partial sums of S^T e, S^T y, e.e, e.y, x.x and y.y, from
 //     which the small-state kernel forms the second Gram-Schmidt projection
 //     p2 = U^T e = Q^T S^T e and U^T y (CGS2);
-//   * on a refold pass (no free column left), S[:, :r] <- S Q in place on the
-//     matrix cores, with e then stored as column r.
+//   * on a refold pass (the small-state kernel sets it once the stored
+//     columns reach their limit: the capacity, or r + 16 pending columns for
+//     FP64/FP32 storage), S[:, :r] <- S Q in place on the matrix cores, with
+//     e then stored as column r.
 // For general (unchained) pairs the same sweep also serves as the projection
 // of x (k_proj: e = x, nothing stored), writes e contiguously for the next
 // sweep, and, run on the stored columns T of B = Y W = T R with zero
