@@ -308,6 +308,10 @@ typedef struct {
   int32_t last_sweeps;/* Jacobi sweeps of the last small SVD            */
   int32_t nblocks;    /* workgroups of the streaming pass               */
   int32_t threads;    /* threads per workgroup of the streaming pass    */
+  int32_t stored;     /* stored basis columns in use (U = S[:, :stored] Q) */
+  int32_t capacity;   /* stored-column capacity: min(72, r_max + 16 rounded
+                         up to 8); FP64/FP32 bases refold at r + 16 stored
+                         columns already, BF16 bases at the capacity      */
 } odmd_info;
 
 odmd_status odmd_get_info(odmd_t h, odmd_info* info);

@@ -779,6 +779,8 @@ odmd_status odmd_get_info(odmd_t h, odmd_info* info) {
   info->last_sweeps = hdr.sweeps;
   info->nblocks = h->nblk;
   info->threads = h->threads;
+  info->stored = hdr.m;
+  info->capacity = h->ct;
   return ODMD_OK;
 }
 

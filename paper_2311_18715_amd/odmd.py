@@ -42,7 +42,7 @@ class Info(ctypes.Structure):
         ("r", ctypes.c_int32), ("r_max", ctypes.c_int32), ("n", ctypes.c_int64),
         ("m", ctypes.c_int64), ("tol_eff", ctypes.c_double), ("last_rho", ctypes.c_double),
         ("last_sweeps", ctypes.c_int32), ("nblocks", ctypes.c_int32),
-        ("threads", ctypes.c_int32),
+        ("threads", ctypes.c_int32), ("stored", ctypes.c_int32), ("capacity", ctypes.c_int32),
     ]
 
 

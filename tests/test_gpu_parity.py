@@ -229,3 +229,37 @@ def test_full_size_wake_prefix():
     pg = g.predict(5).cpu().numpy()
     po = o.predict(5)
     assert np.max(np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)) < 1e-9
+
+
+def test_refold_limit_follows_the_rank():
+    """FP64/FP32 bases refold once r + 16 columns are stored, below the
+    capacity (here 48); a BF16 basis only at the capacity.  The oracle's
+    values are kept.  The stream (Gaussian modes, rank 27, cap 30) keeps
+    appending directions that truncation then drops, so the stored columns
+    grow at a steady rank."""
+    n, rank, r_max, steps = 90992, 27, 30, 120
+    gen = synth.DevicePlanted(torch, n, rank, seed=231118715 + 1)
+    X64 = gen.chunk(0, steps + 1)
+    X = X64.cpu().numpy().T
+    o = O.OnlineDMD(n, r_max, 1e-8)
+    for k in range(steps):
+        o.update(X[:, k], X[:, k + 1])
+    for basis in ("f64", "f32", "bf16"):
+        g = ODMD(n, r_max, 1e-8, basis=basis)
+        Xd = X64 if basis == "f64" else X64.float()
+        peak, over = 0, 0
+        for k in range(steps):
+            g.update(Xd[k], Xd[k + 1])
+            info = g.info()
+            peak = max(peak, info.stored)
+            over = max(over, info.stored - info.r)
+        assert info.capacity == 48
+        assert peak <= 48, (basis, peak)
+        if basis != "bf16":
+            assert over <= 16, (basis, over)
+        if basis == "f64":
+            assert over == 16 and peak < 48, (peak, over)     # refolded below the capacity
+            st = g.state()
+            assert st["r"] == o.r
+            np.testing.assert_allclose(st["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
+        g.close()
