@@ -185,3 +185,12 @@ def test_plan_entry_points_check_arguments_on_the_host():
     assert L.odmd_plan_create(H, H, H, 1, ctypes.byref(p)) == 1     # NULL handle
     assert L.odmd_plan_launch(None) == 1
     assert L.odmd_plan_destroy(None) == 1
+
+
+def test_info_struct_matches_the_header():
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} odmd_info;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(int32_t|int64_t|double)\s+(\w+);", body)
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    assert [(n, ctype[t]) for t, n in fields] == list(B.Info._fields_)
