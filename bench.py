@@ -22,8 +22,9 @@ of one update (pass start to core end), a plain device-copy rate, S =
 tuned launch shapes), the same mix stepped by a plan and by HIP-graph
 replay of the plan's launch, the serving
 loop at swept request rates, general (unchained) pairs, the hybrid
-full-order/DMD workflow, the n = 6,000,000 precision form (FP64, FP32,
-BF16), and the CPU oracle timed on a bounded sample on this host (all
+full-order/DMD workflow, prediction times at the paper's mesh size
+(n = 585,732), the n = 6,000,000 precision form (FP64, FP32, BF16), and
+the CPU oracle timed on a bounded sample on this host (all
 threads and one).  --no-extra keeps only the main measurement; the
 --*-only flags run one section alone.
 """
@@ -163,6 +164,49 @@ def general_pairs(torch, Xd, bytes_upd):
             "updates_timed": len(timed), "rank": r,
             "pairs": "x_k -> x_k+1 of the stream, k = 4 mod 5 left out (unchained after each gap)",
             "hbm_gbps_algorithmic_chained_bytes": round(ups * bytes_upd / 1e9, 1)}
+
+
+PRED_N, PRED_RANK, PRED_RMAX, PRED_UPDATES = 585732, 20, 40, 120
+
+
+def prediction_section(torch):
+    """Prediction cost at the paper's mesh size (n = 585,732, the size its
+    only timing of this path, one time step of a converged DMD model, is
+    quoted at): a planted stream (Gaussian modes, rank 20, generated on the
+    device), r_max = 40, 120 updates, then odmd_predict of one state: the
+    first call (the eigendecomposition of A~ included) and the following
+    ones (eigenpairs reused), and a 100-state rollout.  Device time between
+    events on the handle's stream."""
+    from paper_2311_18715_amd import synth
+    from paper_2311_18715_amd.odmd import ODMD
+    gen = synth.DevicePlanted(torch, PRED_N, PRED_RANK, 231118715 + 9)
+    X = gen.chunk(0, PRED_UPDATES + 1)
+    g = ODMD(PRED_N, PRED_RMAX, TOL)
+    for k in range(PRED_UPDATES):
+        g.update(X[k], X[k + 1])
+    out1 = torch.empty((1, PRED_N), dtype=torch.float64, device="cuda")
+    out100 = torch.empty((100, PRED_N), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    first = timed(lambda: g.predict(1, out=out1), 1)
+    again = timed(lambda: g.predict(1, out=out1), 50)
+    roll = timed(lambda: g.predict(100, out=out100), 10)
+    res = {"n": PRED_N, "rank": g.info().r, "r_max": PRED_RMAX,
+           "one_step_first_call_us": round(first, 1), "one_step_us": round(again, 1),
+           "rollout_100_states_us": round(roll, 1),
+           "paper_context": "the paper's single time step of its converged DMD model takes 0.0286 s "
+                            "at N = 585,732 (hardware and precision not stated); context only"}
+    g.close()
+    return res
 
 
 def hybrid_section(torch):
@@ -681,6 +725,8 @@ def main():
                     help="run only the serving section")
     ap.add_argument("--graph-only", action="store_true",
                     help="run only the plan / HIP-graph section")
+    ap.add_argument("--prediction-only", action="store_true",
+                    help="run only the prediction section (n = 585,732)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy MIB MiB once on the device (a reference "
                          "kernel of known traffic for hardware byte counters)")
@@ -702,6 +748,9 @@ def main():
         return
     if args.graph_only:
         print(json.dumps({"graph_replay": graph_section(torch)}), flush=True)
+        return
+    if args.prediction_only:
+        print(json.dumps({"prediction_n585k": prediction_section(torch)}), flush=True)
         return
     if args.hybrid_only:
         print(json.dumps({"hybrid_heat_n160k": hybrid_section(torch)}), flush=True)
@@ -819,6 +868,8 @@ def main():
         result["serving"] = serving_section(torch)
         torch.cuda.empty_cache()
         result["hybrid_heat_n160k"] = hybrid_section(torch)
+        torch.cuda.empty_cache()
+        result["prediction_n585k"] = prediction_section(torch)
         torch.cuda.empty_cache()
         result["precision_n6m"] = precision_section(torch)
     if args.calibrate_copy > 0:
