@@ -22,7 +22,7 @@ namespace odmd {
 constexpr int RMAX = 64;          // rank cap
 constexpr int MMAX = RMAX + 1;    // core size (r + 1)
 constexpr int CMAX = 72;          // stored columns per tile, at most
-constexpr int FOLD_SLACK = 16;    // stored columns beyond r_max before a refold
+constexpr int FOLD_SLACK = 16;    // pending stored columns (beyond r, or r_max for the capacity) before a refold
 constexpr int PW = 2 * CMAX + 4;  // partial-sum record per workgroup
 // Streaming-pass launch shape of a stream, fixed at creation (the
 // partition sets the order of the pass's sums, so it never changes for a
