@@ -35,6 +35,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "odmd_internal.h"
 #include "pass.h"
 #include "storage.h"
@@ -74,12 +76,21 @@ template <> struct Mfma<float> {
 // stored residual is also written to p.eout (general pairs).
 template <typename TS, typename TIO, int RB, int NTH, bool PROJ = false, bool EOUT = false>
 __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
-  constexpr int UR = 16;                  // rows per unit
+  typedef Storage<TS> SC;
+  // rows per lane (one load per column): two for BF16 storage in the
+  // 512-thread shape (large n, HBM-bound: 16 lanes then read half a line of
+  // a column instead of a quarter), one otherwise.  Two FP32 rows per lane
+  // (whole lines) made a single large stream 7 % faster but cost a third
+  // of the occupancy (178 against 136 registers), which slowed the
+  // 256-stream batch by 9 %.
+  constexpr int RPL = (NTH == PASS_WIDE.threads && sizeof(TS) == 2) ? SC::RPL : 1;
+  // the loaded rows of one column, packed (8 or 4 bytes)
+  typedef typename std::conditional<RPL * sizeof(TS) == 8, uint64_t, uint32_t>::type raw_t;
+  constexpr int UR = 16 * RPL;            // rows per unit
   constexpr int UPT = 64 / UR;            // units per 64-row tile
   constexpr int KK = RB / 4;              // k-steps over the RB live stored columns
   constexpr int NT = ((RB < RMAX ? RB : RMAX) + 15) / 16;   // 16-column output blocks of a refold (r <= RMAX)
   constexpr int NWAVE = NTH / 64;           // waves of the workgroup
-  typedef Storage<TS> SC;
   typedef typename SC::tc TC;             // compute type of the matrix-core refold
   typedef typename Mfma<TC>::acc_t acc_t;
 
@@ -100,16 +111,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   const int64_t u0 = (int64_t)blk * units / p.nblk;
   const int64_t u1 = (int64_t)(blk + 1) * units / p.nblk;
 
-  // Addressing: a unit is 16 rows of one tile, so its base is wave-uniform
-  // (scalar registers) and each lane adds a constant 32-bit offset.  Rows
-  // of the last tile past n are never written and stay zero, so stored
-  // columns are read without a row test.  Every load is issued
-  // unconditionally, so the number in flight is fixed and the waits can
-  // leave the prefetched unit outstanding: a k-step past the m live columns
-  // re-reads k-step 0 (a cache hit) and meets zero coefficients (a and the
-  // staged Q vanish past m; every stored value is finite, see the residual
-  // store), x and y are read at a clamped row and zeroed past n.
-  const uint32_t loff = (uint32_t)((q * 64 + l16) * sizeof(TS));
+  // Addressing: a unit is 16 RPL rows of one tile (lane row group l16 holds
+  // its rows RPL l16 .. RPL l16 + RPL - 1, read with one load per column:
+  // for FP64 and FP32 storage 16 lanes read a whole 128-byte line of a
+  // column), so its base is wave-uniform (scalar registers) and each lane adds a constant
+  // 32-bit offset.  Rows of the last tile past n are never written and stay
+  // zero, so stored columns are read without a row test.  Every load is
+  // issued unconditionally, so the number in flight is fixed and the waits
+  // can leave the prefetched unit outstanding: a k-step past the m live
+  // columns re-reads k-step 0 (a cache hit) and meets zero coefficients (a
+  // and the staged Q vanish past m; every stored value is finite, see the
+  // residual store), x and y are read at a clamped row and zeroed past n.
+  const uint32_t loff = (uint32_t)((q * 64 + RPL * l16) * sizeof(TS));
   typedef gbytes gbase_t;
   auto unit_base = [&](int64_t uu) -> gbase_t {
     const int64_t tile = uu / UPT;
@@ -118,24 +131,28 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
     return (gbase_t)(((uint64_t)hi << 32) | lo);
   };
-  auto load_unit = [&](int64_t uu, TS (&A)[KK], double& xv, double& yv) {
+  auto load_unit = [&](int64_t uu, raw_t (&A)[KK], double (&xv)[RPL], double (&yv)[RPL]) {
     const gbase_t base = unit_base(uu);
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
       const int ks = 4 * kk < m ? kk : 0;   // uniform
-      A[kk] = SC::gload(base + ks * 256 * (int)sizeof(TS) + loff);
+      if constexpr (RPL == SC::RPL) A[kk] = (raw_t)SC::rows(base + ks * 256 * (int)sizeof(TS) + loff);
+      else A[kk] = (raw_t)SC::row(base + ks * 256 * (int)sizeof(TS) + loff);
     }
-    const int64_t row = (uu / UPT) * 64 + UR * (uu % UPT) + l16;
-    const int64_t rc = row < p.n ? row : p.n - 1;
-    xv = (double)X[rc];     // zeroed past n at the point of use
-    yv = (double)Y[rc];
+    const int64_t row0 = (uu / UPT) * 64 + UR * (uu % UPT) + RPL * l16;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      const int64_t rc = row0 + j < p.n ? row0 + j : p.n - 1;
+      xv[j] = (double)X[rc];   // zeroed past n at the point of use
+      yv[j] = (double)Y[rc];
+    }
   };
 
   // software pipeline: the next unit's loads (the current unit's again on
   // the last round, so the count never varies) are in flight while the
   // current one is processed
-  TS A[KK], An[KK];
-  double xv, yv, xn, yn;
+  raw_t A[KK], An[KK];                    // RPL stored values per k-step, packed
+  double xv[RPL], yv[RPL], xn[RPL], yn[RPL];
   // the coefficients a of the first projection go to LDS, with Q
   // pre-arranged in the MFMA operand layout (entry [kk][nt][lane] =
   // Q[4 kk + lane/16][16 nt + lane%16]) for a refold.  a is loaded before
@@ -161,73 +178,106 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   }
   __syncthreads();
 
+  // (an empty asm statement that claims to change the packed values keeps
+  // the compiler from holding every unpacked row live between the steps:
+  // each step unpacks again)
+  auto fence_rows = [&](raw_t (&V)[KK]) {
+    if constexpr (RPL > 1) {
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk) asm volatile("" : "+v"(V[kk]));
+    }
+  };
   for (; u < u1; u += NWAVE) {
     const bool more = u + NWAVE < u1;
     load_unit(more ? u + NWAVE : u, An, xn, yn);
     const int64_t tile = u / UPT;
-    const int rr = UR * (int)(u % UPT) + l16;
-    const int64_t row = tile * 64 + rr;
+    const int rr0 = UR * (int)(u % UPT) + RPL * l16;   // the lane's first row in the tile
+    const int64_t row0 = tile * 64 + rr0;
     TS* __restrict__ T = Us + tile * (int64_t)p.ct * 64;
-    if (row >= p.n) xv = yv = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+      if (row0 + j >= p.n) xv[j] = yv[j] = 0.0;
 
     // e = x - S a, in FP64, stored as column `slot`
-    double ed = xv;
-    if constexpr (!PROJ) {
-      double s = 0.0;
+    double ed[RPL];
 #pragma unroll
-      for (int kk = 0; kk < KK; ++kk) s = __builtin_fma(SC::to_double(A[kk]), sa[4 * kk + q], s);
-      s = add_half_pair(add_row_pair(s));
-      const TS es = SC::from_double(xv - s);
-      ed = SC::to_double(es);    // the stored value, which the sums see
-      // a non-finite residual (rejected by the small-state kernel, which
-      // sees it in the sums below) is stored as zero: stored columns stay
-      // finite
-      if (q == 0 && row < p.n) T[slot * 64 + rr] = __builtin_isfinite(ed) ? es : SC::from_double(0.0);
-      if constexpr (EOUT) {
-        if (q == 0 && row < p.n) static_cast<TIO*>(p.eout)[row] = (TIO)ed;
+    for (int j = 0; j < RPL; ++j) ed[j] = xv[j];
+    if constexpr (!PROJ) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+          s = __builtin_fma(SC::to_double(SC::elem(A[kk], j)), sa[4 * kk + q], s);
+        s = add_half_pair(add_row_pair(s));
+        const TS es = SC::from_double(xv[j] - s);
+        ed[j] = SC::to_double(es);    // the stored value, which the sums see
+        // a non-finite residual (rejected by the small-state kernel, which
+        // sees it in the sums below) is stored as zero: stored columns stay
+        // finite
+        if (q == 0 && row0 + j < p.n)
+          T[slot * 64 + rr0 + j] = __builtin_isfinite(ed[j]) ? es : SC::from_double(0.0);
+        if constexpr (EOUT) {
+          if (q == 0 && row0 + j < p.n) static_cast<TIO*>(p.eout)[row0 + j] = (TIO)ed[j];
+        }
+      }
+      fence_rows(A);
+    }
+
+    // projections, accumulated in-lane (the lane's rows in order)
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const double av = SC::to_double(SC::elem(A[kk], j));
+        accE[kk] = __builtin_fma(av, ed[j], accE[kk]);
+        accY[kk] = __builtin_fma(av, yv[j], accY[kk]);
+      }
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        sEE = __builtin_fma(ed[j], ed[j], sEE);
+        sEY = __builtin_fma(ed[j], yv[j], sEY);
+        sXX = __builtin_fma(xv[j], xv[j], sXX);
+        sYY = __builtin_fma(yv[j], yv[j], sYY);
       }
     }
 
-    // projections, accumulated in-lane
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-      const double av = SC::to_double(A[kk]);
-      accE[kk] = __builtin_fma(av, ed, accE[kk]);
-      accY[kk] = __builtin_fma(av, yv, accY[kk]);
-    }
-    if (q == 0) {
-      sEE = __builtin_fma(ed, ed, sEE);
-      sEY = __builtin_fma(ed, yv, sEY);
-      sXX = __builtin_fma(xv, xv, sXX);
-      sYY = __builtin_fma(yv, yv, sYY);
-    }
-
     // refold on the matrix cores, computed transposed: (S Q)^T = Q^T S^T, so
-    // that lane l owns row l%16 of S Q and every store instruction writes
-    // whole 16-row column segments; k-steps outermost keeps the NT
-    // accumulator chains independent
+    // that lane l owns the rows of row group l%16 of S Q (one product chain
+    // per row of the group); k-steps outermost keeps the NT accumulator
+    // chains independent
     if (refold) {
+      fence_rows(A);
       // one 16-column output block at a time keeps the accumulator small
       // (the refold pass is the rare one; the register budget is set for
       // the plain pass)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        acc_t d = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) d = Mfma<TC>::mma(sG[kk][nt][lane], SC::to_tc(A[kk]), d);
-        if (row < p.n) {
+        for (int j = 0; j < RPL; ++j) {
+          acc_t d = acc_t{0, 0, 0, 0};
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int col = 16 * nt + Mfma<TC>::dsub(lane, v);
-            if (col < r) T[col * 64 + rr] = SC::from_tc(d[v]);
+          for (int kk = 0; kk < KK; ++kk)
+            d = Mfma<TC>::mma(sG[kk][nt][lane], SC::to_tc(SC::elem(A[kk], j)), d);
+          if (row0 + j < p.n) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int col = 16 * nt + Mfma<TC>::dsub(lane, v);
+              if (col < r) T[col * 64 + rr0 + j] = SC::from_tc(d[v]);
+            }
           }
         }
       }
     }
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) A[kk] = An[kk];
-    xv = xn;
-    yv = yn;
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+      xv[j] = xn[j];
+      yv[j] = yn[j];
+    }
   }
 
   // fixed-order reduction: across the 16 lanes that share a column (one

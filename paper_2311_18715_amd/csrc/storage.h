@@ -19,8 +19,19 @@ template <typename TS> struct Storage;
 
 typedef const __attribute__((address_space(1))) char* gbytes;   // global-memory byte address
 
+__device__ inline uint64_t gload8(gbytes p) { return *(const __attribute__((address_space(1))) uint64_t*)p; }
+
+// Rows per lane: a lane reads RPL consecutive rows of a column with one
+// load, rows(p) (8 bytes for FP64 and FP32, so 16 lanes read a whole
+// 128-byte line; 4 bytes for BF16, whose four-row loads kept too many rows
+// live), or a single row with row(p), packed in a 64-bit value; elem(v, j)
+// is row j of it.
 template <> struct Storage<double> {
   typedef double tc;
+  static constexpr int RPL = 1;
+  __device__ static uint64_t rows(gbytes p) { return gload8(p); }
+  __device__ static uint64_t row(gbytes p) { return gload8(p); }
+  __device__ static double elem(uint64_t v, int) { return __builtin_bit_cast(double, v); }
   __device__ static double gload(gbytes p) { return *(const __attribute__((address_space(1))) double*)p; }
   __device__ static double to_double(double v) { return v; }
   __device__ static double to_tc(double v) { return v; }
@@ -30,6 +41,10 @@ template <> struct Storage<double> {
 
 template <> struct Storage<float> {
   typedef float tc;
+  static constexpr int RPL = 2;
+  __device__ static uint64_t rows(gbytes p) { return gload8(p); }
+  __device__ static uint64_t row(gbytes p) { return *(const __attribute__((address_space(1))) uint32_t*)p; }
+  __device__ static float elem(uint64_t v, int j) { return __uint_as_float((uint32_t)(v >> (32 * j))); }
   __device__ static float gload(gbytes p) { return *(const __attribute__((address_space(1))) float*)p; }
   __device__ static double to_double(float v) { return (double)v; }
   __device__ static float to_tc(float v) { return v; }
@@ -39,6 +54,10 @@ template <> struct Storage<float> {
 
 template <> struct Storage<bf16> {
   typedef float tc;
+  static constexpr int RPL = 2;
+  __device__ static uint64_t rows(gbytes p) { return *(const __attribute__((address_space(1))) uint32_t*)p; }
+  __device__ static uint64_t row(gbytes p) { return *(const __attribute__((address_space(1))) uint16_t*)p; }
+  __device__ static bf16 elem(uint64_t v, int j) { return bf16{(uint16_t)(v >> (16 * j))}; }
   __device__ static bf16 gload(gbytes p) {
     return bf16{*(const __attribute__((address_space(1))) uint16_t*)p};
   }
