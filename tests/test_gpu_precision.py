@@ -1,6 +1,6 @@
 """FP32 precision form against the FP64 oracle.
 
-The survey's precision configuration (wake generator with 10 shedding
+The precision configuration (wake generator with 10 shedding
 harmonics and 10 transients, noise 1e-5 relative, r_max = 64, FP32 basis,
 FP64 core and eigensolver), reduced to n = 60,000 (300 x 100 grid) and 300
 snapshots so that the oracle finishes in seconds.  Both sides see the same

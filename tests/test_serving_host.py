@@ -134,10 +134,10 @@ def test_late_arrivals_join_the_next_round():
     S.open(1, 10, 4, 1e-8)
     p = [_Ptr() for _ in range(4)]
     S.submit_update(0, p[0], p[1])
-    S.pump()                                       # round 1: stream 0 only
-    S.submit_update(1, p[2], p[3])                 # arrives while round 1 runs
+    S.pump()                                       # first round: stream 0 only
+    S.submit_update(1, p[2], p[3])                 # arrives while the first round runs
     S.submit_update(0, p[1], p[2])
-    S.pump()                                       # round 2: both
+    S.pump()                                       # second round: both
     batches = [e for e in B.log if e[0] == "batch"]
     assert [len(b[1]) for b in batches] == [1, 2]
 
