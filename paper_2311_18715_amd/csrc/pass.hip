@@ -255,6 +255,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
       // the plain pass)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
+        if (16 * nt >= r) break;   // uniform: output blocks past the rank hold no column
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
           acc_t d = acc_t{0, 0, 0, 0};
