@@ -170,3 +170,24 @@ def test_captured_single_stream_updates_and_prediction():
     np.testing.assert_allclose(g.state()["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
     e.close()
     g.close()
+
+
+def test_plan_argument_checks():
+    S = torch.cuda.Stream()
+    a = ODMD(1000, 8, 1e-10, stream=S)
+    b = ODMD(1000, 8, 1e-10, stream=S)
+    gen = ODMD(1000, 8, 1e-10, stream=S, pairs="general")
+    other = ODMD(1000, 8, 1e-10)                     # another stream
+    x = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    with pytest.raises(OdmdError):
+        Plan([gen], [x], [x])                         # general pairs: per-handle updates only
+    with pytest.raises(OdmdError):
+        Plan([a, a], [x, x], [x, x])                  # duplicate handle
+    with pytest.raises(OdmdError):
+        Plan([a, other], [x, x], [x, x])              # handles on different streams
+    p = Plan([a, b], [x, x], [x, x])
+    with pytest.raises(OdmdError):
+        b.close()                                     # held by the plan
+    p.close()
+    for m in (a, b, gen, other):
+        m.close()
