@@ -50,6 +50,7 @@ struct odmd_s {
   void* eout = nullptr;         // the residual e as a contiguous vector (io type)
   int nblk = 0;
   int threads = 0;              // workgroup size of the stream's pass launch shape
+  int rows2 = 0;                // the pass's wide-row variant (PassArgs::rows2)
   int64_t units = 0;
   bool prof = false;
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
@@ -95,6 +96,15 @@ bool valid_args(int64_t n, int32_t r_max, double tol, odmd_dtype basis, odmd_dty
 }
 
 int col_bucket(int cols) { return (cols + 7) / 8 * 8; }
+
+// Two rows per lane in the 512-thread pass: always for BF16 storage (half
+// lines instead of quarter lines per load), for FP32 storage only from
+// 2^21 rows on, where a single HBM-bound stream gains (whole lines) and the
+// higher register count no longer costs batches of mid-size streams.
+int wide_rows(odmd_dtype basis, int threads, int64_t n) {
+  if (threads != PASS_WIDE.threads) return 0;
+  return basis == ODMD_BF16 || (basis == ODMD_F32 && n >= (int64_t(1) << 21));
+}
 
 // Stored basis: 64-row tiles, column-major inside a tile, fold_capacity(r_max)
 // columns per tile.
@@ -221,6 +231,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   p.nblk = h->nblk;
   p.ct = h->ct;
   p.threads = h->threads;
+  p.rows2 = h->rows2;
   const int kb = live_bucket(h);
   if (h->general) {
     // U^T x from a projection sweep, then the coefficients of the streaming
@@ -341,10 +352,10 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   // group streams by (launch shape, storage type, live-column bucket): one
   // pass launch per group
   std::vector<int> kb(count);
-  std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
+  std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> groups;
   for (int32_t i = 0; i < count; ++i) {
     kb[i] = live_bucket(hs[i]);
-    groups[{hs[i]->threads, (int)hs[i]->basis, kb[i]}].push_back(i);
+    groups[{hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, kb[i]}].push_back(i);
   }
   const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
   const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
@@ -358,7 +369,7 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   BatchSlot& sl = *slp;
   PassDesc* pd = static_cast<PassDesc*>(sl.host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
-  struct Launch { int first, nd, nblocks, threads, basis, rb; };
+  struct Launch { int first, nd, nblocks, threads, rows2, basis, rb; };
   std::vector<Launch> launches;
   int k = 0;
   for (auto& g : groups) {
@@ -368,7 +379,8 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     std::stable_sort(g.second.begin(), g.second.end(), [&](int32_t a, int32_t b) {
       return hs[a]->n * hs[b]->nblk > hs[b]->n * hs[a]->nblk;
     });
-    Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first)};
+    Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first),
+             std::get<3>(g.first)};
     for (int32_t i : g.second) {
       odmd_t h = hs[i];
       PassDesc& d = pd[k++];
@@ -408,14 +420,14 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
   if (launches.size() == 1) {
     const Launch& L = launches[0];
-    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb, stream));
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, stream));
   } else {
     const int nside = std::min<int>(NSIDE, (int)launches.size());
     HIP_OK(hipEventRecord(ring->fork, stream));
     for (int i = 0; i < nside; ++i) HIP_OK(hipStreamWaitEvent(ring->side[i], ring->fork, 0));
     for (size_t i = 0; i < launches.size(); ++i) {
       const Launch& L = launches[i];
-      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb,
+      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb,
                                ring->side[i % nside]));
     }
     for (int i = 0; i < nside; ++i) {
@@ -473,7 +485,7 @@ struct odmd_plan_s {
   std::vector<odmd_t> hs;
   void* dev = nullptr;          // PassDesc table, then the CoreArgs table
   size_t pass_bytes = 0;
-  struct Launch { int first, nd, nblocks, threads, basis, rb; };
+  struct Launch { int first, nd, nblocks, threads, rows2, basis, rb; };
   std::vector<Launch> launches;
   int nside = 0;
   hipStream_t side[NSIDE] = {};
@@ -568,6 +580,7 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->nblk = L.nblk;
   s->threads = L.threads;
+  s->rows2 = wide_rows(basis, L.threads, n);
   s->units = L.units;
   {
     const char* alg = std::getenv("ODMD_CORE_SVD");
@@ -902,9 +915,9 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
   p->stream = hs[0]->stream;
   // the same grouping and order as a batched update, with every pass sized
   // for the full stored-column capacity
-  std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
+  std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> groups;
   for (int32_t i = 0; i < count; ++i)
-    groups[{hs[i]->threads, (int)hs[i]->basis, hs[i]->ct}].push_back(i);
+    groups[{hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, hs[i]->ct}].push_back(i);
   p->pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
   const size_t bytes = p->pass_bytes + (size_t)count * sizeof(CoreArgs);
   std::vector<char> host(bytes, 0);
@@ -915,7 +928,8 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
     std::stable_sort(g.second.begin(), g.second.end(), [&](int32_t a, int32_t b) {
       return hs[a]->n * hs[b]->nblk > hs[b]->n * hs[a]->nblk;
     });
-    odmd_plan_s::Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first)};
+    odmd_plan_s::Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first),
+                          std::get<3>(g.first)};
     for (int32_t i : g.second) {
       odmd_t h = hs[i];
       PassDesc& d = pd[k++];
@@ -976,13 +990,13 @@ odmd_status odmd_plan_launch(odmd_plan_t p) {
   const PassDesc* dpd = static_cast<const PassDesc*>(p->dev);
   if (p->nside == 0) {
     const odmd_plan_s::Launch& L = p->launches[0];
-    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb, p->stream));
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, p->stream));
   } else {
     HIP_OK(hipEventRecord(p->fork, p->stream));
     for (int i = 0; i < p->nside; ++i) HIP_OK(hipStreamWaitEvent(p->side[i], p->fork, 0));
     for (size_t i = 0; i < p->launches.size(); ++i) {
       const odmd_plan_s::Launch& L = p->launches[i];
-      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.basis, L.rb,
+      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb,
                                p->side[i % p->nside]));
     }
     for (int i = 0; i < p->nside; ++i) {

@@ -19,6 +19,8 @@ struct PassArgs {
   void* eout;           // general pairs: the stored residual e also written here
                         // as a contiguous n-vector of the io type (else null)
   int threads;          // workgroup size of the stream's launch shape
+  int rows2;            // wide-row variant: with 512 threads, FP32 and BF16 storage
+                        // read two rows per lane (fixed per stream, like its shape)
 };
 
 // basis: storage type (0 double, 1 float, 2 bf16; the odmd_dtype codes);
@@ -44,7 +46,7 @@ struct PassDesc {
   int ct;               // column capacity of its basis tiles
 };
 // threads: the launch shape's workgroup size, common to the streams of d
-hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int basis,
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int rows2, int basis,
                              int rb, hipStream_t s);
 
 struct CoreArgs {

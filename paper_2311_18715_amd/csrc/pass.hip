@@ -74,16 +74,13 @@ template <> struct Mfma<float> {
 // PROJ: projection-only sweep of a general pair (e = x: the sums S^T x,
 // S^T y, x.x, x.y; nothing is stored and no refold happens).  EOUT: the
 // stored residual is also written to p.eout (general pairs).
-template <typename TS, typename TIO, int RB, int NTH, bool PROJ = false, bool EOUT = false>
+template <typename TS, typename TIO, int RB, int NTH, bool R2, bool PROJ = false, bool EOUT = false>
 __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   typedef Storage<TS> SC;
-  // rows per lane (one load per column): two for BF16 storage in the
-  // 512-thread shape (large n, HBM-bound: 16 lanes then read half a line of
-  // a column instead of a quarter), one otherwise.  Two FP32 rows per lane
-  // (whole lines) made a single large stream 7 % faster but cost a third
-  // of the occupancy (178 against 136 registers), which slowed the
-  // 256-stream batch by 9 %.
-  constexpr int RPL = (NTH == PASS_WIDE.threads && sizeof(TS) == 2) ? SC::RPL : 1;
+  // rows per lane (one load per column): R2, the stream's wide-row variant
+  // (see PassArgs::rows2), reads two (16 lanes then read a whole line of an
+  // FP32 column, half a line of a BF16 one), else one
+  constexpr int RPL = R2 ? SC::RPL : 1;
   // the loaded rows of one column, packed (8 or 4 bytes)
   typedef typename std::conditional<RPL * sizeof(TS) == 8, uint64_t, uint32_t>::type raw_t;
   constexpr int UR = 16 * RPL;            // rows per unit
@@ -318,26 +315,26 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   }
 }
 
-template <typename TS, typename TIO, int RB, int NTH>
+template <typename TS, typename TIO, int RB, int NTH, bool R2>
 __global__ __launch_bounds__(NTH) void k_pass(PassArgs p) {
-  pass_body<TS, TIO, RB, NTH>(p, blockIdx.x);
+  pass_body<TS, TIO, RB, NTH, R2>(p, blockIdx.x);
 }
 
-template <typename TS, typename TIO, int RB, int NTH>
+template <typename TS, typename TIO, int RB, int NTH, bool R2>
 __global__ __launch_bounds__(NTH) void k_proj(PassArgs p) {
-  pass_body<TS, TIO, RB, NTH, true>(p, blockIdx.x);
+  pass_body<TS, TIO, RB, NTH, R2, true>(p, blockIdx.x);
 }
 
-template <typename TS, typename TIO, int RB, int NTH>
+template <typename TS, typename TIO, int RB, int NTH, bool R2>
 __global__ __launch_bounds__(NTH) void k_pass_eout(PassArgs p) {
-  pass_body<TS, TIO, RB, NTH, false, true>(p, blockIdx.x);
+  pass_body<TS, TIO, RB, NTH, R2, false, true>(p, blockIdx.x);
 }
 
 // Many streams of one storage type and live-column bucket in one launch: workgroup b
 // belongs to the stream whose block range [blk0, blk0 + nblk) contains b, and
 // runs exactly the work that workgroup b - blk0 of that stream's own launch
 // would (same partition, same reduction order: results are bitwise equal).
-template <typename TS, typename TIO, int RB, int NTH>
+template <typename TS, typename TIO, int RB, int NTH, bool R2>
 __global__ __launch_bounds__(NTH) void k_pass_batch(const PassDesc* __restrict__ d, int nd) {
   typedef const __attribute__((address_space(4))) PassDesc* cdesc;
   cdesc D = (cdesc)d;
@@ -358,44 +355,56 @@ __global__ __launch_bounds__(NTH) void k_pass_batch(const PassDesc* __restrict__
   p.units = 0;
   p.nblk = D[lo].nblk;
   p.ct = D[lo].ct;
-  pass_body<TS, TIO, RB, NTH>(p, b - D[lo].blk0);
+  pass_body<TS, TIO, RB, NTH, R2>(p, b - D[lo].blk0);
 }
 
 // Launchers: storage type and live-column bucket select the instantiation,
-// the stream's launch shape (PassShape::threads) the workgroup size.
+// the stream's launch shape (PassShape::threads) the workgroup size, and its
+// wide-row flag (512-thread FP32/BF16 streams only) the rows per lane.
 template <typename TS, typename TIO, int RB>
-static void batch_one(const PassDesc* d, int nd, int nblocks, int threads, hipStream_t s) {
-  if (threads == PASS_WIDE.threads)
-    hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, PASS_WIDE.threads>), dim3(nblocks),
-                       dim3(PASS_WIDE.threads), 0, s, d, nd);
+static void batch_one(const PassDesc* d, int nd, int nblocks, int threads, int rows2, hipStream_t s) {
+  constexpr int W = PASS_WIDE.threads, D = PASS_DEEP.threads;
+  if constexpr (Storage<TS>::RPL > 1) {
+    if (threads == W && rows2) {
+      hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, W, true>), dim3(nblocks), dim3(W), 0, s, d, nd);
+      return;
+    }
+  }
+  if (threads == W)
+    hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, W, false>), dim3(nblocks), dim3(W), 0, s, d, nd);
   else
-    hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, PASS_DEEP.threads>), dim3(nblocks),
-                       dim3(PASS_DEEP.threads), 0, s, d, nd);
+    hipLaunchKernelGGL((k_pass_batch<TS, TIO, RB, D, false>), dim3(nblocks), dim3(D), 0, s, d, nd);
+}
+
+template <typename TS, typename TIO, int RB, int NTH, bool R2>
+static void launch_kind(const PassArgs& p, bool proj, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(p.nblk);
+  if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, NTH, R2>), grid, dim3(NTH), 0, s, e0, e1, 0, p);
+  else if (p.eout) hipExtLaunchKernelGGL((k_pass_eout<TS, TIO, RB, NTH, R2>), grid, dim3(NTH), 0, s, e0, e1, 0, p);
+  else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, NTH, R2>), grid, dim3(NTH), 0, s, e0, e1, 0, p);
 }
 
 template <typename TS, typename TIO, int RB>
 static void launch_one(const PassArgs& p, bool proj, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const dim3 grid(p.nblk);
   constexpr int W = PASS_WIDE.threads, D = PASS_DEEP.threads;
-  if (p.threads == W) {
-    if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
-    else if (p.eout) hipExtLaunchKernelGGL((k_pass_eout<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
-    else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, W>), grid, dim3(W), 0, s, e0, e1, 0, p);
-  } else {
-    if (proj) hipExtLaunchKernelGGL((k_proj<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
-    else if (p.eout) hipExtLaunchKernelGGL((k_pass_eout<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
-    else hipExtLaunchKernelGGL((k_pass<TS, TIO, RB, D>), grid, dim3(D), 0, s, e0, e1, 0, p);
+  if constexpr (Storage<TS>::RPL > 1) {
+    if (p.threads == W && p.rows2) {
+      launch_kind<TS, TIO, RB, W, true>(p, proj, s, e0, e1);
+      return;
+    }
   }
+  if (p.threads == W) launch_kind<TS, TIO, RB, W, false>(p, proj, s, e0, e1);
+  else launch_kind<TS, TIO, RB, D, false>(p, proj, s, e0, e1);
 }
 
 #define ODMD_BUCKETS(CASE) CASE(8) CASE(16) CASE(24) CASE(32) CASE(40) CASE(48) CASE(56) CASE(64) CASE(72)
 
 template <typename TS, typename TIO>
-static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int threads, int rb,
-                                  hipStream_t s) {
+static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int threads, int rows2,
+                                  int rb, hipStream_t s) {
   switch (rb) {
 #define ODMD_CASE(RB) \
-  case RB: batch_one<TS, TIO, RB>(d, nd, nblocks, threads, s); break;
+  case RB: batch_one<TS, TIO, RB>(d, nd, nblocks, threads, rows2, s); break;
     ODMD_BUCKETS(ODMD_CASE)
 #undef ODMD_CASE
     default: return hipErrorInvalidValue;
@@ -403,12 +412,12 @@ static hipError_t launch_batch_rb(const PassDesc* d, int nd, int nblocks, int th
   return hipGetLastError();
 }
 
-hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int basis,
-                             int rb, hipStream_t s) {
+hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int rows2,
+                             int basis, int rb, hipStream_t s) {
   switch (basis) {
-    case 0: return launch_batch_rb<double, double>(d, nd, nblocks, threads, rb, s);
-    case 1: return launch_batch_rb<float, float>(d, nd, nblocks, threads, rb, s);
-    case 2: return launch_batch_rb<bf16, float>(d, nd, nblocks, threads, rb, s);
+    case 0: return launch_batch_rb<double, double>(d, nd, nblocks, threads, rows2, rb, s);
+    case 1: return launch_batch_rb<float, float>(d, nd, nblocks, threads, rows2, rb, s);
+    case 2: return launch_batch_rb<bf16, float>(d, nd, nblocks, threads, rows2, rb, s);
   }
   return hipErrorInvalidValue;
 }
