@@ -841,7 +841,7 @@ def main():
                      "core_mean": round(float(np.mean(core_ms)) * 1e3, 2)},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_pass<double,double,KB,512> (streaming pass; KB = live-column bucket, 56 "
+            "kernel": "k_pass<double,double,KB,512,false> (streaming pass; KB = live-column bucket, 56 "
                       "at steady state: 40 live basis columns + 16 deferred-rotation columns; "
                       "512-thread workgroups, the stream's launch shape)",
             "achieved": round(achieved, 1),
