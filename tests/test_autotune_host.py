@@ -52,3 +52,20 @@ def test_shipped_table_is_valid():
         assert r.startswith("r") and n.startswith("n2^") and objective in T.OBJECTIVES
         assert T._valid(entry), k
         assert entry["us_best"] <= entry["us_default"], k
+
+
+def test_bucket_ranges_parse():
+    assert T._parse_range("13-16") == [13, 14, 15, 16]
+    assert T._parse_range("16,32,48,64") == [16, 32, 48, 64]
+    assert T._parse_range("13-14,21") == [13, 14, 21]
+
+
+def test_invalid_entries_are_ignored(tmp_path):
+    path = str(tmp_path / "shapes.json")
+    k = T.key("gfx950", "f64", "f64", 40, 160000, "latency")
+    T.save_table({k: {"shape": [512, 256]}}, path)            # too short
+    assert T.lookup(160000, 40, "f64", table=T.load_table(path), arch="gfx950") is None
+    T.save_table({k: {"us_best": 1.0}}, path)                 # no shape
+    assert T.lookup(160000, 40, "f64", table=T.load_table(path), arch="gfx950") is None
+    T.save_table({k: {"shape": [512, 256, 256]}}, path)
+    assert T.lookup(160000, 40, "f64", table=T.load_table(path), arch="gfx950") == (512, 256, 256)
