@@ -296,12 +296,22 @@ def rollout_power(U, A, p_y, steps: int) -> np.ndarray:
 
 
 def subspace_angle(A: np.ndarray, B: np.ndarray) -> float:
-    """Largest principal angle (radians) between span(A) and span(B)."""
+    """Largest principal angle (radians) between span(A) and span(B).
+
+    With orthonormal bases Qa, Qb (thin QR), the principal angles theta_i
+    have cosines = singular values of Qa^T Qb and sines = singular values of
+    (I - Qa Qa^T) Qb (Bjorck and Golub, 1973).  The largest angle is taken
+    as atan2(largest sine, smallest cosine): the sine alone loses accuracy
+    near pi/2 and the cosine alone near 0, the pair is accurate at both ends.
+    If B has more columns than A, some direction of span(B) lies outside
+    span(A) and the smallest cosine is 0.
+    """
     qa, _ = np.linalg.qr(A)
     qb, _ = np.linalg.qr(B)
-    # sine form: accurate for small angles, where arccos of a cosine is not
-    s = np.linalg.norm(qb - qa @ (qa.T @ qb), 2)
-    return float(np.arcsin(min(1.0, s)))
+    s_max = float(np.linalg.norm(qb - qa @ (qa.T @ qb), 2))
+    cos = np.linalg.svd(qa.T @ qb, compute_uv=False)
+    c_min = 0.0 if qb.shape[1] > qa.shape[1] else float(np.min(cos))
+    return float(np.arctan2(s_max, c_min))
 
 
 def match_eigs(ref: np.ndarray, got: np.ndarray) -> np.ndarray:

@@ -426,3 +426,94 @@ def test_planted_mistakes_in_update_are_caught(monkeypatch):
         monkeypatch.undo()
         assert rel_eig_err(s.planted_eigs(), np.linalg.eigvals(o.atilde())) > 1e-9 \
             or o.r != 6
+
+
+# ---------------------------------------------------------------- principal angles
+
+def _axis_pair(theta):
+    """span{e1, e2} against span{e1, cos(theta) e2 + sin(theta) e3} in R^4:
+    principal angles 0 and theta, exactly representable bases."""
+    A = np.zeros((4, 2))
+    A[0, 0] = A[1, 1] = 1.0
+    B = np.zeros((4, 2))
+    B[0, 0] = 1.0
+    B[1, 1], B[2, 1] = np.cos(theta), np.sin(theta)
+    return A, B
+
+
+def _embedded_pair(thetas, n=40, seed=7):
+    """Two k-dimensional subspaces of R^n at the principal angles ``thetas``
+    (Bjorck-Golub canonical form rotated by a random orthogonal matrix),
+    each given by a non-orthonormal basis (a random well-conditioned right
+    factor), so the function must orthonormalise before measuring."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    k = len(thetas)
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    c, s = np.cos(thetas), np.sin(thetas)
+    A = Q[:, :k]
+    B = Q[:, :k] * c[None, :] + Q[:, k:2 * k] * s[None, :]
+    MA = np.eye(k) + 0.3 * g.standard_normal((k, k)) / np.sqrt(k)
+    MB = np.eye(k) + 0.3 * g.standard_normal((k, k)) / np.sqrt(k)
+    return A @ MA, B @ MB
+
+
+@pytest.mark.parametrize("theta", [1e-9, 1e-4, 1e-3, 0.7, np.pi / 2 - 1e-6])
+def test_subspace_angle_known_angle(theta):
+    """The largest principal angle of an exactly known pair, to 1e-12
+    relative at every scale from 1e-9 rad to pi/2 - 1e-6."""
+    A, B = _axis_pair(theta)
+    assert abs(O.subspace_angle(A, B) - theta) <= 1e-12 * theta
+    assert abs(O.subspace_angle(B, A) - theta) <= 1e-12 * theta
+
+
+def test_subspace_angle_several_angles_and_basis_invariance():
+    """Several nonzero angles: the largest one is returned (not the smallest,
+    not a norm over all of them), whatever bases span the two subspaces."""
+    for thetas in ([0.3, 0.5, 0.1], [1e-6, 2e-6, 5e-7], [1.2, 0.0, 0.4, 1.5]):
+        A, B = _embedded_pair(np.asarray(thetas))
+        got = O.subspace_angle(A, B)
+        assert abs(got - max(thetas)) <= 1e-12 * max(thetas) + 1e-14, (thetas, got)
+    A, _ = _embedded_pair(np.array([0.2, 0.3]))
+    assert O.subspace_angle(A, A @ np.array([[2.0, 1.0], [0.0, 3.0]])) <= 1e-14
+    # a direction of span(B) outside span(A) when B is larger: pi/2
+    A, _ = _axis_pair(0.0)
+    assert abs(O.subspace_angle(A[:, :1], A) - np.pi / 2) <= 1e-15
+
+
+def test_subspace_angle_planted_mistakes_are_caught(monkeypatch):
+    """Plausible wrong versions of the function fail the pins above."""
+    def cosine_form(A, B):
+        qa, _ = np.linalg.qr(A)
+        qb, _ = np.linalg.qr(B)
+        c = np.linalg.svd(qa.T @ qb, compute_uv=False)
+        return float(np.arccos(min(1.0, np.min(c))))
+
+    def frobenius_sine(A, B):
+        qa, _ = np.linalg.qr(A)
+        qb, _ = np.linalg.qr(B)
+        return float(np.arcsin(min(1.0, np.linalg.norm(qb - qa @ (qa.T @ qb)))))
+
+    def smallest_angle(A, B):
+        qa, _ = np.linalg.qr(A)
+        qb, _ = np.linalg.qr(B)
+        c = np.linalg.svd(qa.T @ qb, compute_uv=False)
+        s = np.sqrt(np.maximum(0.0, 1.0 - c ** 2))
+        return float(np.arctan2(np.min(s), np.max(c)))
+
+    def no_orthonormalisation(A, B):
+        s = np.linalg.norm(B - A @ (A.T @ B), 2)
+        c = np.linalg.svd(A.T @ B, compute_uv=False)
+        return float(np.arctan2(s, np.min(c)))
+
+    for bad in (cosine_form, frobenius_sine, smallest_angle, no_orthonormalisation,
+                lambda A, B: 0.0):
+        monkeypatch.setattr(O, "subspace_angle", bad)
+        failed = False
+        for theta in (1e-9, 1e-4, 0.7, np.pi / 2 - 1e-6):
+            A, B = _axis_pair(theta)
+            failed |= abs(O.subspace_angle(A, B) - theta) > 1e-12 * theta
+        for thetas in ([0.3, 0.5, 0.1], [1.2, 0.0, 0.4, 1.5]):
+            A, B = _embedded_pair(np.asarray(thetas))
+            failed |= abs(O.subspace_angle(A, B) - max(thetas)) > 1e-12 * max(thetas) + 1e-14
+        monkeypatch.undo()
+        assert failed, bad
