@@ -220,6 +220,29 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
                               int32_t count);
 
 /*
+ * For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid hipMalloc): odmd_update_batch without any allocation.  Arguments,
+ * results (bit for bit) and errors as odmd_update_batch, with count at most
+ * ODMD_NOALLOC_MAX_STREAMS (ODMD_EINVAL above it).  The descriptor tables
+ * of the launch live in a fixed device array of the library, one per GPU,
+ * 152 KB, held until the process ends, instead of staging memory
+ * the library allocates and grows; every pass launch goes to the handles'
+ * stream (no side streams).  The tables are copied from a static host
+ * buffer of the library, and the call waits for the handles' stream before
+ * it returns (the work queued before it, not the update it queues), so
+ * calls from several host threads are serialised.  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's tables: calls that
+ * overlap on one GPU, from handles on different streams, race (the first
+ * call's kernels may read the second call's tables).  Not capturable
+ * (ODMD_EINVAL while the stream is being captured): capture a plan's
+ * launch instead.  The first call on a device also looks up the array's
+ * address on that device (no allocation).
+ */
+#define ODMD_NOALLOC_MAX_STREAMS 1024
+odmd_status odmd_update_batch_noalloc(odmd_t* hs, const void* const* xs, const void* const* ys,
+                                      int32_t count);
+
+/*
  * Plans: one batched step (Sec. 2.3's rank-1 update of every handle, as
  * odmd_update_batch) fixed once, so that it can be launched again and
  * again with no host staging, host wait or allocation, and captured into

@@ -444,6 +444,127 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   return ODMD_OK;
 }
 
+// ---- the batched update without allocation (odmd_update_batch_noalloc) ----
+//
+// Its descriptor tables live in `scratch`, one file-scope device array per
+// GPU (held until the process ends), instead of a ring slot the library
+// grows with hipMalloc; every pass launch goes to the caller's stream (no
+// side streams); the host staging is a static buffer of this library.  The
+// device address of each GPU's copy of `scratch` is taken once per device
+// (hipGetSymbolAddress, that device current) and used wherever host code
+// names the array's memory.
+constexpr int NOALLOC_MAX = ODMD_NOALLOC_MAX_STREAMS;
+constexpr size_t NOALLOC_PASS_BYTES = (NOALLOC_MAX * sizeof(PassDesc) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_PASS_BYTES + NOALLOC_MAX * sizeof(CoreArgs);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex g_noalloc_mu;                      // guards the two tables below
+void* g_scratch_ptr[NOALLOC_DEVICES] = {};    // per device: its copy of scratch
+alignas(256) unsigned char g_noalloc_host[NOALLOC_BYTES];   // host staging (pageable)
+
+// Caller holds g_noalloc_mu; the device is current.
+odmd_status scratch_for(int device, unsigned char** out) {
+  if (device < 0 || device >= NOALLOC_DEVICES) return ODMD_EDEVICE;
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return ODMD_EDEVICE;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return ODMD_OK;
+}
+
+odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* const* ys,
+                                 int32_t count) {
+  hipStream_t stream = hs[0]->stream;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  unsigned char* dev = nullptr;
+  {
+    const odmd_status s = scratch_for(hs[0]->device, &dev);
+    if (s != ODMD_OK) return s;
+  }
+  // order: by (launch shape, storage type, live-column bucket), the groups
+  // of one pass launch each, then as odmd_update_batch orders a group (the
+  // most rows per workgroup first), then by position; sorted in place on the
+  // stack (the results do not depend on the order: each stream's work is its
+  // own launch's)
+  int kb[NOALLOC_MAX], order[NOALLOC_MAX];
+  for (int32_t i = 0; i < count; ++i) {
+    kb[i] = live_bucket(hs[i]);
+    order[i] = i;
+  }
+  auto key = [&](int i) {
+    return std::make_tuple(hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, kb[i]);
+  };
+  std::sort(order, order + count, [&](int a, int b) {
+    if (key(a) != key(b)) return key(a) < key(b);
+    const int64_t la = hs[a]->n * hs[b]->nblk, lb = hs[b]->n * hs[a]->nblk;
+    if (la != lb) return la > lb;
+    return a < b;
+  });
+  PassDesc* pd = reinterpret_cast<PassDesc*>(g_noalloc_host);
+  CoreArgs* cd = reinterpret_cast<CoreArgs*>(g_noalloc_host + NOALLOC_PASS_BYTES);
+  struct Launch { int first, nd, nblocks, threads, rows2, basis, rb; };
+  Launch launches[NOALLOC_MAX];
+  int nl = 0;
+  for (int k = 0; k < count; ++k) {
+    const int i = order[k];
+    odmd_t h = hs[i];
+    if (k == 0 || key(i) != key(order[k - 1]))
+      launches[nl++] = Launch{k, 0, 0, h->threads, h->rows2, (int)h->basis, kb[i]};
+    Launch& L = launches[nl - 1];
+    PassDesc& d = pd[k];
+    d = PassDesc{};
+    d.Us = h->Us;
+    d.x = xs[i];
+    d.y = ys[i];
+    d.partials = h->partials;
+    d.st = h->st;
+    d.n = h->n;
+    d.nblk = h->nblk;
+    d.ct = h->ct;
+    d.blk0 = L.nblocks;
+    L.nblocks += h->nblk;
+    ++L.nd;
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    odmd_t h = hs[i];
+    CoreArgs& c = cd[i];
+    c = CoreArgs{};
+    c.st = h->st;
+    c.partials = h->partials;
+    c.nblk = h->nblk;
+    c.r_max = h->r_max;
+    c.basis_f32 = h->basis != ODMD_F64;
+    c.jacobi_only = h->jacobi_only;
+    c.rb = kb[i];
+    c.ct = h->ct;
+    c.fold_slack = fold_slack(h);
+    h->seq = (h->seq + 1) & 0xFFFFFFu;
+    c.fb = h->fb_dev;
+    c.seq = h->seq;
+  }
+  // Copy the used parts of the tables (pageable source: the copy completes
+  // before the call returns, after the work queued on the stream before it,
+  // which includes the kernels of an earlier call that read the tables);
+  // the wait makes sure of that whatever the runtime does, so the static
+  // staging buffer is free when the lock is released.
+  const size_t pbytes = (size_t)count * sizeof(PassDesc), cbytes = (size_t)count * sizeof(CoreArgs);
+  HIP_OK(hipMemcpyAsync(dev, g_noalloc_host, pbytes, hipMemcpyHostToDevice, stream));
+  HIP_OK(hipMemcpyAsync(dev + NOALLOC_PASS_BYTES, g_noalloc_host + NOALLOC_PASS_BYTES, cbytes,
+                        hipMemcpyHostToDevice, stream));
+  HIP_OK(hipStreamSynchronize(stream));
+  const PassDesc* dpd = reinterpret_cast<const PassDesc*>(dev);
+  for (int l = 0; l < nl; ++l) {
+    const Launch& L = launches[l];
+    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, stream));
+  }
+  HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(dev + NOALLOC_PASS_BYTES), count, stream));
+  return ODMD_OK;
+}
+
 odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool out_f32) {
   CombineArgs c{};
   c.st = h->st;
@@ -686,6 +807,27 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
   HIP_OK(hipSetDevice(hs[0]->device));
   if (capturing(hs[0]->stream)) return ODMD_EINVAL;   // staged through host memory: use a plan
   return launch_batch(hs, xs, ys, count);
+}
+
+odmd_status odmd_update_batch_noalloc(odmd_t* hs, const void* const* xs, const void* const* ys,
+                                      int32_t count) {
+  if (!hs || !xs || !ys || count < 0 || count > NOALLOC_MAX) return ODMD_EINVAL;
+  if (count == 0) return ODMD_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i] || !xs[i] || !ys[i] || hs[i]->general) return ODMD_EINVAL;
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return ODMD_EINVAL;
+  }
+  {
+    // duplicates: sorted copy of the handles on the stack (nothing allocated)
+    odmd_t sorted[NOALLOC_MAX];
+    std::copy(hs, hs + count, sorted);
+    std::sort(sorted, sorted + count);
+    for (int32_t i = 1; i < count; ++i)
+      if (sorted[i] == sorted[i - 1]) return ODMD_EINVAL;
+  }
+  HIP_OK(hipSetDevice(hs[0]->device));
+  if (capturing(hs[0]->stream)) return ODMD_EINVAL;   // the tables are copied from host memory
+  return launch_batch_noalloc(hs, xs, ys, count);
 }
 
 odmd_status odmd_sync(odmd_t h) {

@@ -26,7 +26,7 @@ EXPORTS = [
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
     "odmd_profile_samples", "odmd_create_general", "odmd_state_bytes_general",
     "odmd_default_shape", "odmd_create_shaped", "odmd_state_bytes_shaped", "odmd_autotune",
-    "odmd_plan_create", "odmd_plan_launch", "odmd_plan_destroy",
+    "odmd_plan_create", "odmd_plan_launch", "odmd_plan_destroy", "odmd_update_batch_noalloc",
 ]
 
 
@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
             "odmd_update": ([vp, vp, vp], ctypes.c_int),
             "odmd_update_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32],
                                   ctypes.c_int),
+            "odmd_update_batch_noalloc": ([ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), i32], ctypes.c_int),
             "odmd_eigs": ([vp, i32, ctypes.POINTER(i32), pd, pd, pd, pd], ctypes.c_int),
             "odmd_predict": ([vp, i32, vp], ctypes.c_int),
             "odmd_predict_batch": ([ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp), i32],
@@ -283,6 +285,21 @@ def update_batch(models, xs, ys) -> None:
     X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
     Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
     _check(lib().odmd_update_batch(H, X, Y, n), "odmd_update_batch")
+
+
+# most streams of one odmd_update_batch_noalloc call (ODMD_NOALLOC_MAX_STREAMS)
+NOALLOC_MAX_STREAMS = 1024
+
+
+def update_batch_noalloc(models, xs, ys) -> None:
+    """odmd_update_batch_noalloc: the fused update of several streams with
+    no allocation (descriptor tables in the library's fixed device array);
+    results equal update_batch's bit for bit."""
+    n = len(models)
+    H = (ctypes.c_void_p * n)(*[m.handle for m in models])
+    X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
+    Y = (ctypes.c_void_p * n)(*[_dptr(y) for y in ys])
+    _check(lib().odmd_update_batch_noalloc(H, X, Y, n), "odmd_update_batch_noalloc")
 
 
 class Plan:

@@ -88,6 +88,7 @@ def test_null_arguments_are_rejected():
     assert L.odmd_destroy(None) == 1
     assert L.odmd_predict(None, 5, None) == 1
     assert L.odmd_update_batch(None, None, None, 1) == 1
+    assert L.odmd_update_batch_noalloc(None, None, None, 1) == 1
     r = ctypes.c_int32()
     assert L.odmd_eigs(None, 4, ctypes.byref(r), None, None, None, None) == 1
     assert L.odmd_get_info(None, None) == 1
@@ -194,3 +195,19 @@ def test_info_struct_matches_the_header():
     fields = re.findall(r"(int32_t|int64_t|double)\s+(\w+);", body)
     ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
     assert [(n, ctype[t]) for t, n in fields] == list(B.Info._fields_)
+
+
+@needs_lib
+def test_noalloc_batch_limits_are_host_checked():
+    """The no-allocation batched update rejects more streams than its fixed
+    tables hold, and NULL entries, on the host (no handle is dereferenced,
+    no device call is made)."""
+    L = B.lib()
+    cnt = B.NOALLOC_MAX_STREAMS + 1
+    H = (ctypes.c_void_p * cnt)()
+    X = (ctypes.c_void_p * cnt)()
+    Y = (ctypes.c_void_p * cnt)()
+    assert L.odmd_update_batch_noalloc(H, X, Y, cnt) == 1
+    assert L.odmd_update_batch_noalloc(H, X, Y, -1) == 1
+    assert L.odmd_update_batch_noalloc(H, X, Y, 0) == 0          # nothing to do
+    assert L.odmd_update_batch_noalloc(H, X, Y, 2) == 1          # NULL handles
