@@ -74,10 +74,10 @@ odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
  * prediction output) type, the HIP stream (hipStream_t, NULL = null
  * stream) and optionally caller-owned device memory.
  *   basis: ODMD_F64, ODMD_F32 or ODMD_BF16 (stored columns rounded to
- *          nearest even; residuals, projections and the small problems
- *          stay FP64).  The effective tolerance is max(tol, 16 * 2^-24)
- *          for an FP32 basis and max(tol, 2^-8) for BF16: the storage
- *          cannot hold a direction weaker than that.
+ *          nearest even; residuals, projections, the rotation of the stored
+ *          columns and the small problems stay FP64).  The effective
+ *          tolerance is tol for FP64 and FP32 bases and max(tol, 2^-8) for
+ *          BF16: a BF16 basis cannot hold a direction weaker than that.
  *   io:    ODMD_F64 or ODMD_F32; equal to basis for F64/F32 bases, ODMD_F32
  *          for a BF16 basis.
  *   The small SVD of each update is solved through its secular equation,
@@ -327,7 +327,7 @@ typedef struct {
   int32_t r_max;
   int64_t n;
   int64_t m;          /* accepted pairs                                 */
-  double tol_eff;     /* tolerance in use (after the FP32 clamp)        */
+  double tol_eff;     /* tolerance in use (after the BF16 clamp)        */
   double last_rho;    /* residual norm of the last accepted update      */
   int32_t last_sweeps;/* Jacobi sweeps of the last small SVD            */
   int32_t nblocks;    /* workgroups of the streaming pass               */

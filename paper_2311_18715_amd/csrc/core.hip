@@ -608,7 +608,6 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
         if (cr >= CMAX) continue;
         const int idx = cr * RMAX + k0 + (l & 15);
         tst->Q[idx] = rt[h][v];
-        if (c.basis_f32) tst->Q32[idx] = (float)rt[h][v];
       }
     }
   }
@@ -840,7 +839,6 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
         const int c0 = idx / RMAX, j = idx % RMAX;
         const double v = (c0 == j && j < r) ? 1.0 : 0.0;
         st->Q[idx] = v;
-        if (c.basis_f32) st->Q32[idx] = (float)v;
       }
       if (tid < CMAX) st->a[tid] = tid < r ? st->py[tid] : 0.0;
     }
@@ -851,7 +849,6 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
         const int c0 = idx / RMAX, j = idx % RMAX;
         const double v = (c0 == j && j < r) ? 1.0 : 0.0;
         tst->Q[idx] = v;
-        if (c.basis_f32) tst->Q32[idx] = (float)v;
       }
     }
     __syncthreads();
@@ -1062,7 +1059,6 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
           if (cr >= CMAX) continue;
           const int idx = cr * RMAX + k0 + (l & 15);
           st->Q[idx] = qt[h][v];
-          if (c.basis_f32) st->Q32[idx] = (float)qt[h][v];
         }
       }
     }

@@ -266,7 +266,6 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.partials = h->partials;
   c.nblk = h->nblk;
   c.r_max = h->r_max;
-  c.basis_f32 = h->basis != ODMD_F64;
   c.jacobi_only = h->jacobi_only;
   c.rb = kb;
   c.ct = h->ct;
@@ -407,7 +406,6 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     c.partials = h->partials;
     c.nblk = h->nblk;
     c.r_max = h->r_max;
-    c.basis_f32 = h->basis != ODMD_F64;
     c.jacobi_only = h->jacobi_only;
     c.rb = kb[i];
     c.ct = h->ct;
@@ -537,7 +535,6 @@ odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* 
     c.partials = h->partials;
     c.nblk = h->nblk;
     c.r_max = h->r_max;
-    c.basis_f32 = h->basis != ODMD_F64;
     c.jacobi_only = h->jacobi_only;
     c.rb = kb[i];
     c.ct = h->ct;
@@ -691,11 +688,11 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
   s->r_max = r_max;
   s->ct = L.ct;
   s->tol = tol;
-  // a stored basis cannot hold a direction weaker than its own rounding:
-  // FP32 16 units of roundoff, BF16 one unit (2^-8)
-  s->tol_eff = basis == ODMD_F32    ? std::max(tol, 16.0 * 5.9604644775390625e-08)
-               : basis == ODMD_BF16 ? std::max(tol, 0.00390625)
-                                    : tol;
+  // A BF16 stored basis cannot hold a direction weaker than one unit of its
+  // rounding (2^-8): every refold rounds the rotated basis to BF16 again.
+  // FP64 and FP32 bases take the tolerance as given (the refold is FP64, so
+  // FP32 storage adds only its own rounding to the new columns).
+  s->tol_eff = basis == ODMD_BF16 ? std::max(tol, 0.00390625) : tol;
   s->basis = basis;
   s->io = io;
   s->stream = static_cast<hipStream_t>(hip_stream);
@@ -1098,7 +1095,6 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
     c.partials = h->partials;
     c.nblk = h->nblk;
     c.r_max = h->r_max;
-    c.basis_f32 = h->basis != ODMD_F64;
     c.jacobi_only = h->jacobi_only;
     c.rb = h->ct;
     c.ct = h->ct;

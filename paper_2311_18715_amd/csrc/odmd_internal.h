@@ -85,7 +85,6 @@ struct DevState {
   double a[CMAX];       // Q p1: coefficients of the next pass's first projection
   double p1[RMAX];      // U^T x of a general pair (chained pairs use py)
   double Q[RMAX * CMAX];      // m x r, row c (stored column c) at Q + c*RMAX
-  float Q32[RMAX * CMAX];     // FP32 copy for FP32 storage
   double C[RMAX * RMAX];      // r x r: shifted product W[2:]^T W[:-1] (chained
                               // pairs) or G = U^T B (general pairs)
   double At[RMAX * RMAX];     // A~ (r x r)

@@ -54,7 +54,6 @@ struct CoreArgs {
   const double* partials;
   int nblk;
   int r_max;
-  int basis_f32;        // also keep an FP32 copy of the rotation
   int jacobi_only;      // skip the secular solver (diagnostics)
   int rb;               // live-column bucket of the pass (compact partial records)
   int ct;               // stored-column capacity of the stream

@@ -50,10 +50,15 @@ template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
+// The refold S[:, :r] <- S Q runs in FP64 on the matrix cores for every
+// storage type: the stored values convert exactly, Q enters unrounded and the
+// sums are FP64, so the only error of the new columns is their own rounding
+// to the storage type.  (Rounding Q to FP32 for an FP32 product perturbs
+// the basis inside its own span by FP32 roundoff at every refold; that loss
+// of orthogonality compounds and needs a rank tolerance far above the
+// storage's resolution to stay stable.)
+struct RefoldMfma {
   typedef d4_t acc_t;
   __device__ static cptr<double> Q(const DevState* s) { return (cptr<double>)s->Q; }
   __device__ static acc_t mma(double a, double b, acc_t c) {
@@ -61,14 +66,6 @@ template <> struct Mfma<double> {
   }
   // result element v of lane l sits in result row dsub(l, v), column l % 16
   __device__ static int dsub(int l, int v) { return 4 * v + (l >> 4); }
-};
-template <> struct Mfma<float> {
-  typedef f4_t acc_t;
-  __device__ static cptr<float> Q(const DevState* s) { return (cptr<float>)s->Q32; }
-  __device__ static acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static int dsub(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
 // PROJ: projection-only sweep of a general pair (e = x: the sums S^T x,
@@ -88,8 +85,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   constexpr int KK = RB / 4;              // k-steps over the RB live stored columns
   constexpr int NT = ((RB < RMAX ? RB : RMAX) + 15) / 16;   // 16-column output blocks of a refold (r <= RMAX)
   constexpr int NWAVE = NTH / 64;           // waves of the workgroup
-  typedef typename SC::tc TC;             // compute type of the matrix-core refold
-  typedef typename Mfma<TC>::acc_t acc_t;
+  typedef RefoldMfma::acc_t acc_t;
 
   const DevState* __restrict__ st = p.st;
   const int m = st->m, r = st->r, refold = PROJ ? 0 : st->refold;
@@ -155,7 +151,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   // Q[4 kk + lane/16][16 nt + lane%16]) for a refold.  a is loaded before
   // the first unit, so that waiting for it leaves the unit's loads in flight.
   static_assert(NTH >= 4 * KK, "one thread per coefficient");
-  __shared__ TC sG[KK][NT][64];
+  __shared__ double sG[KK][NT][64];
   __shared__ double sa[4 * KK];          // a, zero past the m stored columns
   const int ca = threadIdx.x;
   const double a_c = (ca < 4 * KK && ca < m) ? st->a[ca] : 0.0;
@@ -166,11 +162,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   load_unit(u < u1 ? u : u0, A, xv, yv);
   if (ca < 4 * KK) sa[ca] = a_c;
   if (refold) {
-    cptr<TC> Q = Mfma<TC>::Q(st);
+    cptr<double> Q = RefoldMfma::Q(st);
     for (int idx = threadIdx.x; idx < KK * NT * 64; idx += NTH) {
       const int ln = idx & 63, nt = (idx >> 6) % NT, kk = (idx >> 6) / NT;
       const int c = 4 * kk + (ln >> 4), col = 16 * nt + (ln & 15);
-      sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : TC(0);
+      sG[kk][nt][ln] = (c < m && col < r) ? Q[c * RMAX + col] : 0.0;
     }
   }
   __syncthreads();
@@ -255,15 +251,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
         if (16 * nt >= r) break;   // uniform: output blocks past the rank hold no column
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
+          // the FP64 operands are converted again for every block and row,
+          // not held across them (that would double the stored values'
+          // registers)
+          fence_rows(A);
           acc_t d = acc_t{0, 0, 0, 0};
 #pragma unroll
           for (int kk = 0; kk < KK; ++kk)
-            d = Mfma<TC>::mma(sG[kk][nt][lane], SC::to_tc(SC::elem(A[kk], j)), d);
+            d = RefoldMfma::mma(sG[kk][nt][lane], SC::to_double(SC::elem(A[kk], j)), d);
           if (row0 + j < p.n) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int col = 16 * nt + Mfma<TC>::dsub(lane, v);
-              if (col < r) T[col * 64 + rr0 + j] = SC::from_tc(d[v]);
+              const int col = 16 * nt + RefoldMfma::dsub(lane, v);
+              if (col < r) T[col * 64 + rr0 + j] = SC::from_double(d[v]);
             }
           }
         }
