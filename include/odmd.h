@@ -207,8 +207,13 @@ odmd_status odmd_autotune(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype
 odmd_status odmd_update(odmd_t h, const void* x_k, const void* x_k1);
 
 /*
- * Append one pair to each of `count` handles in one fused launch.  All
- * handles must share one device and one HIP stream (that of hs[0]);
+ * Append one pair to each of `count` handles: Sec. 2.3's rank-1 update
+ * (as odmd_update) of every handle in one batched step.  The streaming
+ * passes of all handles run as one launch per group of handles with the
+ * same launch shape, storage type and live-column bucket (the groups'
+ * launches on up to four side streams of default priority, joined to the
+ * handles' stream), then one launch runs every handle's small-state update.
+ * All handles must share one device and one HIP stream (that of hs[0]);
  * duplicates are not allowed.  hs, xs, ys: host arrays of length count;
  * xs[i], ys[i] are device pointers as in odmd_update.  Results are
  * identical, bit for bit, to calling odmd_update on each handle.
@@ -276,7 +281,9 @@ odmd_status odmd_plan_launch(odmd_plan_t plan);
 odmd_status odmd_plan_destroy(odmd_plan_t plan);
 
 /*
- * Eigenpairs of A~ (synchronising).  cap: capacity of the output arrays
+ * Eigenpairs of A~ (synchronising): the eigendecomposition A~ = V Lambda V^-1
+ * of Sec. 2.3, whose columns of V give the projected DMD modes Phi = U V.
+ * cap: capacity of the output arrays
  * (eigenvalue count; V arrays hold cap*cap doubles).  Outputs (host):
  *   *r        current rank;
  *   lam_re/im eigenvalues, |lambda| descending, then Im descending;

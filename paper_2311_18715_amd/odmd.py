@@ -279,7 +279,9 @@ class ODMD:
 
 
 def update_batch(models, xs, ys) -> None:
-    """One fused update of several streams (odmd_update_batch)."""
+    """One batched update of several streams (odmd_update_batch: one pass
+    launch per group of equal launch shape, storage type and live-column
+    bucket, then one small-state launch for all)."""
     n = len(models)
     H = (ctypes.c_void_p * n)(*[m.handle for m in models])
     X = (ctypes.c_void_p * n)(*[_dptr(x) for x in xs])
@@ -292,7 +294,7 @@ NOALLOC_MAX_STREAMS = 1024
 
 
 def update_batch_noalloc(models, xs, ys) -> None:
-    """odmd_update_batch_noalloc: the fused update of several streams with
+    """odmd_update_batch_noalloc: the batched update of several streams with
     no allocation (descriptor tables in the library's fixed device array);
     results equal update_batch's bit for bit."""
     n = len(models)

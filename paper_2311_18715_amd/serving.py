@@ -9,7 +9,8 @@ streams free enough.
 
 Each scheduling round takes the head request of every admitted stream that
 has one: all head updates go to the device as one batched update
-(odmd_update_batch, one fused launch per kernel for all of them), head
+(odmd_update_batch: one pass launch per group of like streams, one
+small-state launch for all), head
 predictions are queued behind it.  Requests that arrive while a round runs on
 the device join the next round; a stream's requests are served strictly in
 order, so every result equals the one the stream would get alone (the

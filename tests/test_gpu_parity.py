@@ -263,3 +263,91 @@ def test_refold_limit_follows_the_rank():
             assert st["r"] == o.r
             np.testing.assert_allclose(st["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
         g.close()
+
+
+def _basis_invariant_err(g, o, n, seed=3):
+    """max |U A~ U^T P - U_o A~_o U_o^T P| over random probes P, relative:
+    the DMD operator on span(U) does not depend on the basis chosen inside
+    ties of equal singular values."""
+    U = g.basis_matrix().cpu().numpy()
+    P = np.random.default_rng(seed).standard_normal((n, 4))
+    Pg = U @ (g.state()["atilde"] @ (U.T @ P))
+    Po = o.U @ (o.atilde() @ (o.U.T @ P))
+    return np.max(np.abs(Pg - Po)) / np.max(np.abs(Po))
+
+
+def test_tied_singular_values_and_orthogonal_appends(core_svd):
+    """Special cases of the core (Sec. 2.3's rank-1 append with a core
+    K = [[diag sigma, p], [0, rho]]):
+      * x orthogonal to span(U) with the norm of every earlier snapshot:
+        p = 0 and rho = sigma_i, so K is diagonal with all values tied (every
+        secular term deflates);
+      * then a snapshot mixing all earlier directions plus a new one: p has
+        nonzero entries on exactly tied poles, which the secular solver must
+        merge by rotations before it solves;
+      * then ordinary snapshots.
+    Compared with the oracle by invariants (sorted sigma, the operator
+    U A~ U^T on probes, orthogonality), since the singular vectors inside a
+    tie are not unique."""
+    n, k = 5000, 12
+    X = np.zeros((n, k + 8))
+    rows = np.random.default_rng(11).permutation(n)[:k + 1]
+    for j in range(k):
+        X[rows[j], j] = 3.0                     # equal norms, orthogonal
+    a = np.random.default_rng(12).standard_normal(k)
+    X[rows[:k], k] = a                          # mixes every tied direction
+    X[rows[k], k] = 0.5                         # plus a new one
+    X[:, k + 1:] = np.random.default_rng(13).standard_normal((n, 7))
+    g, o = run_both(X, 24, 1e-12, steps=k - 1)
+    st = g.state()
+    assert st["r"] == o.r == k - 1
+    np.testing.assert_allclose(st["sigma"], 3.0, rtol=1e-14)      # all tied
+    for steps in (k, k + 1, X.shape[1] - 1):                        # the merge, then more
+        g, o = run_both(X, 24, 1e-12, steps=steps)
+        st = g.state()
+        assert st["r"] == o.r
+        np.testing.assert_allclose(st["sigma"], o.sigma, rtol=1e-12, atol=1e-14 * o.sigma[0])
+        assert orth_err(g) < 1e-12
+        assert _basis_invariant_err(g, o, n) < 1e-10
+        g.close()
+
+
+def test_full_size_wake_all_updates():
+    """The benchmark's stream exactly (wake on a 400 x 200 grid, n =
+    160,000, noise 1e-6, r_max 40, tol 1e-8, all 1999 updates, the launch
+    the benchmark times) against the oracle: rank and sigma every 200
+    updates, then the eigenvalues of the planted modes present in the data
+    (mean flow, shedding harmonics), orthogonality and a 500-state
+    rollout."""
+    s = synth.wake(nx=400, ny=200, noise=1e-6)
+    X = s.snapshots(0, 2000)
+    print("wake n=160000: 1999 updates against the oracle", flush=True)
+    g, o = run_both(X, 40, 1e-8, check_every=200)
+    st = g.state()
+    assert st["r"] == o.r == 40
+    np.testing.assert_allclose(st["sigma"], o.sigma, rtol=1e-11, atol=1e-13 * o.sigma[0])
+    lam, _ = g.eigs()
+    lo, _ = o.eigs()
+    pl = s.planted_eigs()[:11]
+    mg, mo = O.match_eigs(pl, lam), O.match_eigs(pl, lo)
+    assert np.max(np.abs(mg - mo) / np.abs(mo)) < 1e-10
+    # the other eigenvalues belong to noise directions (reading: the 1e-10
+    # tolerance applies to the planted ones).  A~_ij carries 1/sigma_j, so
+    # rounding in the columns of the noise directions (sigma_j down to
+    # 1e-6 sigma_1) is amplified; the operator on the directions above the
+    # noise, U_k A~_kk U_k^T with sigma_k >= 1e-4 sigma_1, must agree to 1e-10
+    print(f"all eigenvalues with |lambda| >= 1e-2 max: {rel_eig_err(lo, lam):.2e}; "
+          f"whole operator on probes: {_basis_invariant_err(g, o, X.shape[0]):.2e}", flush=True)
+    k = int(np.sum(o.sigma >= 1e-4 * o.sigma[0]))
+    assert k >= 11
+    U = g.basis_matrix().cpu().numpy()[:, :k]
+    P = np.random.default_rng(5).standard_normal((X.shape[0], 4))
+    Pg = U @ (st["atilde"][:k, :k] @ (U.T @ P))
+    Po = o.U[:, :k] @ (o.atilde()[:k, :k] @ (o.U[:, :k].T @ P))
+    assert np.max(np.abs(Pg - Po)) < 1e-10 * np.max(np.abs(Po))
+    assert orth_err(g) < 1e-12
+    pg = g.predict(500).cpu().numpy()
+    po = o.predict(500)
+    err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)
+    print(f"rollout over 500 states: max relative difference {err.max():.2e}", flush=True)
+    assert err.max() < 1e-9
