@@ -4,9 +4,24 @@
 //     out[k*ldo + i] = sum_{j < m} S(i, j) * coefA[k*CMAX + j],
 // S(i, j) stored at ((i/64)*ct + j)*64 + i%64 (64-row tiles).
 // This is the O(N r) prediction of Sec. 2.3 (one read of the basis, one
-// write per predicted state).  Each thread keeps one row of S in registers
-// and streams the output rows; coefficient columns are wave-uniform and come
-// through the scalar cache.
+// write per predicted state).
+//
+// As a product it is Out (K x n) = Coef (K x m) S^T (m x n) with a short
+// contraction (m <= 72): 2 K n m flops against K n output writes.  At the
+// FP64 matrix-core rate this GPU reaches in practice (about 45 TFLOP/s, a
+// 16x16x4 product every ~100 cycles per SIMD) the flops take longer than
+// the writes: it is bound by the matrix cores.  It runs on
+// the FP64 matrix cores (16x16x4): a wavefront takes 16 rows of one tile in
+// the streaming pass's operand layout (lane l holds row l%16 of stored
+// columns 4 kk + l/16, so one column of the unit is a 128-byte line for
+// FP64) and multiplies them by 16-step blocks of coefficients staged in LDS
+// in the operand layout; lane l then holds states 4 v + l/16 of the block
+// at row l%16, so 16 lanes write 16 consecutive rows of one state (streaming
+// stores: the states are not read again here).  The
+// stored values convert exactly to FP64, the coefficients are FP64 and so
+// are the sums; the output is rounded once, to its type.  A workgroup covers
+// RPW rows and 16 NS states; its stored columns are read once per 16 NS
+// states.
 #include <hip/hip_runtime.h>
 
 #include "odmd_internal.h"
@@ -15,26 +30,103 @@
 
 namespace odmd {
 
-template <typename TS, typename TO, int RB>
-__global__ __launch_bounds__(256) void k_combine(CombineArgs c) {
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int CB_THREADS = 256;          // four wavefronts
+constexpr int CB_RPW = 512;              // rows per workgroup (8 tiles)
+
+// NS 16-state blocks per workgroup (the host picks NS from the number of
+// states, so that a short rollout computes no more than 16 states in vain)
+template <typename TS, typename TO, int RB, int NS>
+__global__ __launch_bounds__(CB_THREADS) void k_combine(CombineArgs c) {
+  typedef Storage<TS> SC;
+  constexpr int KK = RB / 4;                 // k-steps over the stored columns
+  constexpr int NW = CB_THREADS / 64;
   const DevState* __restrict__ st = c.st;
-  const int ncols = st->m;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= c.n) return;
+  const int m = st->m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, l16 = lane & 15;
+  const int k0 = blockIdx.y * (16 * NS);
+
+  // coefficients of the workgroup's states in the A-operand layout:
+  // sC[s][kk][lane] = coef(state k0 + 16 s + lane%16, column 4 kk + lane/16)
+  __shared__ double sC[NS][KK][64];
+  for (int idx = threadIdx.x; idx < NS * KK * 64; idx += CB_THREADS) {
+    const int ln = idx & 63, kk = (idx >> 6) % KK, s = (idx >> 6) / KK;
+    const int k = k0 + 16 * s + (ln & 15), col = 4 * kk + (ln >> 4);
+    sC[s][kk][ln] = (k < c.K && col < m) ? st->coefA[k * CMAX + col] : 0.0;
+  }
+
   const TS* __restrict__ Us = static_cast<const TS*>(c.Us);
   TO* __restrict__ out = static_cast<TO*>(c.out);
-  double u[RB];
-  const TS* __restrict__ T = Us + (i >> 6) * (int64_t)c.ct * 64 + (i & 63);
+  const int64_t r0 = (int64_t)blockIdx.x * CB_RPW;
+  const int64_t rend = r0 + CB_RPW < c.n ? r0 + CB_RPW : c.n;
+  const int nunit = (int)((rend - r0 + 15) / 16);
+  const int kmax = (m + 3) / 4;              // live k-steps (uniform)
+  // the unit's stored values stay in their storage type until used; the next
+  // unit's loads are in flight while the current one is multiplied
+  auto load = [&](int u, TS (&A)[KK]) {
+    const int64_t row0 = r0 + 16 * u;        // 16-row units never straddle a tile
+    const TS* __restrict__ T = Us + (row0 >> 6) * (int64_t)c.ct * 64 + (row0 & 63);
 #pragma unroll
-  for (int j = 0; j < RB; ++j) u[j] = j < ncols ? Storage<TS>::to_double(T[j * 64]) : 0.0;
-  const int k0 = blockIdx.y * c.kb;
-  const int k1 = min(c.K, k0 + c.kb);
-  // coefficients are read-only for the launch: scalar loads via the
-  // constant address space
+    for (int kk = 0; kk < KK; ++kk)
+      if (kk < kmax) A[kk] = T[(4 * kk + q) * 64 + l16];
+  };
+  TS A[KK], An[KK];
+  int u = wave;
+  if (u < nunit) load(u, A);
+  __syncthreads();
+  for (; u < nunit; u += NW) {
+    if (u + NW < nunit) load(u + NW, An);    // uniform
+    d4_t d[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) d[s] = d4_t{0.0, 0.0, 0.0, 0.0};
+    // the NS accumulator chains are independent: k-steps outermost
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      if (kk < kmax) {                       // uniform
+        const double a = SC::to_double(A[kk]);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          d[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(sC[s][kk][lane], a, d[s], 0, 0, 0);
+      }
+    }
+    // the states are written once and not read again here: streaming stores
+    const int64_t row = r0 + 16 * u + l16;
+    if (row < c.n) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = k0 + 16 * s + 4 * v + q;
+          if (k < c.K) __builtin_nontemporal_store((TO)d[s][v], out + (int64_t)k * c.ldo + row);
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) A[kk] = An[kk];
+  }
+}
+
+// A few states (a one-step prediction, Sec. 2.3's u(t + dt)): bound by the
+// read of the stored columns, not by the flops.  One row per lane (a wave
+// reads 64 consecutive rows of a column, one 64-row tile), the coefficients
+// of each state uniform across the wave (scalar loads); the stored values
+// are read once for all the states of the launch.
+constexpr int CR_KMAX = 4;
+template <typename TS, typename TO, int RB>
+__global__ __launch_bounds__(256) void k_combine_rows(CombineArgs c) {
+  const DevState* __restrict__ st = c.st;
+  const int m = st->m;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= c.n) return;
+  const TS* __restrict__ T = static_cast<const TS*>(c.Us) + (i >> 6) * (int64_t)c.ct * 64 + (i & 63);
+  double u[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) u[j] = j < m ? Storage<TS>::to_double(T[j * 64]) : 0.0;
   typedef const __attribute__((address_space(4))) double* cdp;
   cdp A = (cdp)st->coefA;
-  for (int k = k0; k < k1; ++k) {
-    asm volatile("" : "+s"(A));
+  TO* __restrict__ out = static_cast<TO*>(c.out);
+  for (int k = 0; k < c.K; ++k) {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < RB; ++j) acc = __builtin_fma(u[j], A[k * CMAX + j], acc);
@@ -42,22 +134,47 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs c) {
   }
 }
 
-template <typename TS, typename TO>
-static hipError_t launch_t(const CombineArgs& c, int rb, hipStream_t s) {
-  const dim3 grid((unsigned)((c.n + 255) / 256), (unsigned)((c.K + c.kb - 1) / c.kb)), block(256);
+template <typename TS, typename TO, int NS>
+static hipError_t launch_ns(const CombineArgs& c, int rb, hipStream_t s) {
+  const dim3 grid((unsigned)((c.n + CB_RPW - 1) / CB_RPW), (unsigned)((c.K + 16 * NS - 1) / (16 * NS)));
+  const dim3 block(CB_THREADS);
   switch (rb) {
-    case 8: hipLaunchKernelGGL((k_combine<TS, TO, 8>), grid, block, 0, s, c); break;
-    case 16: hipLaunchKernelGGL((k_combine<TS, TO, 16>), grid, block, 0, s, c); break;
-    case 24: hipLaunchKernelGGL((k_combine<TS, TO, 24>), grid, block, 0, s, c); break;
-    case 32: hipLaunchKernelGGL((k_combine<TS, TO, 32>), grid, block, 0, s, c); break;
-    case 40: hipLaunchKernelGGL((k_combine<TS, TO, 40>), grid, block, 0, s, c); break;
-    case 48: hipLaunchKernelGGL((k_combine<TS, TO, 48>), grid, block, 0, s, c); break;
-    case 56: hipLaunchKernelGGL((k_combine<TS, TO, 56>), grid, block, 0, s, c); break;
-    case 64: hipLaunchKernelGGL((k_combine<TS, TO, 64>), grid, block, 0, s, c); break;
-    case 72: hipLaunchKernelGGL((k_combine<TS, TO, 72>), grid, block, 0, s, c); break;
+#define ODMD_CASE(RB) \
+  case RB: hipLaunchKernelGGL((k_combine<TS, TO, RB, NS>), grid, block, 0, s, c); break;
+    ODMD_CASE(8) ODMD_CASE(16) ODMD_CASE(24) ODMD_CASE(32) ODMD_CASE(40) ODMD_CASE(48)
+    ODMD_CASE(56) ODMD_CASE(64) ODMD_CASE(72)
+#undef ODMD_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename TS, typename TO>
+static hipError_t launch_rows(const CombineArgs& c, int rb, hipStream_t s) {
+  const dim3 grid((unsigned)((c.n + 255) / 256)), block(256);
+  switch (rb) {
+#define ODMD_CASE(RB) \
+  case RB: hipLaunchKernelGGL((k_combine_rows<TS, TO, RB>), grid, block, 0, s, c); break;
+    ODMD_CASE(8) ODMD_CASE(16) ODMD_CASE(24) ODMD_CASE(32) ODMD_CASE(40) ODMD_CASE(48)
+    ODMD_CASE(56) ODMD_CASE(64) ODMD_CASE(72)
+#undef ODMD_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename TS, typename TO>
+static hipError_t launch_t(const CombineArgs& c, int rb, hipStream_t s) {
+  if (c.K <= CR_KMAX) return launch_rows<TS, TO>(c, rb, s);
+  // more 16-state blocks per workgroup: more independent accumulator
+  // chains per wave (the FP64 matrix-core chains are latency-bound: 500
+  // states at n = 160,000 and 56 columns took 182 us of matrix-core time
+  // with eight blocks against 237 us with four) and fewer re-reads of the
+  // stored columns, at the price of LDS (eight blocks of 72 columns: 72 KB)
+  if (c.K <= 16) return launch_ns<TS, TO, 1>(c, rb, s);
+  if (c.K <= 32) return launch_ns<TS, TO, 2>(c, rb, s);
+  if (c.K <= 64) return launch_ns<TS, TO, 4>(c, rb, s);
+  return launch_ns<TS, TO, 8>(c, rb, s);
 }
 
 hipError_t launch_combine(const CombineArgs& c, int basis, int out_f32, int rb, hipStream_t s) {

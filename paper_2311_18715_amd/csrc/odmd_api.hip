@@ -571,10 +571,6 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   c.ct = h->ct;
   c.ldo = ldo;
   c.K = K;
-  const int64_t xb = (h->n + 255) / 256;
-  int ysplit = (int)std::max<int64_t>(1, (1024 + xb - 1) / xb);
-  ysplit = std::min(ysplit, std::max(1, (K + 7) / 8));
-  c.kb = (K + ysplit - 1) / ysplit;
   HIP_OK(launch_combine(c, (int)h->basis, out_f32, h->ct, h->stream));
   return ODMD_OK;
 }

@@ -87,7 +87,7 @@ struct CombineArgs {
   void* out;            // out[k*ldo + i], k < K
   int64_t n, ldo;
   int ct;               // column capacity of a basis tile
-  int K, kb;            // columns, columns per workgroup row of the grid
+  int K;                // columns (predicted states) of this launch
 };
 // out type: 0 = FP64, 1 = FP32; basis: storage type code as for launch_pass
 hipError_t launch_combine(const CombineArgs& c, int basis, int out_f32, int rb, hipStream_t s);
