@@ -663,66 +663,99 @@ def graph_section(torch):
 
 
 # serving form: Poisson arrivals over many streams, admission under a budget
-SERVE_COUNT, SERVE_N, SERVE_UPDATES, SERVE_PRED = 128, (1e4, 2e5), (100, 200), 100
-SERVE_RATES = (2e4, 6e4, 2e5)          # offered requests/s
-SERVE_BUDGET_FRAC = 0.4                # of the streams' total device state
+SERVE_COUNT, SERVE_N, SERVE_UPDATES, SERVE_PRED = 1024, (1e4, 2e6), (20, 60), 100
+SERVE_RATES = (2e4, 6e4, 1.5e5, 4e5)    # offered requests/s, at the 200 GB budget
+SERVE_BUDGET = 200 << 30
+SERVE_TIGHT = (20 << 30, 6e4)           # a budget that binds, at one offered rate
+
+
+class _DPtr:
+    """A device address with the data_ptr() the serving loop reads."""
+    __slots__ = ("p",)
+
+    def __init__(self, p):
+        self.p = p
+
+    def data_ptr(self):
+        return self.p
 
 
 def serving_section(torch):
-    """Streams with n log-uniform in [1e4, 2e5], r_max in {16, 32, 64}, FP32
-    or BF16 basis (one half each), planted rank in {6..30}, U[100, 200]
-    updates each.  All streams
-    ask for admission at the start; the budget holds 40 % of their state, so
-    later streams wait for earlier ones to close.  Requests arrive as a
-    Poisson process at the offered rate, each from a random admitted,
-    unfinished stream (a simulation sends snapshots once it has a slot):
-    90 % its next update, 10 % a 100-state prediction.  Reports achieved
-    rates, p50/p99 request latency (submission to observed completion) and
-    the streams' admission waits."""
-    import math
+    """The serving form at its full size: 1024 streams, n log-uniform in
+    [1e4, 2e6], r_max in {16, 32, 64}, FP32 or BF16 basis (one half each),
+    planted rank in {6..30}, under a 200 GB budget.  Each stream sends
+    U[20, 60] updates in a run (the stand-in for a simulation's snapshot
+    stream, shortened so that a run of the sweep takes seconds) and closes.
+    Requests arrive as a Poisson process at the offered rate, each from a
+    random admitted, unfinished stream: 90 % its next update, 10 % a
+    100-state prediction (of a stream with at least one update).  Reports
+    the achieved rates, p50/p99 latency of updates and predictions
+    (submission to observed completion), requests per round, and, for a
+    20 GB budget that holds only part of the streams, the admission waits.
+    Snapshots are formed on the device beforehand (device Gaussian modes,
+    FP32); prediction outputs are freed as their rounds complete."""
+    from paper_2311_18715_amd import synth
     from paper_2311_18715_amd.odmd import ODMD
     from paper_2311_18715_amd.serving import Server
-    rng = np.random.Generator(np.random.PCG64(231118715 + 5))
+    rng = np.random.Generator(np.random.PCG64(231118715 + 11))
     specs = []
     for i in range(SERVE_COUNT):
         n = int(round(math.exp(rng.uniform(math.log(SERVE_N[0]), math.log(SERVE_N[1])))))
         specs.append((n, int(rng.integers(6, 31)), int(rng.choice([16, 32, 64])),
                       int(rng.integers(SERVE_UPDATES[0], SERVE_UPDATES[1] + 1)), 231118715 + 7000 + i,
                       "bf16" if rng.random() < 0.5 else "f32"))
-    data = [_DeviceStream(torch, n, rank, seed).chunk(0, m + 1).float()
-            for (n, rank, _, m, seed, _) in specs]
+    data = []
+    for (n, rank, _, m, seed, _) in specs:
+        gen = synth.DevicePlanted(torch, n, rank, seed, dtype=torch.float32)
+        data.append(gen.chunk(0, m + 1))
+        del gen
+    torch.cuda.synchronize()
+    ptrs = [[_DPtr(X.data_ptr() + k * X.shape[1] * 4) for k in range(X.shape[0])] for X in data]
     need = [ODMD.state_bytes(n, rmax, basis) for (n, _, rmax, _, _, basis) in specs]
-    budget = int(SERVE_BUDGET_FRAC * sum(need)) + max(need)
-    out = {"streams": SERVE_COUNT, "budget_bytes": budget, "total_state_bytes": int(sum(need)),
-           "rates": []}
-    for rate in SERVE_RATES:
-        S = Server(budget)
+    out = {"streams": SERVE_COUNT, "n_range": list(SERVE_N), "total_state_bytes": int(sum(need)),
+           "snapshot_bytes": int(sum(X.numel() * 4 for X in data)), "runs": []}
+
+    def run(budget, rate):
+        S = Server(budget, keep_outputs=False)
         for i, (n, _, rmax, _, _, basis) in enumerate(specs):
             S.open(i, n, rmax, 1e-8, basis)
         pos = [0] * SERVE_COUNT
         left = set(range(SERVE_COUNT))
+        pending = set(range(SERVE_COUNT))        # open streams not yet admitted
+        active, predictable = [], []
         n_req = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         next_t = t0
         t_admit = {}
+        t_say = t0 + 5.0
         while left:
             now = time.perf_counter()
-            for i in left:
-                if i not in t_admit and S.admitted(i):
+            if now > t_say:
+                print(f"serving budget {budget >> 30} GB, rate {rate:g}: {n_req} requests, "
+                      f"{len(left)} streams open", file=sys.stderr, flush=True)
+                t_say = now + 5.0
+            if pending:
+                for i in [i for i in pending if S.admitted(i)]:
+                    pending.discard(i)
                     t_admit[i] = now - t0
-            active = sorted(i for i in left if i in t_admit)
+                    active.append(i)
             while active and next_t <= now:
-                i = int(rng.choice(active))
-                if rng.random() < 0.1:
-                    S.submit_predict(i, SERVE_PRED)
+                if predictable and rng.random() < 0.1:
+                    S.submit_predict(predictable[int(rng.integers(len(predictable)))], SERVE_PRED)
                 else:
+                    j = int(rng.integers(len(active)))
+                    i = active[j]
                     k = pos[i]
-                    S.submit_update(i, data[i][k], data[i][k + 1])
+                    S.submit_update(i, ptrs[i][k], ptrs[i][k + 1])
                     pos[i] += 1
+                    if k == 0:
+                        predictable.append(i)
                     if pos[i] == specs[i][3]:
                         left.discard(i)
-                        active.remove(i)
+                        active[j] = active[-1]
+                        active.pop()
+                        predictable.remove(i)
                         S.close(i)
                 n_req += 1
                 next_t += rng.exponential(1.0 / rate)
@@ -732,20 +765,32 @@ def serving_section(torch):
         S.drain()
         dt = time.perf_counter() - t0
         ups = sum(1 for r in S.completed if r.kind == "update")
-        out["rates"].append({
+        errors = sum(1 for r in S.completed if r.error is not None)
+        res = {
+            "budget_bytes": budget,
             "offered_requests_per_s": rate,
             "achieved_requests_per_s": round(n_req / dt, 1),
             "stream_updates_per_s": round(ups / dt, 1),
+            "requests": n_req,
             "update_latency_us": {k: round(v, 1) for k, v in S.latency_us("update").items()},
             "predict_latency_us": {k: round(v, 1) for k, v in S.latency_us("predict").items()},
             "admission_wait_ms": {"p50": round(float(np.percentile(list(t_admit.values()), 50)) * 1e3, 1),
                                   "max": round(max(t_admit.values()) * 1e3, 1)},
             "rounds": S.rounds,
-            "mean_batch": round(float(np.mean(S.batch_sizes)), 1),
-            "peak_state_bytes": S.peak_used})
-        print(f"serving rate {rate:g}: {out['rates'][-1]}", file=sys.stderr, flush=True)
+            "mean_update_batch": round(float(np.mean(S.batch_sizes)), 1),
+            "requests_per_round": round(n_req / max(1, S.rounds), 1),
+            "errors": errors,
+            "peak_state_bytes": S.peak_used}
+        print(f"serving budget {budget >> 30} GB, rate {rate:g}: {res}", file=sys.stderr, flush=True)
         del S
         torch.cuda.empty_cache()
+        return res
+
+    for rate in SERVE_RATES:
+        out["runs"].append(run(SERVE_BUDGET, rate))
+    out["runs"].append(run(*SERVE_TIGHT))
+    del data, ptrs
+    torch.cuda.empty_cache()
     return out
 
 

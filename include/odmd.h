@@ -321,6 +321,19 @@ odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* ou
 /* Wait for the handle's stream; return and clear a latched error. */
 odmd_status odmd_sync(odmd_t h);
 
+/*
+ * The error latched by the handle's finished device work, without waiting
+ * and without any device call (a request loop that tracks completion with
+ * its own events reads it per handle once that work is known to be done).
+ * Every kernel that latches an error bit (an update skipped for a
+ * non-finite or unchained pair, an iteration cap, a prediction of an empty
+ * model) also writes the latched bits into a word of the handle's pinned
+ * host memory; *status receives them as odmd_sync would return them (ODMD_OK
+ * if none).  Work still in flight may not be reflected yet.  Does not clear
+ * the error: odmd_sync (or odmd_eigs) does.  ODMD_EINVAL for NULL arguments.
+ */
+odmd_status odmd_peek_status(odmd_t h, odmd_status* status);
+
 /* Free the handle and (unless caller-owned) its device memory; ODMD_EINVAL
  * while a plan holds it. */
 odmd_status odmd_destroy(odmd_t h);

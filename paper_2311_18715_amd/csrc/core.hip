@@ -853,7 +853,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
     __syncthreads();
     if (tid == 0) {
-      st->status |= skip;
+      latch_status(st, skip);
       if (refolded) {
         st->m = r;
         st->refold = 0;
@@ -936,7 +936,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       st->last_rho = rho;
       st->sweeps = sweeps;
       st->eig_valid = 0;
-      if (sweeps > MAX_SWEEPS) st->status |= ST_NOCONV;
+      if (sweeps > MAX_SWEEPS) latch_status(st, ST_NOCONV);
     }
     return;
   }
@@ -1125,7 +1125,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     st->last_rho = rho;
     st->sweeps = sweeps;
     st->eig_valid = 0;
-    if (sweeps > MAX_SWEEPS) st->status |= ST_NOCONV;
+    if (sweeps > MAX_SWEEPS) latch_status(st, ST_NOCONV);
   }
 }
 

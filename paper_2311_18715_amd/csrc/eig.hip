@@ -497,7 +497,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   }
   if (t == 0) {
     st->eig_status = sfail;
-    if (sfail) st->status |= ST_NOCONV;
+    if (sfail) latch_status(st, ST_NOCONV);
     st->eig_valid = 1;
   }
 }
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(256) void k_predict_coef(DevState* st, int k0, int 
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && (n == 0 || st->eig_status != 0))
-    st->status |= (n == 0 ? ST_EMPTY : ST_NOCONV);
+    latch_status(st, n == 0 ? ST_EMPTY : ST_NOCONV);
 }
 
 // Coefficients that materialise the basis: column k of U is S[:, :m] Q[:, k].

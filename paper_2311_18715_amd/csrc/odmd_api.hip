@@ -164,6 +164,7 @@ odmd_status sync_and_status(odmd_t h) {
   if (bits) {
     const int zero = 0;
     HIP_OK(hipMemcpy(&h->st->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    __atomic_store_n(h->fb_host + 1, 0u, __ATOMIC_RELEASE);   // the host-visible copy too
   }
   return map_status(bits);
 }
@@ -346,16 +347,60 @@ odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>&
   return ODMD_OK;
 }
 
+// Launch plan of a batched update.  Streams are grouped by launch shape,
+// wide-row variant and storage type (one pass kernel each), and inside such
+// a group by live-column bucket; a bucket group too small to fill the chip
+// (fewer than BATCH_FILL workgroups) is merged into the next larger bucket
+// of its group, whose pass reads more columns than it needs (the extra
+// k-steps meet zero coefficients: results do not change by a bit), so that
+// the batch makes fewer, fuller launches.  kb[i] is raised to the bucket
+// stream i runs with (its small-state kernel reads records of that length).
+// order receives the streams in launch order (per launch the most rows per
+// workgroup first: workgroups start in index order, so the short ones fill
+// in behind the long ones), out the launches; returns their count.  No
+// allocation: order and out are caller arrays of count entries.
+constexpr int BATCH_FILL = 512;
+struct BatchLaunch { int first, nd, nblocks, threads, rows2, basis, rb; };
+int plan_batch(odmd_t* hs, int* kb, int32_t count, int* order, BatchLaunch* out) {
+  auto key = [&](int i) { return std::make_tuple(hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis); };
+  for (int32_t i = 0; i < count; ++i) order[i] = i;
+  std::sort(order, order + count, [&](int a, int b) {
+    if (key(a) != key(b)) return key(a) < key(b);
+    if (kb[a] != kb[b]) return kb[a] < kb[b];
+    return a < b;
+  });
+  int nl = 0;
+  for (int a = 0; a < count;) {
+    // [a, b): streams of one kernel group merged up to one bucket
+    int b = a, nblk = 0;
+    while (b < count && key(order[b]) == key(order[a])) {
+      const int bucket = kb[order[b]];
+      while (b < count && key(order[b]) == key(order[a]) && kb[order[b]] == bucket)
+        nblk += hs[order[b++]]->nblk;
+      if (nblk >= BATCH_FILL) break;
+    }
+    const int rb = kb[order[b - 1]];
+    std::sort(order + a, order + b, [&](int x, int y) {
+      const int64_t lx = hs[x]->n * hs[y]->nblk, ly = hs[y]->n * hs[x]->nblk;
+      if (lx != ly) return lx > ly;
+      return x < y;
+    });
+    out[nl++] = BatchLaunch{a, b - a, nblk, hs[order[a]]->threads, hs[order[a]]->rows2,
+                            (int)hs[order[a]]->basis, rb};
+    for (int k = a; k < b; ++k) kb[order[k]] = rb;
+    a = b;
+  }
+  return nl;
+}
+
 odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* ys, int32_t count) {
   hipStream_t stream = hs[0]->stream;
-  // group streams by (launch shape, storage type, live-column bucket): one
-  // pass launch per group
+  // one pass launch per group of plan_batch
   std::vector<int> kb(count);
-  std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> groups;
-  for (int32_t i = 0; i < count; ++i) {
-    kb[i] = live_bucket(hs[i]);
-    groups[{hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, kb[i]}].push_back(i);
-  }
+  std::vector<int> order(count);
+  std::vector<BatchLaunch> launches(count);
+  for (int32_t i = 0; i < count; ++i) kb[i] = live_bucket(hs[i]);
+  launches.resize(plan_batch(hs, kb.data(), count, order.data(), launches.data()));
   const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
   const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
   std::unique_lock<std::mutex> lk;
@@ -368,21 +413,12 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   BatchSlot& sl = *slp;
   PassDesc* pd = static_cast<PassDesc*>(sl.host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
-  struct Launch { int first, nd, nblocks, threads, rows2, basis, rb; };
-  std::vector<Launch> launches;
-  int k = 0;
-  for (auto& g : groups) {
-    // the longest workgroups (largest streams) first: workgroups are started
-    // in index order, so the short ones fill in behind them instead of
-    // leaving a tail of long ones at the end of the launch
-    std::stable_sort(g.second.begin(), g.second.end(), [&](int32_t a, int32_t b) {
-      return hs[a]->n * hs[b]->nblk > hs[b]->n * hs[a]->nblk;
-    });
-    Launch L{k, 0, 0, std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first),
-             std::get<3>(g.first)};
-    for (int32_t i : g.second) {
+  for (const BatchLaunch& L : launches) {
+    int blk0 = 0;
+    for (int k = L.first; k < L.first + L.nd; ++k) {
+      const int i = order[k];
       odmd_t h = hs[i];
-      PassDesc& d = pd[k++];
+      PassDesc& d = pd[k];
       d = PassDesc{};
       d.Us = h->Us;
       d.x = xs[i];
@@ -392,11 +428,9 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
       d.n = h->n;
       d.nblk = h->nblk;
       d.ct = h->ct;
-      d.blk0 = L.nblocks;
-      L.nblocks += h->nblk;
-      ++L.nd;
+      d.blk0 = blk0;
+      blk0 += h->nblk;
     }
-    launches.push_back(L);
   }
   for (int32_t i = 0; i < count; ++i) {
     odmd_t h = hs[i];
@@ -417,14 +451,14 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   HIP_OK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream));
   const PassDesc* dpd = static_cast<const PassDesc*>(sl.dev);
   if (launches.size() == 1) {
-    const Launch& L = launches[0];
+    const BatchLaunch& L = launches[0];
     HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, stream));
   } else {
     const int nside = std::min<int>(NSIDE, (int)launches.size());
     HIP_OK(hipEventRecord(ring->fork, stream));
     for (int i = 0; i < nside; ++i) HIP_OK(hipStreamWaitEvent(ring->side[i], ring->fork, 0));
     for (size_t i = 0; i < launches.size(); ++i) {
-      const Launch& L = launches[i];
+      const BatchLaunch& L = launches[i];
       HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb,
                                ring->side[i % nside]));
     }
@@ -483,49 +517,32 @@ odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* 
     const odmd_status s = scratch_for(hs[0]->device, &dev);
     if (s != ODMD_OK) return s;
   }
-  // order: by (launch shape, storage type, live-column bucket), the groups
-  // of one pass launch each, then as odmd_update_batch orders a group (the
-  // most rows per workgroup first), then by position; sorted in place on the
-  // stack (the results do not depend on the order: each stream's work is its
-  // own launch's)
+  // the launch plan of odmd_update_batch (plan_batch), in stack arrays
   int kb[NOALLOC_MAX], order[NOALLOC_MAX];
-  for (int32_t i = 0; i < count; ++i) {
-    kb[i] = live_bucket(hs[i]);
-    order[i] = i;
-  }
-  auto key = [&](int i) {
-    return std::make_tuple(hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, kb[i]);
-  };
-  std::sort(order, order + count, [&](int a, int b) {
-    if (key(a) != key(b)) return key(a) < key(b);
-    const int64_t la = hs[a]->n * hs[b]->nblk, lb = hs[b]->n * hs[a]->nblk;
-    if (la != lb) return la > lb;
-    return a < b;
-  });
+  BatchLaunch launches[NOALLOC_MAX];
+  for (int32_t i = 0; i < count; ++i) kb[i] = live_bucket(hs[i]);
+  const int nl = plan_batch(hs, kb, count, order, launches);
   PassDesc* pd = reinterpret_cast<PassDesc*>(g_noalloc_host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(g_noalloc_host + NOALLOC_PASS_BYTES);
-  struct Launch { int first, nd, nblocks, threads, rows2, basis, rb; };
-  Launch launches[NOALLOC_MAX];
-  int nl = 0;
-  for (int k = 0; k < count; ++k) {
-    const int i = order[k];
-    odmd_t h = hs[i];
-    if (k == 0 || key(i) != key(order[k - 1]))
-      launches[nl++] = Launch{k, 0, 0, h->threads, h->rows2, (int)h->basis, kb[i]};
-    Launch& L = launches[nl - 1];
-    PassDesc& d = pd[k];
-    d = PassDesc{};
-    d.Us = h->Us;
-    d.x = xs[i];
-    d.y = ys[i];
-    d.partials = h->partials;
-    d.st = h->st;
-    d.n = h->n;
-    d.nblk = h->nblk;
-    d.ct = h->ct;
-    d.blk0 = L.nblocks;
-    L.nblocks += h->nblk;
-    ++L.nd;
+  for (int l = 0; l < nl; ++l) {
+    const BatchLaunch& L = launches[l];
+    int blk0 = 0;
+    for (int k = L.first; k < L.first + L.nd; ++k) {
+      const int i = order[k];
+      odmd_t h = hs[i];
+      PassDesc& d = pd[k];
+      d = PassDesc{};
+      d.Us = h->Us;
+      d.x = xs[i];
+      d.y = ys[i];
+      d.partials = h->partials;
+      d.st = h->st;
+      d.n = h->n;
+      d.nblk = h->nblk;
+      d.ct = h->ct;
+      d.blk0 = blk0;
+      blk0 += h->nblk;
+    }
   }
   for (int32_t i = 0; i < count; ++i) {
     odmd_t h = hs[i];
@@ -555,7 +572,7 @@ odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* 
   HIP_OK(hipStreamSynchronize(stream));
   const PassDesc* dpd = reinterpret_cast<const PassDesc*>(dev);
   for (int l = 0; l < nl; ++l) {
-    const Launch& L = launches[l];
+    const BatchLaunch& L = launches[l];
     HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, stream));
   }
   HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(dev + NOALLOC_PASS_BYTES), count, stream));
@@ -571,7 +588,9 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   c.ct = h->ct;
   c.ldo = ldo;
   c.K = K;
-  HIP_OK(launch_combine(c, (int)h->basis, out_f32, h->ct, h->stream));
+  // the live-column bucket (an upper bound on the stored columns in use):
+  // fewer k-steps, and less LDS per workgroup for the staged coefficients
+  HIP_OK(launch_combine(c, (int)h->basis, out_f32, live_bucket(h), h->stream));
   return ODMD_OK;
 }
 
@@ -712,7 +731,8 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
     delete s;
     return ODMD_ENOMEM;
   }
-  *s->fb_host = 0;
+  s->fb_host[0] = 0;
+  s->fb_host[1] = 0;            // host-visible copy of the latched status
   if (workspace) {
     s->mem = static_cast<char*>(workspace);
   } else {
@@ -738,8 +758,11 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
   }
   const double tol_eff = s->tol_eff;
   const int gflag = general ? 1 : 0;
+  unsigned* const mirror = s->fb_dev + 1;
   if (hipMemsetAsync(s->mem, 0, L.total, s->stream) != hipSuccess ||
       hipMemcpyAsync(&s->st->tol, &tol_eff, sizeof(double), hipMemcpyHostToDevice, s->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(&s->st->smirror, &mirror, sizeof(mirror), hipMemcpyHostToDevice, s->stream) !=
           hipSuccess ||
       hipMemcpyAsync(&s->st->general, &gflag, sizeof(int), hipMemcpyHostToDevice, s->stream) !=
           hipSuccess ||
@@ -821,6 +844,12 @@ odmd_status odmd_update_batch_noalloc(odmd_t* hs, const void* const* xs, const v
   HIP_OK(hipSetDevice(hs[0]->device));
   if (capturing(hs[0]->stream)) return ODMD_EINVAL;   // the tables are copied from host memory
   return launch_batch_noalloc(hs, xs, ys, count);
+}
+
+odmd_status odmd_peek_status(odmd_t h, odmd_status* status) {
+  if (!h || !status) return ODMD_EINVAL;
+  *status = map_status((int)__atomic_load_n(h->fb_host + 1, __ATOMIC_ACQUIRE));
+  return ODMD_OK;
 }
 
 odmd_status odmd_sync(odmd_t h) {

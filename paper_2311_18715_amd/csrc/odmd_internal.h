@@ -78,6 +78,10 @@ struct DevState {
   double yy_prev; // y.y of the last accepted pair (chaining fingerprint)
   double last_rho;
   double pad_[4];
+  // host-visible copy of `status` (a word of the handle's mapped pinned
+  // memory), rewritten by every kernel that latches a bit, so that the host
+  // can read the latched status of finished work without a device call
+  unsigned* smirror;
   // vectors and matrices; r x r matrices column-major with leading dim RMAX
   double sigma[RMAX];
   double w[RMAX];
@@ -97,6 +101,14 @@ struct DevState {
 };
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+#ifdef __HIPCC__
+// Latch status bits (one thread) and mirror the result to the host word.
+__device__ inline void latch_status(DevState* st, int bits) {
+  st->status |= bits;
+  if (st->smirror) *reinterpret_cast<volatile unsigned*>(st->smirror) = (unsigned)st->status;
+}
+#endif
 
 // stored-column capacity of a stream with rank cap r_max (multiple of 8)
 inline int fold_capacity(int r_max) {

@@ -27,7 +27,13 @@ EXPORTS = [
     "odmd_profile_samples", "odmd_create_general", "odmd_state_bytes_general",
     "odmd_default_shape", "odmd_create_shaped", "odmd_state_bytes_shaped", "odmd_autotune",
     "odmd_plan_create", "odmd_plan_launch", "odmd_plan_destroy", "odmd_update_batch_noalloc",
+    "odmd_peek_status",
 ]
+
+
+def status_name(code: int) -> str:
+    """Name of an odmd_status code ("ESEQ", ...)."""
+    return STATUS.get(int(code), str(code))
 
 
 class OdmdError(RuntimeError):
@@ -88,6 +94,7 @@ def lib() -> ctypes.CDLL:
             "odmd_predict_batch": ([ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp), i32],
                                    ctypes.c_int),
             "odmd_sync": ([vp], ctypes.c_int),
+            "odmd_peek_status": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "odmd_destroy": ([vp], ctypes.c_int),
             "odmd_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "odmd_get_info": ([vp, ctypes.POINTER(Info)], ctypes.c_int),
@@ -196,6 +203,13 @@ class ODMD:
 
     def sync(self) -> None:
         _check(lib().odmd_sync(self._h), "odmd_sync")
+
+    def peek_status(self) -> int:
+        """The status code latched by finished device work (0: none), read
+        without a device call and without clearing it (odmd_peek_status)."""
+        v = ctypes.c_int()
+        _check(lib().odmd_peek_status(self._h, ctypes.byref(v)), "odmd_peek_status")
+        return v.value
 
     def eigs(self, vectors: bool = True):
         """(lam, V): complex eigenvalues (r,) and eigenvectors (r, r) of A~."""

@@ -7,17 +7,23 @@ device.  A stream is admitted when its device bytes (odmd_state_bytes) fit
 in the memory budget; otherwise it waits, in arrival order, until closed
 streams free enough.
 
-Each scheduling round takes the head request of every admitted stream that
-has one: all head updates go to the device as one batched update
-(odmd_update_batch: one pass launch per group of like streams, one
-small-state launch for all), head
-predictions are queued behind it.  Requests that arrive while a round runs on
-the device join the next round; a stream's requests are served strictly in
-order, so every result equals the one the stream would get alone (the
-batched launch is bitwise equal to per-stream launches).
+Each scheduling round takes, from every admitted stream with queued
+requests, its leading updates (up to ``max_layers``) and a prediction that
+follows them: the k-th updates of the streams form layer k, one batched
+update each (odmd_update_batch: one pass launch per group of like streams,
+one small-state launch for all), and all the round's predictions follow as
+one batched prediction.  Everything goes to one device stream in that
+order, so a stream's requests run strictly in order and every result equals
+the one the stream would get alone (the batched launches are bitwise equal
+to per-stream launches).
+Requests that arrive while a round runs on the device join a later round.
 
 The device work of a round is recorded with one event; a request's latency
 runs from its submission to the host's observation that its round finished.
+Errors the device latches for a stream in a round (an update skipped for a
+non-finite or unchained pair, a prediction of an empty model, an iteration
+cap) are read then, without a device call, and reported on that round's
+requests of the stream (the error is then cleared).
 """
 from __future__ import annotations
 
@@ -74,18 +80,29 @@ class Server:
     be passed for host-only tests of the scheduling logic)."""
 
     def __init__(self, budget_bytes: int, backend=None, torch_module=None,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, max_layers: int = 8,
+                 max_inflight: int = 4, keep_outputs: bool = True, pred_bytes: int = 8 << 30):
         if backend is None:
             from paper_2311_18715_amd import odmd as backend
         if torch_module is None:
             import torch as torch_module
+        if max_layers < 1:
+            raise ValueError("max_layers must be at least 1")
         self.B, self.torch, self.clock = backend, torch_module, clock
+        self.max_layers = int(max_layers)
+        # rounds in flight before pump() waits for the oldest (bounds the
+        # prediction outputs held on the device); keep_outputs=False drops a
+        # prediction's states once its round is done (load generators)
+        self.max_inflight = max(1, int(max_inflight))
+        self.keep_outputs = bool(keep_outputs)
+        self.pred_bytes = int(pred_bytes)    # prediction output per round (FP64 bound)
+        self.active: Dict[int, _Stream] = {}    # admitted streams with queued work or closing
         self.budget = int(budget_bytes)
         self.used = 0
         self.peak_used = 0
         self.streams: Dict[int, _Stream] = {}
         self.waiting: Deque[_Stream] = collections.deque()
-        self.inflight: List = []          # (event, [requests]) per round
+        self.inflight: List = []          # (event, [requests], {sid: stream}) per round
         self.completed: List[Request] = []
         self.rounds = 0
         self.batch_sizes: List[int] = []
@@ -112,7 +129,10 @@ class Server:
 
     def close(self, sid: int) -> None:
         """Close a stream once its queued requests are served."""
-        self.streams[sid].closing = True
+        st = self.streams[sid]
+        st.closing = True
+        if st.model is not None:
+            self.active[sid] = st
 
     def admitted(self, sid: int) -> bool:
         return self.streams[sid].model is not None
@@ -126,6 +146,8 @@ class Server:
             st.model = self.B.ODMD(st.n, st.r_max, st.tol, basis=st.basis, workspace=ws, **kw)
             self.used += st.bytes
             self.peak_used = max(self.peak_used, self.used)
+            if st.queue or st.closing:
+                self.active[st.sid] = st
 
     def _release(self, st: _Stream) -> None:
         st.model.close()
@@ -133,84 +155,129 @@ class Server:
         st.workspace = None
         self.used -= st.bytes
         del self.streams[st.sid]
+        self.active.pop(st.sid, None)
 
     # ---- requests ------------------------------------------------------
-    def submit_update(self, sid: int, x, y) -> Request:
-        r = Request("update", sid, x=x, y=y, t_submit=self.clock())
-        self.streams[sid].queue.append(r)
+    def _enqueue(self, r: Request) -> Request:
+        st = self.streams[r.sid]
+        st.queue.append(r)
+        if st.model is not None:
+            self.active[r.sid] = st
         return r
 
+    def submit_update(self, sid: int, x, y) -> Request:
+        return self._enqueue(Request("update", sid, x=x, y=y, t_submit=self.clock()))
+
     def submit_predict(self, sid: int, steps: int) -> Request:
-        r = Request("predict", sid, steps=int(steps), t_submit=self.clock())
-        self.streams[sid].queue.append(r)
-        return r
+        return self._enqueue(Request("predict", sid, steps=int(steps), t_submit=self.clock()))
 
     # ---- scheduling ----------------------------------------------------
     def pump(self) -> int:
-        """One round: the head request of every admitted stream goes to the
-        device (updates batched into one launch).  Returns the number of
-        requests launched."""
+        """One round: for every admitted stream with queued requests, its
+        leading updates (at most max_layers of them) and, if one follows, a
+        prediction.  The k-th updates of the streams form layer k (one
+        batched launch per layer); the predictions go last, in one batched
+        launch (one eigendecomposition launch for all), each after its own
+        stream's updates.  Predictions past pred_bytes of output in the
+        round wait for the next one.  Returns the number of requests
+        launched."""
         self.poll()
+        while len(self.inflight) >= self.max_inflight:
+            self.inflight[0][0].synchronize()
+            self.poll()
         self._admit()
-        ups, preds = [], []
-        for st in list(self.streams.values()):
-            if st.model is None:
-                continue
+        layers: List[list] = []              # per layer: [(st, r)] updates
+        preds: List[tuple] = []
+        pred_bytes = 0
+        members: Dict[int, _Stream] = {}
+        taken: Dict[int, int] = {}
+        for st in list(self.active.values()):
             if not st.queue:
                 if st.closing:
                     self._release(st)
+                else:
+                    del self.active[st.sid]
                 continue
-            head = st.queue[0]
-            if head.kind == "update":
-                ups.append((st, head))
-            else:
-                preds.append((st, head))
+            j = 0
+            q = st.queue
+            while j < len(q) and j < self.max_layers and q[j].kind == "update":
+                if j == len(layers):
+                    layers.append([])
+                layers[j].append((st, q[j]))
+                j += 1
+            if j < len(q) and q[j].kind == "predict":
+                nb = q[j].steps * st.n * 8
+                if not preds or pred_bytes + nb <= self.pred_bytes:
+                    preds.append((st, q[j]))
+                    pred_bytes += nb
+                    j += 1
+            if j:
+                members[st.sid] = st
+                taken[st.sid] = j
         launched = []
-        if ups:
+        for ups in layers:
             H = self.B.handle_array([st.model for st, _ in ups])
-            xp = np.array([r.x.data_ptr() for _, r in ups], dtype=np.uint64)
-            yp = np.array([r.y.data_ptr() for _, r in ups], dtype=np.uint64)
+            xp = np.fromiter((r.x.data_ptr() for _, r in ups), dtype=np.uint64, count=len(ups))
+            yp = np.fromiter((r.y.data_ptr() for _, r in ups), dtype=np.uint64, count=len(ups))
             self.B.update_batch_ptrs(H, xp, yp)
-            for st, r in ups:
-                st.queue.popleft()
-                launched.append(r)
+            launched.extend(r for _, r in ups)
             self.batch_sizes.append(len(ups))
         if preds:
-            # the eigendecompositions of all of them in one launch
             try:
-                outs = self.B.predict_batch([st.model for st, _ in preds], [r.steps for _, r in preds])
+                outs = self.B.predict_batch([st.model for st, _ in preds],
+                                            [r.steps for _, r in preds])
             except Exception as e:
                 outs = [None] * len(preds)
                 for _, r in preds:
                     r.error = str(e)
-            for (st, r), o in zip(preds, outs):
+            for (_, r), o in zip(preds, outs):
                 r.out = o
-                st.queue.popleft()
-                launched.append(r)
+            launched.extend(r for _, r in preds)
+        for sid, j in taken.items():
+            q = members[sid].queue
+            for _ in range(j):
+                q.popleft()
         if launched:
             ev = self.torch.cuda.Event()
             ev.record()
-            self.inflight.append((ev, launched))
+            self.inflight.append((ev, launched, members))
             self.rounds += 1
         return len(launched)
 
     def poll(self) -> None:
-        """Mark the requests of finished rounds done."""
+        """Mark the requests of finished rounds done, with the errors their
+        streams latched on the device in that round."""
         keep = []
         now = None
-        for ev, reqs in self.inflight:
+        for ev, reqs, members in self.inflight:
             if ev.query():
                 now = now if now is not None else self.clock()
+                bad = {}
+                for sid, st in members.items():
+                    if st.model is None:
+                        continue
+                    code = st.model.peek_status()
+                    if code:
+                        bad[sid] = self.B.status_name(code)
+                        try:
+                            st.model.sync()          # clears the latched error
+                        except Exception:
+                            pass
                 for r in reqs:
                     r.t_done, r.done = now, True
+                    if r.sid in bad and r.error is None:
+                        r.error = bad[r.sid]
+                    if not self.keep_outputs:
+                        r.out = None
+                    r.x = r.y = None
                     self.completed.append(r)
             else:
-                keep.append((ev, reqs))
+                keep.append((ev, reqs, members))
         self.inflight = keep
 
     def idle(self) -> bool:
         return not self.inflight and not self.waiting and \
-            all(not st.queue for st in self.streams.values())
+            all(not st.queue for st in self.active.values())
 
     def drain(self) -> None:
         """Run rounds until every queued request is done.  Raises if queued
@@ -220,14 +287,13 @@ class Server:
             launched = self.pump()
             if self.idle():
                 break
-            if not any(st.queue for st in self.streams.values() if st.model is not None):
+            if not any(st.queue for st in self.active.values()):
                 # only waits for the device, or for admission, are left
                 self.torch.cuda.synchronize()
                 self.poll()
                 if launched == 0 and not self.inflight:
                     self.pump()        # releases closing streams, admits waiting ones
-                    if not any(st.queue for st in self.streams.values()
-                               if st.model is not None) and self.waiting:
+                    if not any(st.queue for st in self.active.values()) and self.waiting:
                         raise RuntimeError("admission blocked: the budget is held by open "
                                            "streams with no queued work; close some")
         self.torch.cuda.synchronize()

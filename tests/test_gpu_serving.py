@@ -95,3 +95,38 @@ def test_mix_equals_alone_under_admission():
             assert np.array_equal(a, b), f"stream {i} differs alone vs in the mix"
     lat = S.latency_us("update")
     assert lat["count"] == sum(s[4] for s in SPECS)
+
+
+def test_device_errors_reach_the_requests_of_their_stream():
+    """A non-chaining pair of one stream in a mixed round: the device skips
+    it and latches ESEQ; that stream's request of the round carries the
+    error, the other streams' requests do not, and later rounds are clean.
+    odmd_peek_status sees the latched bits without a device call."""
+    data = streams()[:3]
+    S = Server(10 ** 10, max_layers=1)
+    for i in range(3):
+        n, _, rmax, basis, _ = SPECS[i]
+        S.open(i, n, rmax, 1e-8, basis)
+    first = [S.submit_update(i, data[i][0], data[i][1]) for i in range(3)]
+    S.drain()
+    assert all(r.done and r.error is None for r in first)
+    ok0 = S.submit_update(0, data[0][1], data[0][2])
+    bad = S.submit_update(1, data[1][5], data[1][6])      # does not chain to x_1
+    ok2 = S.submit_update(2, data[2][1], data[2][2])
+    S.drain()
+    assert ok0.error is None and ok2.error is None
+    assert bad.error == "ESEQ"
+    later = S.submit_update(1, data[1][1], data[1][2])    # the chain resumes
+    S.drain()
+    assert later.done and later.error is None
+    # peek: latched by a finished update, cleared by sync
+    n, _, rmax, basis, _ = SPECS[1]
+    g = ODMD(n, rmax, 1e-8, basis=basis)
+    g.update(data[1][0], data[1][1])
+    g.update(data[1][3], data[1][4])                      # unchained
+    torch.cuda.synchronize()
+    assert g.peek_status() == 6                            # ESEQ
+    with pytest.raises(Exception):
+        g.sync()
+    assert g.peek_status() == 0
+    g.close()

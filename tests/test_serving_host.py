@@ -29,6 +29,9 @@ class FakeTorch:
             def query(self):
                 return True
 
+            def synchronize(self):
+                pass
+
         @staticmethod
         def synchronize():
             pass
@@ -65,11 +68,23 @@ class FakeBackend:
                 B.log.append(("predict", self.id, steps))
                 return np.zeros((steps, self.n))
 
+            def peek_status(self):
+                return B.errors.get(self.id, 0)
+
+            def sync(self):
+                B.log.append(("sync", self.id))
+                B.errors.pop(self.id, None)
+
             def close(self):
                 B.live.discard(self.id)
 
         self.models = {}
+        self.errors = {}             # model id -> latched status code
         self.ODMD = ODMD
+
+    @staticmethod
+    def status_name(code):
+        return {4: "ENONFINITE", 6: "ESEQ"}.get(code, str(code))
 
     def predict_batch(self, models, steps):
         return [m.predict(s) for m, s in zip(models, steps)]
@@ -81,9 +96,9 @@ class FakeBackend:
         self.log.append(("batch", tuple(int(h) for h in H), tuple(int(x) for x in xp)))
 
 
-def make(budget):
+def make(budget, **kw):
     B = FakeBackend()
-    return Server(budget, backend=B, torch_module=FakeTorch), B
+    return Server(budget, backend=B, torch_module=FakeTorch, **kw), B
 
 
 def test_admission_fifo_and_budget():
@@ -118,8 +133,9 @@ def test_rounds_keep_stream_order_and_batch_heads():
     pr = S.submit_predict(1, 7)
     S.drain()
     batches = [e for e in B.log if e[0] == "batch"]
-    # one update per stream per round, all three streams in each of 3 rounds
+    # one batched launch per layer: the k-th update of every stream together
     assert len(batches) == 3 and all(len(b[1]) == 3 for b in batches)
+    assert S.rounds == 1
     for k, b in enumerate(batches):
         assert b[2] == tuple(xs[sid][k].data_ptr() for sid in range(3))
     # the prediction of stream 1 runs after its three updates
@@ -159,3 +175,59 @@ def test_stream_shapes_reach_the_handles():
     assert B.models[S.streams[1].model.id].shape == (256, 1024, 512)
     # the budget counts the shaped stream's own bytes
     assert S.used == 2 * 8 * 100 * 8 + 1024 * 512
+
+
+def test_layers_bound_a_round_and_keep_order():
+    """At most max_layers leading updates of a stream per round, then at
+    most one prediction; predictions go after the round's update layers."""
+    S, B = make(budget=10 ** 9, max_layers=2)
+    S.open(0, 10, 4, 1e-8)
+    S.open(1, 10, 4, 1e-8)
+    p = [_Ptr() for _ in range(7)]
+    for k in range(5):
+        S.submit_update(0, p[k], p[k + 1])
+    S.submit_update(1, p[0], p[1])
+    S.submit_predict(1, 3)
+    S.submit_update(1, p[1], p[2])               # after the prediction: next round
+    S.pump()                                      # round 1: layers 0 and 1, then the prediction
+    assert [(e[0], len(e[1]) if e[0] == "batch" else e[1]) for e in B.log] == \
+        [("batch", 2), ("batch", 1), ("predict", S.streams[1].model.id)]
+    assert len(S.streams[0].queue) == 3 and len(S.streams[1].queue) == 1
+    S.drain()
+    xs = [b[2] for b in B.log if b[0] == "batch"]
+    stream0 = [x[0] for x in xs]                  # stream 0 is first in every batch it is in
+    assert stream0 == [p[k].data_ptr() for k in range(5)]
+    assert S.rounds == 3
+
+
+def test_prediction_output_per_round_is_bounded():
+    """Predictions past the round's output budget wait for the next round."""
+    S, B = make(budget=10 ** 9, pred_bytes=100 * 8 * 10)
+    for sid in range(3):
+        S.open(sid, 10, 4, 1e-8)
+        S.submit_update(sid, _Ptr(), _Ptr())
+        S.submit_predict(sid, 100)                # 8000 bytes each: one per round
+    S.pump()
+    assert sum(1 for e in B.log if e[0] == "predict") == 1
+    S.drain()
+    assert sum(1 for e in B.log if e[0] == "predict") == 3 and S.rounds == 3
+
+
+def test_latched_errors_reach_that_rounds_requests():
+    """An error the device latched for one stream in a round is reported on
+    that stream's requests of the round only, and cleared (odmd_sync)."""
+    S, B = make(budget=10 ** 9)
+    S.open(0, 10, 4, 1e-8)
+    S.open(1, 10, 4, 1e-8)
+    p = [_Ptr() for _ in range(4)]
+    a = S.submit_update(0, p[0], p[1])
+    b = S.submit_update(1, p[2], p[3])
+    c = S.submit_predict(1, 2)
+    B.errors[S.streams[1].model.id] = 6           # stream 1's update did not chain
+    S.drain()
+    assert a.done and a.error is None
+    assert b.done and b.error == "ESEQ" and c.error == "ESEQ"
+    assert ("sync", S.streams[1].model.id) in B.log and not B.errors
+    d = S.submit_update(1, p[3], p[0])
+    S.drain()
+    assert d.done and d.error is None
