@@ -268,9 +268,9 @@ def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 
     snapshots = gen.chunk
 
     models = {b: ODMD(n, 64, 1e-8, basis=b) for b in ("f64", "f32", "bf16")}
-    # the same FP64 algorithm at the BF16 storage's effective tolerance 2^-8:
-    # the model BF16 storage can hold, against which its rollout is read
-    models["f64_tol_bf16"] = ODMD(n, 64, 2.0 ** -8, basis="f64")
+    # the same FP64 algorithm at the BF16 storage's effective tolerance
+    # (2^-12): the truncation BF16 storage applies, set apart from its rounding
+    models["f64_tol_bf16"] = ODMD(n, 64, models["bf16"].info().tol_eff, basis="f64")
     times = {b: 0.0 for b in models}
     for k0 in range(0, snaps - 1, chunk):
         cnt = min(chunk, snaps - 1 - k0)
@@ -311,7 +311,10 @@ def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 
     ref16 = lam["f64_tol_bf16"][big]
     out["bf16_eig_rel_diff_vs_f64_at_same_tol"] = float(
         f"{np.max(np.abs(match(ref16, lam['bf16']) - ref16) / np.abs(ref16)):.3e}")
-    # principal subspace (sigma >= 1e-3 sigma_1 of the FP64 run) and orthogonality
+    # principal subspace (sigma >= 1e-3 sigma_1 of the FP64 run): the largest
+    # angle between it and the span of each model's basis (its sine is the
+    # largest part of a principal direction outside that span), and
+    # orthogonality
     sig = models["f64"].state()["sigma"]
     kk = int(np.sum(sig >= 1e-3 * sig[0]))
     U64 = models["f64"].basis_matrix()[:, :kk]
@@ -322,11 +325,10 @@ def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 
         U = models[b].basis_matrix()
         G = U.T @ U
         out["orthogonality_fro"][b] = float(f"{float(torch.linalg.norm(G - torch.eye(G.shape[0], dtype=G.dtype, device=G.device))):.3e}")
-        Uk = U[:, :kk]
-        R = Uk - U64 @ (U64.T @ Uk)
+        R = U64 - U @ (U.T @ U64)
         smax = float(torch.linalg.eigvalsh(R.T @ R).max().clamp(min=0.0)) ** 0.5
         out["subspace_angle_rad_vs_f64"][b] = float(f"{math.asin(min(1.0, smax)):.3e}")
-        del U, G, Uk, R
+        del U, G, R
     del U64
     torch.cuda.empty_cache()
     # rollout over 500 steps against the FP64 rollout

@@ -75,9 +75,12 @@ odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
  * stream) and optionally caller-owned device memory.
  *   basis: ODMD_F64, ODMD_F32 or ODMD_BF16 (stored columns rounded to
  *          nearest even; residuals, projections, the rotation of the stored
- *          columns and the small problems stay FP64).  The effective
- *          tolerance is tol for FP64 and FP32 bases and max(tol, 2^-8) for
- *          BF16: a BF16 basis cannot hold a direction weaker than that.
+ *          columns and the small problems stay FP64; a BF16 basis is
+ *          re-orthonormalised from the Gram matrix of its columns after
+ *          each rewrite).  The effective tolerance is tol for FP64 and FP32
+ *          bases and max(tol, 2^-12) for BF16: the rounding of a rewritten
+ *          BF16 basis shows in the next snapshots as residuals of about
+ *          2^-9 of their norm, which that tolerance truncates again.
  *   io:    ODMD_F64 or ODMD_F32; equal to basis for F64/F32 bases, ODMD_F32
  *          for a BF16 basis.
  *   The small SVD of each update is solved through its secular equation,
@@ -230,7 +233,7 @@ odmd_status odmd_update_batch(odmd_t* hs, const void* const* xs, const void* con
  * results (bit for bit) and errors as odmd_update_batch, with count at most
  * ODMD_NOALLOC_MAX_STREAMS (ODMD_EINVAL above it).  The descriptor tables
  * of the launch live in a fixed device array of the library, one per GPU,
- * 152 KB, held until the process ends, instead of staging memory
+ * 208 KB, held until the process ends, instead of staging memory
  * the library allocates and grows; every pass launch goes to the handles'
  * stream (no side streams).  The tables are copied from a static host
  * buffer of the library, and the call waits for the handles' stream before
@@ -347,7 +350,7 @@ typedef struct {
   int32_t r_max;
   int64_t n;
   int64_t m;          /* accepted pairs                                 */
-  double tol_eff;     /* tolerance in use (after the BF16 clamp)        */
+  double tol_eff;     /* tolerance in use (after the BF16 floor)        */
   double last_rho;    /* residual norm of the last accepted update      */
   int32_t last_sweeps;/* Jacobi sweeps of the last small SVD            */
   int32_t nblocks;    /* workgroups of the streaming pass               */

@@ -619,6 +619,113 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
   }
 }
 
+// BF16 basis after a refold: the refolded columns S' = fl(S Q) are not
+// orthonormal (M = S'^T S' = I + E, ||E||_F about 1e-3).  The orthonormal
+// basis of their span is S' M^-1/2; with the old basis U ~ S' (they differ
+// by the rounding) the model X ~ U diag(sigma) W^T reads
+// X ~ (S' M^-1/2) (M^1/2 diag(sigma)) W^T, so this update's core takes
+// M^1/2 diag(sigma) as its top-left block (a general SVD; the right factor W
+// and with it C and w are unchanged), inner products with the basis carry
+// over as M^-1/2 S'^T v ~ M^-1/2 (U^T v), and Q = M^-1/2 (U = S'[:, :r] Q).
+//   in:  the Gram records (sums in record order), p1 (pvec), p2, pyr.
+//   out: sA = M^1/2 (ld LDK), sQ rows < r = M^-1/2, the three vectors
+//        transformed; sV is scratch.
+// M^1/2 and M^-1/2 come from the coupled Newton-Schulz iteration
+// Y <- Y T, Z <- T Z, T = (3 I - Z Y) / 2 from Y = M, Z = I, quadratically
+// convergent for ||I - M|| < 1 (Higham, Functions of Matrices, 2008, 6.3);
+// its products are 16x16 FP64 matrix-core tiles, one per wave.
+__device__ void gram_fix(const CoreArgs& c, int r, double* sA, double* sV, double* sQ, double* pvec,
+                         double* p2, double* pyr) {
+  const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+  const int nb = (r + 15) / 16;
+  // 1. M from the records (fixed order), both triangles, into sA
+  for (int e = tid; e < GRAM_REC; e += CORE_THREADS) {
+    const int pp = e >> 8, ln = (e >> 2) & 63, v = e & 3;
+    int I = 0, J = 0, k = pp;
+    while (k >= GRAM_BLOCKS - I) { k -= GRAM_BLOCKS - I; ++I; }
+    J = I + k;
+    const int row = 16 * I + 4 * (ln >> 4) + v, col = 16 * J + (ln & 15);
+    if (J < nb && row < r && col < r) {
+      double t = 0.0;
+      for (int w = 0; w < c.gnwg; ++w) t += c.grec[(int64_t)w * GRAM_REC + e];
+      sA[col * LDK + row] = t;
+      if (I != J) sA[row * LDK + col] = t;
+    }
+  }
+  for (int idx = tid; idx < r * r; idx += CORE_THREADS) {
+    const int i = idx % r, j = idx / r;
+    sV[j * LDK + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // 2. Newton-Schulz: Y (sA) -> M^1/2, Z (sV) -> M^-1/2; T in sQ (ld LDQ)
+  const int ti = wv & 3, tj = wv >> 2;           // one 16x16 tile per wave (16 waves)
+  const int row0 = 16 * ti, col0 = 16 * tj;
+  const bool tile_live = row0 < r && col0 < r;
+  const int ra = row0 + (l & 15), cb = col0 + (l & 15);
+  for (int it = 0; it < 12; ++it) {
+    int far = 0;
+    if (tile_live) {
+      const d4_t d = mfma_tile(sV + (ra < r ? ra : 0), LDK, ra < r, sA + (cb < r ? cb : 0) * LDK, 1,
+                               cb < r, r, l);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + 4 * v + (l >> 4), j = cb;
+        if (i < r && j < r) {
+          const double t = ((i == j ? 3.0 : 0.0) - d[v]) * 0.5;
+          sQ[j * LDQ + i] = t;
+          far |= fabs(t - (i == j ? 1.0 : 0.0)) > 0x1p-50;
+        }
+      }
+    }
+    const int more = __syncthreads_or(far);
+    d4_t yt = {0.0, 0.0, 0.0, 0.0}, tz = yt;
+    if (tile_live) {
+      yt = mfma_tile(sA + (ra < r ? ra : 0), LDK, ra < r, sQ + (cb < r ? cb : 0) * LDQ, 1, cb < r, r, l);
+      tz = mfma_tile(sQ + (ra < r ? ra : 0), LDQ, ra < r, sV + (cb < r ? cb : 0) * LDK, 1, cb < r, r, l);
+    }
+    __syncthreads();
+    if (tile_live) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + 4 * v + (l >> 4), j = cb;
+        if (i < r && j < r) {
+          sA[j * LDK + i] = yt[v];
+          sV[j * LDK + i] = tz[v];
+        }
+      }
+    }
+    __syncthreads();
+    if (!more) break;                            // T was I to 2^-50: Y, Z converged
+  }
+  // 3. p1, p2, U^T y in the orthonormal basis: M^-1/2 v (Z symmetric: row j
+  //    of Z is column j), one quarter-wave per entry
+  const int qw = tid >> 4, ql = tid & 15;       // 64 quarter-waves: entry qw of each vector
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  if (qw < r) {
+    for (int i = ql; i < r; i += 16) {
+      const double w = sV[qw * LDK + i];
+      t0 += w * pvec[i];
+      t1 += w * p2[i];
+      t2 += w * pyr[i];
+    }
+  }
+  t0 = row_sum(t0);
+  t1 = row_sum(t1);
+  t2 = row_sum(t2);
+  __syncthreads();
+  if (qw < r && ql == 0) {
+    pvec[qw] = t0;
+    p2[qw] = t1;
+    pyr[qw] = t2;
+  }
+  // 4. Q = M^-1/2 (rows < r of the refolded basis)
+  for (int idx = tid; idx < r * r; idx += CORE_THREADS) {
+    const int cc = idx / r, k2 = idx % r;
+    sQ[cc * LDQ + k2] = sV[k2 * LDK + cc];
+  }
+  __syncthreads();
+}
+
 template <bool GENERAL>
 __device__ __forceinline__ void core_update(const CoreArgs& c) {
   DevState* __restrict__ st = c.st;
@@ -802,6 +909,10 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
   const int meff = refolded ? r : m;   // stored columns U is built from; e sits in column meff
+  // a BF16 basis just refolded: carry the model over to the orthonormal
+  // basis of the refolded columns (the core of this update is then general)
+  const bool gfix = refolded && c.grec != nullptr && r > 0;
+  if (gfix) gram_fix(c, r, sA, sV, sQ, pvec, p2, pyr);
 
   // 3. checks, residual norm, growth test (|p2|^2 and p2 . U^T y summed
   //    across the first wavefront, one entry per lane)
@@ -885,7 +996,17 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 
   // 5. SVD of the core: secular equation, one-sided Jacobi if that fails
   int sweeps = 0;
-  if (c.jacobi_only || !secular_svd(sA, sV, ssig, pvec, rho, r, sec)) {
+  if (gfix) {
+    // K = [[M^1/2 diag(sigma), p], [0, rho]]: M^1/2 is in sA already
+    for (int idx = tid; idx < M * M; idx += CORE_THREADS) {
+      const int i = idx % M, j = idx / M;
+      if (j < r) sA[j * LDK + i] = (i < r) ? sA[j * LDK + i] * ssig[j] : 0.0;
+      else sA[j * LDK + i] = (i < r) ? pvec[i] : rho;
+      sV[j * LDK + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    sweeps = jacobi_sweeps(sA, sV, sd, M, &flag);
+  } else if (c.jacobi_only || !secular_svd(sA, sV, ssig, pvec, rho, r, sec)) {
     for (int idx = tid; idx < M * M; idx += CORE_THREADS) {
       const int i = idx % M, j = idx / M;
       double v;

@@ -61,6 +61,10 @@ struct odmd_s {
   // on the handle.
   unsigned* fb_host = nullptr;
   unsigned* fb_dev = nullptr;
+  // BF16 basis: records of the Gram kernel that follows each pass (the Gram
+  // matrix of the columns a refold rewrote), gnwg of them
+  double* grec = nullptr;
+  int gnwg = 0;
   unsigned seq = 0;
   // Set once a plan holds the handle: plan launches (possibly replayed from
   // a graph) advance the state without the host's count, so every later
@@ -73,6 +77,8 @@ namespace {
 
 struct Layout {
   size_t st = 0, partials = 0, Us = 0, total = 0;
+  size_t gram = 0;   // BF16 basis: Gram records
+  int gnwg = 0;
   size_t tst = 0, pproj = 0, pt = 0, Ts = 0, eout = 0;   // general pairs only
   int64_t ntiles = 0, units = 0;
   int nblk = 0, ct = 0, threads = 0;
@@ -124,6 +130,11 @@ Layout make_layout(int64_t n, int32_t r_max, odmd_dtype basis, bool general, con
   off += round_up((int64_t)L.nblk * PW * sizeof(double), 256);
   L.Us = off;
   off += round_up(L.ntiles * L.ct * 64 * elem_bytes(basis), 256);
+  if (basis == ODMD_BF16) {
+    L.gnwg = gram_workgroups(n);
+    L.gram = off;
+    off += round_up((int64_t)L.gnwg * GRAM_REC * sizeof(double), 256);
+  }
   if (general) {
     L.tst = off;
     off += round_up(sizeof(DevState), 256);
@@ -203,6 +214,34 @@ bool capturing(hipStream_t s) {
   return cs != hipStreamCaptureStatusNone;
 }
 
+GramArgs gram_args(odmd_t h) {
+  GramArgs g{};
+  g.st = h->st;
+  g.Us = h->Us;
+  g.rec = h->grec;
+  g.n = h->n;
+  g.ct = h->ct;
+  g.nwg = h->gnwg;
+  g.blk0 = 0;
+  return g;
+}
+
+// The Gram kernels of the BF16 handles among hs[0..count), in index order,
+// into out (count entries at most); returns their number, *nblocks the
+// workgroups of one batched launch.
+int fill_gram(odmd_t* hs, int32_t count, GramArgs* out, int* nblocks) {
+  int k = 0, blk = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i]->grec) continue;
+    out[k] = gram_args(hs[i]);
+    out[k].blk0 = blk;
+    blk += hs[i]->gnwg;
+    ++k;
+  }
+  *nblocks = blk;
+  return k;
+}
+
 odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   // a captured update is replayed without the host's count of stored
   // columns: from here on the passes are sized for the full capacity (and
@@ -261,11 +300,14 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
     pt.eout = nullptr;
     HIP_OK(launch_pass(pt, (int)h->basis, h->ct, h->stream));
   }
+  if (h->grec) HIP_OK(launch_gram(gram_args(h), h->stream));
   h->seq = (h->seq + 1) & 0xFFFFFFu;
   CoreArgs c{};
   c.st = h->st;
   c.partials = h->partials;
   c.nblk = h->nblk;
+  c.grec = h->grec;
+  c.gnwg = h->gnwg;
   c.r_max = h->r_max;
   c.jacobi_only = h->jacobi_only;
   c.rb = kb;
@@ -402,7 +444,8 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   for (int32_t i = 0; i < count; ++i) kb[i] = live_bucket(hs[i]);
   launches.resize(plan_batch(hs, kb.data(), count, order.data(), launches.data()));
   const size_t pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
-  const size_t bytes = pass_bytes + (size_t)count * sizeof(CoreArgs);
+  const size_t core_bytes = round_up((int64_t)count * sizeof(CoreArgs), 256);
+  const size_t bytes = pass_bytes + core_bytes + (size_t)count * sizeof(GramArgs);
   std::unique_lock<std::mutex> lk;
   BatchSlot* slp = nullptr;
   BatchRing* ring = nullptr;
@@ -413,6 +456,9 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
   BatchSlot& sl = *slp;
   PassDesc* pd = static_cast<PassDesc*>(sl.host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(static_cast<char*>(sl.host) + pass_bytes);
+  GramArgs* gd = reinterpret_cast<GramArgs*>(static_cast<char*>(sl.host) + pass_bytes + core_bytes);
+  int gblocks = 0;
+  const int ngram = fill_gram(hs, count, gd, &gblocks);
   for (const BatchLaunch& L : launches) {
     int blk0 = 0;
     for (int k = L.first; k < L.first + L.nd; ++k) {
@@ -444,6 +490,8 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
     c.rb = kb[i];
     c.ct = h->ct;
     c.fold_slack = fold_slack(h);
+    c.grec = h->grec;
+    c.gnwg = h->gnwg;
     h->seq = (h->seq + 1) & 0xFFFFFFu;
     c.fb = h->fb_dev;
     c.seq = h->seq;
@@ -467,6 +515,10 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
       HIP_OK(hipStreamWaitEvent(stream, ring->join[i], 0));
     }
   }
+  if (ngram > 0)
+    HIP_OK(launch_gram_batch(reinterpret_cast<const GramArgs*>(static_cast<char*>(sl.dev) + pass_bytes +
+                                                               core_bytes),
+                             ngram, gblocks, stream));
   HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(static_cast<char*>(sl.dev) + pass_bytes),
                            count, stream));
   // the slot (host staging and device table) is free again once the
@@ -487,7 +539,8 @@ odmd_status launch_batch(odmd_t* hs, const void* const* xs, const void* const* y
 // names the array's memory.
 constexpr int NOALLOC_MAX = ODMD_NOALLOC_MAX_STREAMS;
 constexpr size_t NOALLOC_PASS_BYTES = (NOALLOC_MAX * sizeof(PassDesc) + 255) / 256 * 256;
-constexpr size_t NOALLOC_BYTES = NOALLOC_PASS_BYTES + NOALLOC_MAX * sizeof(CoreArgs);
+constexpr size_t NOALLOC_CORE_BYTES = (NOALLOC_MAX * sizeof(CoreArgs) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_PASS_BYTES + NOALLOC_CORE_BYTES + NOALLOC_MAX * sizeof(GramArgs);
 static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
 
 constexpr int NOALLOC_DEVICES = 64;
@@ -524,6 +577,9 @@ odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* 
   const int nl = plan_batch(hs, kb, count, order, launches);
   PassDesc* pd = reinterpret_cast<PassDesc*>(g_noalloc_host);
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(g_noalloc_host + NOALLOC_PASS_BYTES);
+  GramArgs* gd = reinterpret_cast<GramArgs*>(g_noalloc_host + NOALLOC_PASS_BYTES + NOALLOC_CORE_BYTES);
+  int gblocks = 0;
+  const int ngram = fill_gram(hs, count, gd, &gblocks);
   for (int l = 0; l < nl; ++l) {
     const BatchLaunch& L = launches[l];
     int blk0 = 0;
@@ -556,6 +612,8 @@ odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* 
     c.rb = kb[i];
     c.ct = h->ct;
     c.fold_slack = fold_slack(h);
+    c.grec = h->grec;
+    c.gnwg = h->gnwg;
     h->seq = (h->seq + 1) & 0xFFFFFFu;
     c.fb = h->fb_dev;
     c.seq = h->seq;
@@ -569,12 +627,19 @@ odmd_status launch_batch_noalloc(odmd_t* hs, const void* const* xs, const void* 
   HIP_OK(hipMemcpyAsync(dev, g_noalloc_host, pbytes, hipMemcpyHostToDevice, stream));
   HIP_OK(hipMemcpyAsync(dev + NOALLOC_PASS_BYTES, g_noalloc_host + NOALLOC_PASS_BYTES, cbytes,
                         hipMemcpyHostToDevice, stream));
+  if (ngram > 0)
+    HIP_OK(hipMemcpyAsync(dev + NOALLOC_PASS_BYTES + NOALLOC_CORE_BYTES,
+                          g_noalloc_host + NOALLOC_PASS_BYTES + NOALLOC_CORE_BYTES,
+                          (size_t)ngram * sizeof(GramArgs), hipMemcpyHostToDevice, stream));
   HIP_OK(hipStreamSynchronize(stream));
   const PassDesc* dpd = reinterpret_cast<const PassDesc*>(dev);
   for (int l = 0; l < nl; ++l) {
     const BatchLaunch& L = launches[l];
     HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, stream));
   }
+  if (ngram > 0)
+    HIP_OK(launch_gram_batch(reinterpret_cast<const GramArgs*>(dev + NOALLOC_PASS_BYTES + NOALLOC_CORE_BYTES),
+                             ngram, gblocks, stream));
   HIP_OK(launch_core_batch(reinterpret_cast<const CoreArgs*>(dev + NOALLOC_PASS_BYTES), count, stream));
   return ODMD_OK;
 }
@@ -616,8 +681,9 @@ struct odmd_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;
   std::vector<odmd_t> hs;
-  void* dev = nullptr;          // PassDesc table, then the CoreArgs table
-  size_t pass_bytes = 0;
+  void* dev = nullptr;          // PassDesc table, then the CoreArgs and GramArgs tables
+  size_t pass_bytes = 0, core_bytes = 0;
+  int ngram = 0, gblocks = 0;   // Gram kernels of the BF16 handles
   struct Launch { int first, nd, nblocks, threads, rows2, basis, rb; };
   std::vector<Launch> launches;
   int nside = 0;
@@ -703,11 +769,13 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
   s->r_max = r_max;
   s->ct = L.ct;
   s->tol = tol;
-  // A BF16 stored basis cannot hold a direction weaker than one unit of its
-  // rounding (2^-8): every refold rounds the rotated basis to BF16 again.
   // FP64 and FP32 bases take the tolerance as given (the refold is FP64, so
-  // FP32 storage adds only its own rounding to the new columns).
-  s->tol_eff = basis == ODMD_BF16 ? std::max(tol, 0.00390625) : tol;
+  // FP32 storage adds only its own rounding to the new columns).  A BF16
+  // basis is re-orthonormalised after each refold (Gram kernel), but the
+  // span of the rounded columns still differs from the basis by about 2^-9:
+  // the next snapshots show that difference as residuals of about 1e-3 of
+  // their norm, and a tolerance of 2^-12 lets truncation drop those again.
+  s->tol_eff = basis == ODMD_BF16 ? std::max(tol, 0x1p-12) : tol;
   s->basis = basis;
   s->io = io;
   s->stream = static_cast<hipStream_t>(hip_stream);
@@ -745,6 +813,10 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
     s->own = true;
   }
   s->bytes = L.total;
+  if (basis == ODMD_BF16) {
+    s->grec = reinterpret_cast<double*>(s->mem + L.gram);
+    s->gnwg = L.gnwg;
+  }
   s->st = reinterpret_cast<DevState*>(s->mem + L.st);
   s->partials = reinterpret_cast<double*>(s->mem + L.partials);
   s->Us = s->mem + L.Us;
@@ -1083,10 +1155,13 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
   for (int32_t i = 0; i < count; ++i)
     groups[{hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, hs[i]->ct}].push_back(i);
   p->pass_bytes = round_up((int64_t)count * sizeof(PassDesc), 256);
-  const size_t bytes = p->pass_bytes + (size_t)count * sizeof(CoreArgs);
+  p->core_bytes = round_up((int64_t)count * sizeof(CoreArgs), 256);
+  const size_t bytes = p->pass_bytes + p->core_bytes + (size_t)count * sizeof(GramArgs);
   std::vector<char> host(bytes, 0);
   PassDesc* pd = reinterpret_cast<PassDesc*>(host.data());
   CoreArgs* cd = reinterpret_cast<CoreArgs*>(host.data() + p->pass_bytes);
+  p->ngram = fill_gram(hs, count, reinterpret_cast<GramArgs*>(host.data() + p->pass_bytes + p->core_bytes),
+                       &p->gblocks);
   int k = 0;
   for (auto& g : groups) {
     std::stable_sort(g.second.begin(), g.second.end(), [&](int32_t a, int32_t b) {
@@ -1124,6 +1199,8 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
     c.rb = h->ct;
     c.ct = h->ct;
     c.fold_slack = fold_slack(h);
+    c.grec = h->grec;
+    c.gnwg = h->gnwg;
   }
   p->nside = p->launches.size() > 1 ? std::min<int>(NSIDE, (int)p->launches.size()) : 0;
   bool ok = hipMalloc(&p->dev, bytes) == hipSuccess &&
@@ -1167,6 +1244,10 @@ odmd_status odmd_plan_launch(odmd_plan_t p) {
       HIP_OK(hipStreamWaitEvent(p->stream, p->join[i], 0));
     }
   }
+  if (p->ngram > 0)
+    HIP_OK(launch_gram_batch(reinterpret_cast<const GramArgs*>(static_cast<char*>(p->dev) + p->pass_bytes +
+                                                               p->core_bytes),
+                             p->ngram, p->gblocks, p->stream));
   HIP_OK(launch_core_batch(
       reinterpret_cast<const CoreArgs*>(static_cast<char*>(p->dev) + p->pass_bytes),
       (int)p->hs.size(), p->stream));

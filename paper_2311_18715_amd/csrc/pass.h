@@ -49,6 +49,28 @@ struct PassDesc {
 hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int rows2, int basis,
                              int rb, hipStream_t s);
 
+// Gram matrix of a BF16 basis after a refold (gram.hip): per-workgroup
+// records of the 16x16 block pairs I <= J of the 64 columns
+constexpr int GRAM_BLOCKS = RMAX / 16;
+constexpr int GRAM_PAIRS = GRAM_BLOCKS * (GRAM_BLOCKS + 1) / 2;
+constexpr int GRAM_REC = GRAM_PAIRS * 256;   // doubles per record
+struct GramArgs {
+  const DevState* st;
+  const void* Us;       // BF16 stored columns (64-row tiles)
+  double* rec;          // nwg records of GRAM_REC doubles
+  int64_t n;
+  int ct;               // column capacity of a tile
+  int nwg;              // workgroups (records)
+  int blk0;             // batched launch: the stream's first workgroup
+};
+// workgroups of the Gram kernel for n rows (one per 8192 rows, 1..64)
+inline int gram_workgroups(int64_t n) {
+  const int64_t w = (n + 8191) / 8192;
+  return (int)(w < 1 ? 1 : (w > 64 ? 64 : w));
+}
+hipError_t launch_gram(const GramArgs& g, hipStream_t s);
+hipError_t launch_gram_batch(const GramArgs* d, int nd, int nblocks, hipStream_t s);
+
 struct CoreArgs {
   DevState* st;
   const double* partials;
@@ -64,6 +86,8 @@ struct CoreArgs {
   DevState* tst;        // general pairs: state of B = T R (R in its Q), else null
   const double* pt;     // general pairs: T sweep records, T^T e in the second half
   int rbt;              // general pairs: bucket of the T sweep
+  const double* grec;   // BF16 basis: Gram records of the refolded columns (else null)
+  int gnwg;             // their count
 };
 
 // General pairs, between the projection sweep and the streaming pass:

@@ -68,38 +68,40 @@ def test_fp32_wake_against_fp64_oracle():
 
 @pytest.mark.parametrize("shape", [None, (512, 256, 256)])   # one and two rows per lane
 def test_bf16_rollout_against_fp64_oracle(shape):
-    """BF16 storage (FP32 snapshots, FP64 residuals, projections, core and
-    eigensolver).  Tolerance: 1e-2 relative rollout error over 500 steps.
-    Reading: the comparison is with the FP64 oracle running the same
-    algorithm at the same effective tolerance, max(tol, 2^-8): a BF16 basis
-    holds directions only down to its rounding, so that is the model the
-    storage defines; the difference to an oracle that keeps directions down
-    to 1e-8 is truncation, not storage error (the test reports it)."""
+    """BF16 storage (FP32 snapshots, FP64 residuals, projections, rotation,
+    core and eigensolver; the basis re-orthonormalised after each refold).
+    Tolerance: 1e-2 relative rollout error over 500 steps against the FP64
+    oracle at the user's tolerance 1e-8 on the same snapshots.  The BF16
+    basis itself truncates at 2^-12 (its rounding shows as residuals of
+    about 2^-9 of a snapshot after each refold); the persistent modes (mean
+    flow and the ten shedding harmonics) must be held."""
     s = synth.wake(nx=300, ny=100, harmonics=10, transients=10, noise=1e-5)
     X = s.snapshots(0, 301)
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).float().cuda()
     X32 = Xd.double().cpu().numpy().T
     n = X.shape[0]
     g = ODMD(n, 64, 1e-8, basis="bf16", shape=shape)
-    tol_eff = g.info().tol_eff
-    assert tol_eff == 2.0 ** -8
-    o = O.OnlineDMD(n, 64, tol_eff)
+    assert g.info().tol_eff == 2.0 ** -12
+    o = O.OnlineDMD(n, 64, 1e-8)
     for k in range(300):
         g.update(Xd[k], Xd[k + 1])
         o.update(X32[:, k], X32[:, k + 1])
     g.sync()
-    assert g.info().r == o.r
+    assert g.info().r > 22
     pg = g.predict(500).double().cpu().numpy()
     po = o.predict(500)
     err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)
-    assert err.max() <= 1e-2
     lam, _ = g.eigs()
-    lo, _ = o.eigs()
-    big = np.abs(lo) >= 1e-2 * np.abs(lo).max()
-    m = O.match_eigs(lo[big], lam)
-    assert np.max(np.abs(m - lo[big]) / np.abs(lo[big])) < 1e-2
+    pl = s.planted_eigs()
+    persist = pl[np.abs(np.abs(pl) - 1.0) < 1e-12]
+    perr = np.max(np.abs(O.match_eigs(persist, lam) - persist) / np.abs(persist))
     U = g.basis_matrix().cpu().numpy()
-    assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) < 1e-2
+    orth = np.linalg.norm(U.T @ U - np.eye(U.shape[1]))
+    print(f"BF16 rank {g.info().r} (oracle {o.r}): rollout over 500 states {err.max():.2e}, "
+          f"persistent eigenvalues {perr:.2e}, orthogonality {orth:.2e}")
+    assert err.max() <= 1e-2
+    assert perr < 1e-2
+    assert orth < 1e-3
 
 
 def test_fp32_full_size_properties():
@@ -140,36 +142,35 @@ def test_fp32_full_size_properties():
 def test_bf16_two_rows_per_lane_ragged():
     """BF16 storage in the 512-thread shape reads two rows per lane; an odd n
     leaves the last lane's second row past the end (read clamped, zeroed,
-    never stored).  Against the FP64 oracle at the BF16 storage's tolerance
-    on the same (FP32) snapshots, the two-row path must do as well as the
+    never stored).  Against the FP64 oracle at the user's tolerance 1e-8 on
+    the same (FP32) snapshots, the two-row path must do as well as the
     one-row path (256-thread shape) on a planted stream with Gaussian
-    (non-orthogonal) modes, where BF16 rounding alone costs about 1e-2."""
+    (non-orthogonal) modes; both must stay within 1e-2 over 200 states."""
     n = 30001
     s = synth.random_planted(n, 6, seed=21)
     X = s.snapshots(0, 121)
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).float().cuda()
     X32 = Xd.double().cpu().numpy().T
+    o = O.OnlineDMD(n, 16, 1e-8)
+    for k in range(120):
+        o.update(X32[:, k], X32[:, k + 1])
+    po = o.predict(200)
     errs = {}
     for shape in ((256, 512, 512), (512, 256, 256)):
         g = ODMD(n, 16, 1e-8, basis="bf16", shape=shape)
-        if shape[0] == 256:
-            o = O.OnlineDMD(n, 16, g.info().tol_eff)
-            for k in range(120):
-                o.update(X32[:, k], X32[:, k + 1])
-            po = o.predict(200)
         for k in range(120):
             g.update(Xd[k], Xd[k + 1])
         g.sync()
-        assert g.info().r == o.r
+        assert g.info().r >= o.r
         pg = g.predict(200).double().cpu().numpy()
         errs[shape[0]] = np.max(np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1))
         U = g.basis_matrix().cpu().numpy()
         assert np.all(np.isfinite(U))
-        assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) < 1e-2
+        assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) < 1e-3
         g.close()
     print(f"rollout error vs oracle: one row per lane {errs[256]:.2e}, two rows {errs[512]:.2e}")
     assert errs[512] <= 1.5 * errs[256] + 1e-3
-    assert max(errs.values()) < 3e-2
+    assert max(errs.values()) < 1e-2
 
 
 FP32_FLOOR = 2.0 ** -20   # FP32 resolution of the singular directions (16 units of 2^-24)
