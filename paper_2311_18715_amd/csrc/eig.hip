@@ -12,7 +12,8 @@
 //   3. eigenvectors of T by back-substitution (complex arithmetic), one lane
 //      per eigenvalue, then V = Z X, unit 2-norm, largest entry real > 0;
 //   4. order by |lambda| descending, then Im descending;
-//   5. b~ = V^-1 p_y by Gaussian elimination with partial pivoting.
+//   5. b~ = V^-1 p_y = G^-1 X^-1 Z^T p_y (V = Z X G, G the normalising
+//      factors): block back-substitution.
 // k_predict_coef: c_k for a chunk of steps, folded with the basis
 // coefficients (U = S[:, :m] Q, so U c = S (Q c)).
 #include <hip/hip_runtime.h>
@@ -48,57 +49,133 @@ __device__ __forceinline__ double cabs2(cplx a) { return hypot(a.re, a.im); }
 #define Hm(i, j) H[(j) * LDH + (i)]
 #define Zm(i, j) Z[(j) * LDH + (i)]
 
-// Apply the reflector P = I - tau v v^T (v = (1, v1, v2), or (1, v1) when
-// three == false) to rows k.. of H from the left over columns [c0, n) and
-// to columns k.. of H (rows [0, r1]) and of Z (all rows) from the right.
-__device__ void apply_reflector(double* H, double* Z, int n, int k, double tau, double v1,
-                                double v2, bool three, int c0, int r1) {
-  const int t = threadIdx.x;
-  if (t >= c0 && t < n) {
-    double s = Hm(k, t) + v1 * Hm(k + 1, t);
-    if (three) s += v2 * Hm(k + 2, t);
-    s *= tau;
-    Hm(k, t) -= s;
-    Hm(k + 1, t) -= s * v1;
-    if (three) Hm(k + 2, t) -= s * v2;
-  }
-  __syncthreads();
-  if (t <= r1) {
-    double s = Hm(t, k) + v1 * Hm(t, k + 1);
-    if (three) s += v2 * Hm(t, k + 2);
-    s *= tau;
-    Hm(t, k) -= s;
-    Hm(t, k + 1) -= s * v1;
-    if (three) Hm(t, k + 2) -= s * v2;
-  }
-  if (t < n) {
-    double s = Zm(t, k) + v1 * Zm(t, k + 1);
-    if (three) s += v2 * Zm(t, k + 2);
-    s *= tau;
-    Zm(t, k) -= s;
-    Zm(t, k + 1) -= s * v1;
-    if (three) Zm(t, k + 2) -= s * v2;
-  }
-  __syncthreads();
+// The value of v in the given lane (a wave-uniform index), in every lane.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/x and 1/sqrt(x): hardware estimates refined by two Newton steps each
+__device__ __forceinline__ double recip_n(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsqrt_n(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  r = r * __builtin_fma(-h * r, r, 1.5);
+  r = r * __builtin_fma(-h * r, r, 1.5);
+  return r;
 }
 
 // Reflector mapping (x, y, z) to (alpha, 0, 0): v = (1, v1, v2), tau.
 __device__ __forceinline__ bool make_reflector(double x, double y, double z, double& tau,
                                                double& v1, double& v2, double& alpha) {
-  const double sc = fmax(fabs(x), fmax(fabs(y), fabs(z)));
-  if (sc == 0.0 || (y == 0.0 && z == 0.0)) return false;
-  const double isc = 1.0 / sc;     // one division per quantity, not per entry
-  x *= isc;
-  y *= isc;
-  z *= isc;
-  const double nrm = sqrt(x * x + y * y + z * z);
+  if (y == 0.0 && z == 0.0) return false;
+  double ss = __builtin_fma(z, z, __builtin_fma(y, y, x * x));
+  double sc = 1.0;
+  if (!(ss > 0x1p-960 && ss < 0x1p960)) {     // rescale (rare): avoid under/overflow
+    sc = fmax(fabs(x), fmax(fabs(y), fabs(z)));
+    const double isc = 1.0 / sc;
+    x *= isc;
+    y *= isc;
+    z *= isc;
+    ss = __builtin_fma(z, z, __builtin_fma(y, y, x * x));
+  }
+  const double rn = rsqrt_n(ss);               // 1 / ||(x, y, z)||
+  double nrm = ss * rn;
+  nrm = __builtin_fma(0.5 * rn, __builtin_fma(-nrm, nrm, ss), nrm);
   const double al = x >= 0.0 ? -nrm : nrm;
-  const double iden = 1.0 / (x - al);
-  v1 = y * iden;
-  v2 = z * iden;
-  tau = (al - x) / al;
+  const double id = recip_n(x - al);           // |x - al| = |x| + nrm
+  v1 = y * id;
+  v2 = z * id;
+  tau = __builtin_fma(fabs(x), rn, 1.0);       // (al - x) / al = 1 + |x| / nrm
   alpha = al * sc;
   return true;
+}
+
+// One step of the double-shift bulge chase: the reflector P = I - tau v v^T
+// (v = (1, v1, v2); (1, v1) for the last step, THREE false) built from
+// (x, y, z), applied as H <- P H P and Z <- Z P.  Every lane t is column t of
+// the left application (rows k .. k+2, columns [c0, n) outside the 3 x 3
+// block), row t of the right one (columns k .. k+2, rows [0, r1]) and row t
+// of Z's.  Rows k .. k+2 meet both: those lanes apply the left reflector to
+// their row of the 3 x 3 block (read by every lane) before the right one,
+// and the column lanes leave the block to them, so no entry is written
+// twice.  A lane outside a role reads and writes its own slots of dum
+// instead (straight-line code, no divergent branches).  Returns this lane's
+// new H(t, k) (rows <= r1), from which the next step's (x, y, z) are taken.
+template <bool THREE>
+__device__ __forceinline__ double bulge_step(double* H, double* Z, double* dum, int n, int l, int hi,
+                                             int k, double x, double y, double z) {
+  constexpr int nb = THREE ? 3 : 2;
+  const int t = threadIdx.x;
+  const int c0 = k > l ? k - 1 : l;
+  const int r1 = THREE ? min(k + 3, hi) : hi;
+  const bool col_live = t >= c0 && t < n && (t < k || t >= k + nb);
+  const bool row_live = t <= r1;
+  const bool z_live = t < n;
+  double* pc = col_live ? &Hm(k, t) : dum + 9 * t;          // rows k .. k+nb-1, stride 1
+  double* pr0 = row_live ? &Hm(t, k) : dum + 9 * t + 3;
+  double* pr1 = row_live ? &Hm(t, k + 1) : dum + 9 * t + 4;
+  double* pr2 = row_live ? &Hm(t, k + 2) : dum + 9 * t + 5;
+  double* pz0 = z_live ? &Zm(t, k) : dum + 9 * t + 6;
+  double* pz1 = z_live ? &Zm(t, k + 1) : dum + 9 * t + 7;
+  double* pz2 = z_live ? &Zm(t, k + 2) : dum + 9 * t + 8;
+  double b0[nb], b1[nb], b2[nb];                             // H(k .. k+2, k + c)
+#pragma unroll
+  for (int c = 0; c < nb; ++c) {
+    b0[c] = Hm(k, k + c);
+    b1[c] = Hm(k + 1, k + c);
+    b2[c] = THREE ? Hm(k + 2, k + c) : 0.0;
+  }
+  double cv0 = pc[0], cv1 = pc[1], cv2 = THREE ? pc[2] : 0.0;
+  double rv0 = *pr0, rv1 = *pr1, rv2 = THREE ? *pr2 : 0.0;
+  double zv0 = *pz0, zv1 = *pz1, zv2 = THREE ? *pz2 : 0.0;
+  double tau, v1, v2 = 0.0, al;
+  if (!make_reflector(x, y, THREE ? z : 0.0, tau, v1, v2, al)) return rv0;   // uniform
+  // column t, rows k .. k+2 (the bulge column k - 1 becomes (alpha, 0, 0))
+  const double sc = tau * (cv0 + v1 * cv1 + v2 * cv2);
+  const bool bulge = k > l && t == k - 1;
+  cv0 = bulge ? al : cv0 - sc;
+  cv1 = bulge ? 0.0 : cv1 - sc * v1;
+  cv2 = bulge ? 0.0 : cv2 - sc * v2;
+  // rows k .. k+2: row t of the block after the left application
+  const int a = t - k;
+  const bool in_blk = a >= 0 && a < nb;
+  const double va = a == 1 ? v1 : (a == 2 ? v2 : 1.0);
+#pragma unroll
+  for (int c = 0; c < nb; ++c) {
+    const double sb = tau * (b0[c] + v1 * b1[c] + v2 * b2[c]);
+    const double ba = a == 1 ? b1[c] : (a == 2 ? b2[c] : b0[c]);
+    const double nr = ba - sb * va;
+    if (c == 0) rv0 = in_blk ? nr : rv0;
+    if (c == 1) rv1 = in_blk ? nr : rv1;
+    if (c == 2) rv2 = in_blk ? nr : rv2;
+  }
+  // row t, columns k .. k+2, and row t of Z
+  const double sr = tau * (rv0 + v1 * rv1 + v2 * rv2);
+  rv0 -= sr;
+  rv1 -= sr * v1;
+  rv2 -= sr * v2;
+  const double sz = tau * (zv0 + v1 * zv1 + v2 * zv2);
+  zv0 -= sz;
+  zv1 -= sz * v1;
+  zv2 -= sz * v2;
+  pc[0] = cv0;
+  pc[1] = cv1;
+  if (THREE) pc[2] = cv2;
+  *pr0 = rv0;
+  *pr1 = rv1;
+  if (THREE) *pr2 = rv2;
+  *pz0 = zv0;
+  *pz1 = zv1;
+  if (THREE) *pz2 = zv2;
+  return rv0;
 }
 
 __device__ __forceinline__ void eig_body(DevState* st) {
@@ -108,7 +185,9 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   __shared__ double Xr[(RMAX + 1) * LDH];
   __shared__ double Xi[(RMAX + 1) * LDH];
   __shared__ double wr[RMAX], wi[RMAX], hv[RMAX];
+  __shared__ double gr[RMAX], gi[RMAX], cr[RMAX], ci[RMAX];
   __shared__ int srank[RMAX];
+  __shared__ double dum[64 * 9];           // slots of lanes outside a role of a bulge step
   __shared__ int sfail;
   const int t = threadIdx.x;
   const int n = st->r;
@@ -145,20 +224,36 @@ __device__ __forceinline__ void eig_body(DevState* st) {
     if (t < n) hv[t] = (t == k + 1) ? v0 : (t > k + 1 ? Hm(t, k) : 0.0);
     __syncthreads();
     if (t >= k && t < n) {          // left: rows k+1.., column t
-      double s = 0.0;
-      for (int i = k + 1; i < n; ++i) s += hv[i] * Hm(i, t);
-      s *= beta;
+      double s = 0.0, s2 = 0.0;
+      int i = k + 1;
+#pragma unroll 4
+      for (; i + 1 < n; i += 2) {
+        s = __builtin_fma(hv[i], Hm(i, t), s);
+        s2 = __builtin_fma(hv[i + 1], Hm(i + 1, t), s2);
+      }
+      if (i < n) s = __builtin_fma(hv[i], Hm(i, t), s);
+      s = (s + s2) * beta;
+#pragma unroll 8
       for (int i = k + 1; i < n; ++i) Hm(i, t) -= s * hv[i];
     }
     __syncthreads();
     if (t < n) {                    // right: columns k+1.., row t (H and Z)
-      double s = 0.0, sz = 0.0;
-      for (int j = k + 1; j < n; ++j) {
-        s += Hm(t, j) * hv[j];
-        sz += Zm(t, j) * hv[j];
+      double s = 0.0, sz = 0.0, s2 = 0.0, sz2 = 0.0;
+      int j = k + 1;
+#pragma unroll 4
+      for (; j + 1 < n; j += 2) {
+        s = __builtin_fma(Hm(t, j), hv[j], s);
+        sz = __builtin_fma(Zm(t, j), hv[j], sz);
+        s2 = __builtin_fma(Hm(t, j + 1), hv[j + 1], s2);
+        sz2 = __builtin_fma(Zm(t, j + 1), hv[j + 1], sz2);
       }
-      s *= beta;
-      sz *= beta;
+      if (j < n) {
+        s = __builtin_fma(Hm(t, j), hv[j], s);
+        sz = __builtin_fma(Zm(t, j), hv[j], sz);
+      }
+      s = (s + s2) * beta;
+      sz = (sz + sz2) * beta;
+#pragma unroll 8
       for (int j = k + 1; j < n; ++j) {
         Hm(t, j) -= s * hv[j];
         Zm(t, j) -= sz * hv[j];
@@ -274,29 +369,17 @@ __device__ __forceinline__ void eig_body(DevState* st) {
     double x = Hm(l, l) * Hm(l, l) + Hm(l, l + 1) * Hm(l + 1, l) - s * Hm(l, l) + tt;
     double y = Hm(l + 1, l) * (Hm(l, l) + Hm(l + 1, l + 1) - s);
     double z = Hm(l + 1, l) * Hm(l + 2, l + 1);
-    for (int k = l; k <= hi - 1; ++k) {
-      const bool three = k < hi - 1;
-      double tau, v1, v2 = 0.0, al;
-      const bool ok = make_reflector(x, y, three ? z : 0.0, tau, v1, v2, al);
-      __syncthreads();
-      if (ok) {
-        const int c0 = k > l ? k - 1 : l;
-        const int r1 = min(k + 3, hi);
-        apply_reflector(H, Z, n, k, tau, v1, v2, three, c0, r1);
-        if (k > l && t == 0) {
-          Hm(k, k - 1) = al;
-          Hm(k + 1, k - 1) = 0.0;
-          if (three) Hm(k + 2, k - 1) = 0.0;
-        }
-        __syncthreads();
-      }
-      if (k < hi - 1) {
-        x = Hm(k + 1, k);
-        y = Hm(k + 2, k);
-        z = (k + 3 <= hi) ? Hm(k + 3, k) : 0.0;
-      }
+    // Bulge chase: one barrier per step; the next step's (x, y, z), the new
+    // H(k+1 .. k+3, k), come from the registers of the lanes of those rows.
+    for (int k = l; k < hi - 1; ++k) {
+      const double colk = bulge_step<true>(H, Z, dum, n, l, hi, k, x, y, z);
+      x = readlane_d(colk, k + 1);
+      y = readlane_d(colk, k + 2);
+      z = (k + 3 <= hi) ? readlane_d(colk, k + 3) : 0.0;
       __syncthreads();
     }
+    bulge_step<false>(H, Z, dum, n, l, hi, hi - 1, x, y, 0.0);
+    __syncthreads();
   }
   __syncthreads();
 
@@ -329,93 +412,152 @@ __device__ __forceinline__ void eig_body(DevState* st) {
       Xi[t * LDH + q] = u2.im;
       start = p - 1;
     }
+    // running bound of the computed entries, for the rescaling test
+    double mx = 0.0;
+    for (int j = start + 1; j < n; ++j) mx = fmax(mx, fabs(Xr[t * LDH + j]) + fabs(Xi[t * LDH + j]));
     int i = start;
     while (i >= 0) {
       const bool blk = i > 0 && Hm(i, i - 1) != 0.0;
-      if (!blk) {
-        cplx s = {0.0, 0.0};
-        for (int j = i + 1; j < n; ++j) {
-          const cplx xj = {Xr[t * LDH + j], Xi[t * LDH + j]};
-          s = cadd(s, cmul({Hm(i, j), 0.0}, xj));
+      // s = sum_{j > i} H(row, j) x_j for the one or two rows of this block
+      // (H real: two real sums per row, two accumulators each)
+      const int i0 = blk ? i - 1 : i;
+      double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;   // row i0
+      double u0r = 0.0, u0i = 0.0, u1r = 0.0, u1i = 0.0;   // row i (block only)
+      int j = i + 1;
+      for (; j + 1 < n; j += 2) {
+        const double xr0 = Xr[t * LDH + j], xi0 = Xi[t * LDH + j];
+        const double xr1 = Xr[t * LDH + j + 1], xi1 = Xi[t * LDH + j + 1];
+        const double h0 = Hm(i0, j), h1 = Hm(i0, j + 1);
+        s0r = __builtin_fma(h0, xr0, s0r);
+        s0i = __builtin_fma(h0, xi0, s0i);
+        s1r = __builtin_fma(h1, xr1, s1r);
+        s1i = __builtin_fma(h1, xi1, s1i);
+        if (blk) {                               // this lane's block row
+          const double g0 = Hm(i, j), g1 = Hm(i, j + 1);
+          u0r = __builtin_fma(g0, xr0, u0r);
+          u0i = __builtin_fma(g0, xi0, u0i);
+          u1r = __builtin_fma(g1, xr1, u1r);
+          u1i = __builtin_fma(g1, xi1, u1i);
         }
+      }
+      if (j < n) {
+        const double xr0 = Xr[t * LDH + j], xi0 = Xi[t * LDH + j];
+        const double h0 = Hm(i0, j);
+        s0r = __builtin_fma(h0, xr0, s0r);
+        s0i = __builtin_fma(h0, xi0, s0i);
+        if (blk) {
+          const double g0 = Hm(i, j);
+          u0r = __builtin_fma(g0, xr0, u0r);
+          u0i = __builtin_fma(g0, xi0, u0i);
+        }
+      }
+      if (!blk) {
         cplx den = csub({Hm(i, i), 0.0}, lam);
         if (cabs2(den) < smin) den = {smin, 0.0};
-        const cplx xi = cdiv({-s.re, -s.im}, den);
+        const cplx xi = cdiv({-(s0r + s1r), -(s0i + s1i)}, den);
         Xr[t * LDH + i] = xi.re;
         Xi[t * LDH + i] = xi.im;
+        mx = fmax(mx, fabs(xi.re) + fabs(xi.im));
         i -= 1;
       } else {
-        const int i0 = i - 1;
-        cplx s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
-        for (int j = i + 1; j < n; ++j) {
-          const cplx xj = {Xr[t * LDH + j], Xi[t * LDH + j]};
-          s0 = cadd(s0, cmul({Hm(i0, j), 0.0}, xj));
-          s1 = cadd(s1, cmul({Hm(i, j), 0.0}, xj));
-        }
         const cplx m00 = csub({Hm(i0, i0), 0.0}, lam), m01 = {Hm(i0, i), 0.0};
         const cplx m10 = {Hm(i, i0), 0.0}, m11 = csub({Hm(i, i), 0.0}, lam);
         cplx det = csub(cmul(m00, m11), cmul(m01, m10));
         if (cabs2(det) < smin * smin) det = {smin * smin, 0.0};
-        const cplx r0 = {-s0.re, -s0.im}, r1 = {-s1.re, -s1.im};
+        const cplx r0 = {-(s0r + s1r), -(s0i + s1i)}, r1 = {-(u0r + u1r), -(u0i + u1i)};
         const cplx x0 = cdiv(csub(cmul(r0, m11), cmul(m01, r1)), det);
         const cplx x1 = cdiv(csub(cmul(m00, r1), cmul(m10, r0)), det);
         Xr[t * LDH + i0] = x0.re;
         Xi[t * LDH + i0] = x0.im;
         Xr[t * LDH + i] = x1.re;
         Xi[t * LDH + i] = x1.im;
+        mx = fmax(mx, fmax(fabs(x0.re) + fabs(x0.im), fabs(x1.re) + fabs(x1.im)));
         i -= 2;
       }
       // rescale to keep the entries bounded
-      double mx = 0.0;
-      for (int j = max(i + 1, 0); j < n; ++j)
-        mx = fmax(mx, fabs(Xr[t * LDH + j]) + fabs(Xi[t * LDH + j]));
       if (mx > 1e100) {
         const double f = 1.0 / mx;
-        for (int j = 0; j < n; ++j) {
-          Xr[t * LDH + j] *= f;
-          Xi[t * LDH + j] *= f;
+        for (int jj = 0; jj < n; ++jj) {
+          Xr[t * LDH + jj] *= f;
+          Xi[t * LDH + jj] *= f;
         }
+        mx = 1.0;
       }
     }
   }
   __syncthreads();
 
   // V = Z X, normalised, stored at its rank in the output order
+  if (t < n) hv[t] = hypot(wr[t], wi[t]);    // |lambda| (hv is free after the reduction)
+  __syncthreads();
   if (t < n && !sfail) {
-    const double ml = hypot(wr[t], wi[t]);
+    const double ml = hv[t];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double mj = hypot(wr[j], wi[j]);
+      const double mj = hv[j];
       rank += (mj > ml) || (mj == ml && (wi[j] > wi[t] || (wi[j] == wi[t] && j < t)));
     }
     srank[t] = rank;
     double* __restrict__ vr = st->V_re + rank * RMAX;
     double* __restrict__ vi = st->V_im + rank * RMAX;
-    double nrm2 = 0.0, best = -1.0;
-    int ib = 0;
-    for (int i = 0; i < n; ++i) {
-      double ar = 0.0, ai = 0.0;
-      for (int j = 0; j < n; ++j) {
-        ar += Zm(i, j) * Xr[t * LDH + j];
-        ai += Zm(i, j) * Xi[t * LDH + j];
+    // entries i0 .. i0+3 of Z X[:, t]: one load of x_j serves four rows of
+    // Z (rows past n read row 0 and are not used)
+    auto zx4 = [&](int i0, double (&ar)[4], double (&ai)[4]) {
+      int ir[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ar[u] = 0.0;
+        ai[u] = 0.0;
+        ir[u] = i0 + u < n ? i0 + u : 0;
       }
-      vr[i] = ar;
-      vi[i] = ai;
-      const double m2 = ar * ar + ai * ai;
-      nrm2 += m2;
-      if (m2 > best) {
-        best = m2;
-        ib = i;
+      for (int j = 0; j < n; ++j) {
+        const double xr = Xr[t * LDH + j], xi = Xi[t * LDH + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double z = Zm(ir[u], j);
+          ar[u] = __builtin_fma(z, xr, ar[u]);
+          ai[u] = __builtin_fma(z, xi, ai[u]);
+        }
+      }
+    };
+    // first pass: the norm and the largest-modulus entry; the second forms
+    // the entries again (bit for bit) and writes them normalised
+    double nrm2 = 0.0, best = -1.0, vbr = 0.0, vbi = 0.0;
+    int ib = 0;
+    for (int i0 = 0; i0 < n; i0 += 4) {
+      double ar[4], ai[4];
+      zx4(i0, ar, ai);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + u < n) {
+          const double m2 = ar[u] * ar[u] + ai[u] * ai[u];
+          nrm2 += m2;
+          if (m2 > best) {
+            best = m2;
+            ib = i0 + u;
+            vbr = ar[u];
+            vbi = ai[u];
+          }
+        }
       }
     }
     // unit norm, largest-modulus entry real and positive: multiply by
     // conj(v_ib) / (|v_ib| ||v||)
     const double m = sqrt(best), f = 1.0 / sqrt(nrm2);
-    const double pr = vr[ib] / m * f, pi = -vi[ib] / m * f;
-    for (int i = 0; i < n; ++i) {
-      const double ar = vr[i], ai = vi[i];
-      vr[i] = ar * pr - ai * pi;
-      vi[i] = i == ib ? 0.0 : ar * pi + ai * pr;
+    const double pr = vbr / m * f, pi = -vbi / m * f;
+    gr[t] = pr;                              // V[:, rank] = (Z X[:, t]) (pr + i pi)
+    gi[t] = pi;
+    for (int i0 = 0; i0 < n; i0 += 4) {
+      double ar[4], ai[4];
+      zx4(i0, ar, ai);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u;
+        if (i < n) {
+          vr[i] = ar[u] * pr - ai[u] * pi;
+          vi[i] = i == ib ? 0.0 : ar[u] * pi + ai[u] * pr;
+        }
+      }
     }
     st->lam_re[rank] = wr[t];
     st->lam_im[rank] = wi[t];
@@ -423,76 +565,62 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   __threadfence();
   __syncthreads();
 
-  // 5. b~ = V^-1 p_y: Gaussian elimination with partial pivoting on [V | p_y]
-  //    (reuses Xr/Xi as the complex augmented matrix, column-major)
+  // 5. b~ = V^-1 p_y.  V is Z X G with its columns reordered (G the
+  //    diagonal of the normalising factors), Z orthogonal and X block upper
+  //    triangular (a 2 x 2 diagonal block per complex pair), so
+  //    b~ = G^-1 X^-1 Z^T p_y: one matrix-vector product, then a block
+  //    back-substitution with one lane per entry of the right-hand side.
   if (!sfail) {
-    for (int idx = t; idx < n * (n + 1); idx += 64) {
-      const int i = idx % n, j = idx / n;
-      if (j < n) {
-        Xr[j * LDH + i] = st->V_re[j * RMAX + i];
-        Xi[j * LDH + i] = st->V_im[j * RMAX + i];
-      } else {
-        Xr[j * LDH + i] = st->py[i];
-        Xi[j * LDH + i] = 0.0;
-      }
+    if (t < n) {
+      double a = 0.0;
+      for (int i = 0; i < n; ++i) a += Zm(i, t) * st->py[i];
+      cr[t] = a;
+      ci[t] = 0.0;
     }
     __syncthreads();
-    for (int cidx = 0; cidx < n; ++cidx) {
-      // pivot: the largest modulus in rows cidx.., the first of equals
-      // (one row per lane, then a butterfly over the wavefront)
-      double best = -1.0;
-      int piv = n;
-      if (t >= cidx && t < n) {
-        best = hypot(Xr[cidx * LDH + t], Xi[cidx * LDH + t]);
-        piv = t;
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int op = __shfl_xor(piv, o, 64);
-        if (ob > best || (ob == best && op < piv)) {
-          best = ob;
-          piv = op;
+    for (int i = n - 1; i >= 0;) {
+      const bool pair = i > 0 && wi[i] < 0.0;     // (i - 1, i): a complex pair
+      if (!pair) {
+        const cplx b = cdiv({cr[i], ci[i]}, {Xr[i * LDH + i], Xi[i * LDH + i]});
+        if (t < i) {
+          const cplx u = cmul({Xr[i * LDH + t], Xi[i * LDH + t]}, b);
+          cr[t] -= u.re;
+          ci[t] -= u.im;
         }
-      }
-      __syncthreads();
-      if (piv != cidx) {
-        for (int j = t; j <= n; j += 64) {
-          const double ar = Xr[j * LDH + cidx], ai = Xi[j * LDH + cidx];
-          Xr[j * LDH + cidx] = Xr[j * LDH + piv];
-          Xi[j * LDH + cidx] = Xi[j * LDH + piv];
-          Xr[j * LDH + piv] = ar;
-          Xi[j * LDH + piv] = ai;
+        if (t == i) {                              // c[i] is spent: it now holds b'[i]
+          cr[i] = b.re;
+          ci[i] = b.im;
         }
-      }
-      __syncthreads();
-      cplx dv = {Xr[cidx * LDH + cidx], Xi[cidx * LDH + cidx]};
-      if (cabs2(dv) < 1e-300) dv = {1e-300, 0.0};
-      if (t > cidx && t < n) {
-        const cplx f = cdiv({Xr[cidx * LDH + t], Xi[cidx * LDH + t]}, dv);
-        for (int j = cidx; j <= n; ++j) {
-          const cplx u = cmul(f, {Xr[j * LDH + cidx], Xi[j * LDH + cidx]});
-          Xr[j * LDH + t] -= u.re;
-          Xi[j * LDH + t] -= u.im;
+        __syncthreads();
+        i -= 1;
+      } else {
+        const int p = i - 1, q = i;
+        const cplx xpp = {Xr[p * LDH + p], Xi[p * LDH + p]}, xpq = {Xr[q * LDH + p], Xi[q * LDH + p]};
+        const cplx xqp = {Xr[p * LDH + q], Xi[p * LDH + q]}, xqq = {Xr[q * LDH + q], Xi[q * LDH + q]};
+        const cplx cp = {cr[p], ci[p]}, cq = {cr[q], ci[q]};
+        const cplx det = csub(cmul(xpp, xqq), cmul(xpq, xqp));
+        const cplx bp = cdiv(csub(cmul(cp, xqq), cmul(xpq, cq)), det);
+        const cplx bq = cdiv(csub(cmul(xpp, cq), cmul(xqp, cp)), det);
+        if (t < p) {
+          const cplx u = cadd(cmul({Xr[p * LDH + t], Xi[p * LDH + t]}, bp),
+                              cmul({Xr[q * LDH + t], Xi[q * LDH + t]}, bq));
+          cr[t] -= u.re;
+          ci[t] -= u.im;
         }
+        if (t == p) {
+          cr[p] = bp.re;
+          ci[p] = bp.im;
+          cr[q] = bq.re;
+          ci[q] = bq.im;
+        }
+        __syncthreads();
+        i -= 2;
       }
-      __syncthreads();
     }
-    for (int i = n - 1; i >= 0; --i) {
-      cplx dv = {Xr[i * LDH + i], Xi[i * LDH + i]};
-      if (cabs2(dv) < 1e-300) dv = {1e-300, 0.0};
-      const cplx xi = cdiv({Xr[n * LDH + i], Xi[n * LDH + i]}, dv);
-      __syncthreads();
-      if (t < i) {
-        const cplx u = cmul({Xr[i * LDH + t], Xi[i * LDH + t]}, xi);
-        Xr[n * LDH + t] -= u.re;
-        Xi[n * LDH + t] -= u.im;
-      }
-      if (t == 0) {
-        st->bt_re[i] = xi.re;
-        st->bt_im[i] = xi.im;
-      }
-      __syncthreads();
+    if (t < n) {
+      const cplx b = cdiv({cr[t], ci[t]}, {gr[t], gi[t]});
+      st->bt_re[srank[t]] = b.re;
+      st->bt_im[srank[t]] = b.im;
     }
   }
   if (t == 0) {
