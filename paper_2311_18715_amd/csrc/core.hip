@@ -136,7 +136,7 @@ struct SecShared {
   double zh[MMAX], nrm[2 * MMAX];
   double gc[MMAX], gs[MMAX], d[MMAX], z[MMAX];
   int J[MMAX], gi[MMAX], gj[MMAX], dflist[MMAX], live[MMAX];
-  int nd, ndef, ngiv, fail, close;
+  int nd, ndef, ngiv, fail;
   double tol;
 };
 
@@ -163,32 +163,34 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
   const int tid = threadIdx.x;
   const int n = r + 1;
 
-  // tolerance 8 eps max(|d|, |z|)
+  // Set-up, by the first wavefront alone (one workgroup barrier at its
+  // end): the tolerance 8 eps max(|d|, |z|), the poles and weights, the
+  // deflation of tiny z (never the zero pole) keeping descending order, the
+  // tied-pole check and merge, and the live poles' staging.  Lane t holds
+  // entries t and t + 64.  Within one wavefront the LDS writes of one step
+  // are seen by the next (the wave's LDS operations complete in order; the
+  // wavefront fence keeps the compiler from reordering them).
   if (tid < 64) {
+    const int j0 = tid, j1 = tid + 64;
     double m = 0.0;
     for (int j = tid; j < r; j += 64) m = fmax(m, fmax(fabs(sig[j]), fabs(pv[j])));
     if (tid == 0) m = fmax(m, fabs(rho));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if (tid == 0) {
-      S.tol = 8.0 * SEC_EPS * m;
-      S.close = 0;
-      S.fail = 0;
-      S.ngiv = 0;
+    const double tl = 8.0 * SEC_EPS * m;
+    const double rz = fabs(rho) <= tl ? tl : rho;
+    const double d0 = j0 < r ? sig[j0] : 0.0, z0 = j0 < r ? pv[j0] : rz;
+    const double d1 = j1 < r ? sig[j1] : 0.0, z1 = j1 < r ? pv[j1] : rz;
+    if (j0 < n) {
+      S.d[j0] = d0;
+      S.z[j0] = z0;
     }
-  }
-  __syncthreads();
-  const double tol = S.tol;
-  if (tid < n) {
-    S.d[tid] = tid < r ? sig[tid] : 0.0;
-    S.z[tid] = tid < r ? pv[tid] : (fabs(rho) <= tol ? tol : rho);
-  }
-  __syncthreads();
-  // deflate tiny z (never the zero pole), keeping descending order (wave 0)
-  if (tid < 64) {
-    const int j0 = tid, j1 = tid + 64;
-    const bool l0 = j0 < n && !(j0 < r && fabs(S.z[j0]) <= tol);
-    const bool l1 = j1 < n && !(j1 < r && fabs(S.z[j1]) <= tol);
+    if (j1 < n) {
+      S.d[j1] = d1;
+      S.z[j1] = z1;
+    }
+    const bool l0 = j0 < n && !(j0 < r && fabs(z0) <= tl);
+    const bool l1 = j1 < n && !(j1 < r && fabs(z1) <= tl);
     const unsigned long long m0 = __ballot(l0), m1 = __ballot(l1);
     const unsigned long long lt = (tid == 0) ? 0ull : (~0ull >> (64 - tid));
     const int p0 = __popcll(m0 & lt), p1 = __popcll(m1 & lt);
@@ -201,52 +203,63 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
       if (l1) S.live[nl0 + p1] = j1;
       else S.dflist[nd0 + (j1 - 64 - p1)] = j1;
     }
-    if (tid == 0) {
-      S.nd = nl0 + __popcll(m1);
-      S.ndef = n - S.nd;
-    }
-  }
-  __syncthreads();
-  // tied poles (rare): detect in parallel, merge serially
-  if (tid + 1 < S.nd) {
-    const int i = S.live[tid], j = S.live[tid + 1];
-    if (j != r && S.d[i] - S.d[j] <= tol) S.close = 1;
-  }
-  __syncthreads();
-  if (S.close && tid == 0) {
-    int nl = S.nd, ndef = S.ndef, ngiv = 0, k = 0;
-    while (k + 1 < nl) {
+    int nl = nl0 + __popcll(m1), ndef = n - nl;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // tied poles (rare): detected in parallel, merged serially by lane 0
+    bool tie = false;
+    for (int k = tid; k + 1 < nl; k += 64) {
       const int i = S.live[k], j = S.live[k + 1];
-      if (j != r && S.d[i] - S.d[j] <= tol) {
-        const double h = hypot(S.z[i], S.z[j]);
-        S.gc[ngiv] = S.z[i] / h;
-        S.gs[ngiv] = S.z[j] / h;
-        S.gi[ngiv] = i;
-        S.gj[ngiv] = j;
-        ++ngiv;
-        S.z[i] = h;
-        S.dflist[ndef++] = j;
-        for (int t = k + 1; t + 1 < nl; ++t) S.live[t] = S.live[t + 1];
-        --nl;
-      } else {
-        ++k;
-      }
+      tie = tie || (j != r && S.d[i] - S.d[j] <= tl);
     }
-    S.nd = nl;
-    S.ndef = ndef;
-    S.ngiv = ngiv;
+    int ngiv = 0;
+    if (__ballot(tie)) {
+      if (tid == 0) {
+        int k = 0;
+        while (k + 1 < nl) {
+          const int i = S.live[k], j = S.live[k + 1];
+          if (j != r && S.d[i] - S.d[j] <= tl) {
+            const double h = hypot(S.z[i], S.z[j]);
+            S.gc[ngiv] = S.z[i] / h;
+            S.gs[ngiv] = S.z[j] / h;
+            S.gi[ngiv] = i;
+            S.gj[ngiv] = j;
+            ++ngiv;
+            S.z[i] = h;
+            S.dflist[ndef++] = j;
+            for (int t = k + 1; t + 1 < nl; ++t) S.live[t] = S.live[t + 1];
+            --nl;
+          } else {
+            ++k;
+          }
+        }
+      }
+      nl = __shfl(nl, 0, 64);
+      ndef = __shfl(ndef, 0, 64);
+      ngiv = __shfl(ngiv, 0, 64);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int t = tid; t < nl; t += 64) {
+      const int j = S.live[t];
+      const double zj = S.z[j];
+      S.J[t] = j;
+      S.dj[t] = S.d[j];
+      S.zz[t] = zj * zj;
+      S.zs[t] = zj < 0.0 ? -1.0 : 1.0;
+    }
+    if (tid == 0) {
+      S.tol = tl;
+      S.fail = 0;
+      S.nd = nl;
+      S.ndef = ndef;
+      S.ngiv = ngiv;
+    }
   }
   __syncthreads();
   const int nd = S.nd;
-  if (tid < nd) {
-    const int j = S.live[tid];
-    const double zj = S.z[j];
-    S.J[tid] = j;
-    S.dj[tid] = S.d[j];
-    S.zz[tid] = zj * zj;
-    S.zs[tid] = zj < 0.0 ? -1.0 : 1.0;
-  }
-  __syncthreads();
 
   // roots: one 16-lane quarter-wave each, the lane's terms kept in registers
   const int qw = tid >> 4, ql = tid & 15;
@@ -272,7 +285,7 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
       half = 0.5 * (S.dj[i - 1] - dI) * (S.dj[i - 1] + dI);
 #pragma unroll
       for (int m = 0; m < SEC_TERMS; ++m)
-        if (ql + 16 * m < nd) fm += tzz[m] / ((tdj[m] - dI) * (tdj[m] + dI) - half);
+        if (ql + 16 * m < nd) fm += tzz[m] * recip((tdj[m] - dI) * (tdj[m] + dI) - half);
       fm = 1.0 + row_sum(fm);
       K = fm > 0.0 ? i : i - 1;
     }
@@ -387,75 +400,81 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
     double prod = 1.0;
     for (int i = ql; i < nd; i += 16) {
       const double di = S.dj[i];
-      prod *= i == jj ? lam_minus_d(S, jj, dj) : lam_minus_d(S, i, dj) / ((di - dj) * (di + dj));
+      prod *= i == jj ? lam_minus_d(S, jj, dj) : lam_minus_d(S, i, dj) * recip((di - dj) * (di + dj));
     }
     prod = row_prod(prod);
     if (ql == 0) S.zh[jj] = S.zs[jj] * sqrt(fmax(prod, 0.0));
   }
-  // clear the outputs
-  for (int idx = tid; idx < n * n; idx += CORE_THREADS) {
-    const int row = idx % n, col = idx / n;
-    A[col * LDK + row] = 0.0;
-    V[col * LDK + row] = 0.0;
-  }
   __syncthreads();
-  // unnormalised vectors of the roots: column i, live rows J[jj]
-  for (int idx = tid; idx < nd * nd; idx += CORE_THREADS) {
-    const int jj = idx % nd, i = idx / nd;
-    const double dj = S.dj[jj];
-    const double den = -lam_minus_d(S, i, dj);      // d_jj^2 - lambda_i
-    const int row = S.J[jj];
-    A[i * LDK + row] = S.zh[jj] / den;
-    V[i * LDK + row] = (row == r) ? -1.0 : dj * S.zh[jj] / den;
-  }
-  __syncthreads();
-  // column norms (one half-wavefront per column and matrix)
-  {
-    const int hw = tid >> 5, hl = tid & 31;
-    for (int q = hw; q < 2 * nd; q += CORE_THREADS / 32) {
-      const int i = q % nd;
-      const double* M = q < nd ? A : V;
-      double sm = 0.0;
-      for (int jj = hl; jj < nd; jj += 32) {
-        const double v = M[i * LDK + S.J[jj]];
-        sm += v * v;
+  // Vectors of the roots, one quarter-wave per column i: the unnormalised
+  // entries on the live rows J[jj] (zero on the deflated rows), their norms,
+  // then U columns of length sigma'_i and V columns of length 1, and the
+  // finite check, with no barrier in between.
+  for (int i = qw; i < nd; i += CORE_THREADS / 16) {
+    double ea[SEC_TERMS], ev[SEC_TERMS];
+    double sa = 0.0, sv = 0.0;
+#pragma unroll
+    for (int m = 0; m < SEC_TERMS; ++m) {
+      const int jj = ql + 16 * m;
+      ea[m] = 0.0;
+      ev[m] = 0.0;
+      if (jj < nd) {
+        const double dj = S.dj[jj];
+        const double a = S.zh[jj] * recip(-lam_minus_d(S, i, dj));   // z~_j / (d_j^2 - lambda_i)
+        ea[m] = a;
+        ev[m] = S.J[jj] == r ? -1.0 : dj * a;
+        sa = __builtin_fma(a, a, sa);
+        sv = __builtin_fma(ev[m], ev[m], sv);
       }
-      sm = halfwave_sum(sm);
-      if (hl == 0) S.nrm[q] = sm;
     }
-  }
-  __syncthreads();
-  // scale: U columns to length sigma', V columns to length 1
-  for (int idx = tid; idx < nd * nd; idx += CORE_THREADS) {
-    const int jj = idx % nd, i = idx / nd;
-    const int row = S.J[jj];
-    const double om = sqrt(S.rK[i] * S.rK[i] + S.mu[i]);
-    A[i * LDK + row] *= om / sqrt(S.nrm[i]);
-    V[i * LDK + row] /= sqrt(S.nrm[nd + i]);
+    sa = row_sum(sa);
+    sv = row_sum(sv);
+    const double fa = sqrt(S.rK[i] * S.rK[i] + S.mu[i]) / sqrt(sa);
+    const double fv = 1.0 / sqrt(sv);
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < SEC_TERMS; ++m) {
+      const int jj = ql + 16 * m;
+      if (jj < nd) {
+        const int row = S.J[jj];
+        const double a = ea[m] * fa, v = ev[m] * fv;
+        A[i * LDK + row] = a;
+        V[i * LDK + row] = v;
+        bad = bad || !isfinite(a) || !isfinite(v);
+      }
+    }
+    for (int t = ql; t < S.ndef; t += 16) {
+      A[i * LDK + S.dflist[t]] = 0.0;
+      V[i * LDK + S.dflist[t]] = 0.0;
+    }
+    if (bad) S.fail = 1;
   }
   // deflated pairs: (d_j, e_j, e_j)
-  for (int t = tid; t < S.ndef; t += CORE_THREADS) {
+  for (int idx = tid; idx < S.ndef * n; idx += CORE_THREADS) {
+    const int t = idx / n, row = idx % n;
     const int j = S.dflist[t], col = nd + t;
-    A[col * LDK + j] = sig[j];
-    V[col * LDK + j] = 1.0;
+    A[col * LDK + row] = row == j ? sig[j] : 0.0;
+    V[col * LDK + row] = row == j ? 1.0 : 0.0;
   }
   __syncthreads();
   // undo the tied-pole rotations on the rows of U_k and V_k
-  if (S.ngiv > 0 && tid < 2 * n) {
-    double* M = tid < n ? A : V;
-    const int col = tid % n;
-    for (int g = S.ngiv - 1; g >= 0; --g) {
-      const int i = S.gi[g], j = S.gj[g];
-      const double cg = S.gc[g], sn = S.gs[g];
-      const double ri = M[col * LDK + i], rj = M[col * LDK + j];
-      M[col * LDK + i] = cg * ri - sn * rj;
-      M[col * LDK + j] = sn * ri + cg * rj;
+  if (S.ngiv > 0) {
+    if (tid < 2 * n) {
+      double* M = tid < n ? A : V;
+      const int col = tid % n;
+      bool bad = false;
+      for (int g = S.ngiv - 1; g >= 0; --g) {
+        const int i = S.gi[g], j = S.gj[g];
+        const double cg = S.gc[g], sn = S.gs[g];
+        const double ri = M[col * LDK + i], rj = M[col * LDK + j];
+        M[col * LDK + i] = cg * ri - sn * rj;
+        M[col * LDK + j] = sn * ri + cg * rj;
+        bad = bad || !isfinite(M[col * LDK + i]) || !isfinite(M[col * LDK + j]);
+      }
+      if (bad) S.fail = 1;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += CORE_THREADS)
-    if (!isfinite(A[idx / n * LDK + idx % n]) || !isfinite(V[idx / n * LDK + idx % n])) S.fail = 1;
-  __syncthreads();
   return !S.fail;
 }
 
@@ -475,21 +494,37 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // pb[k * sb].  Every load is issued (a lane whose row or column is out of
 // range, use_a / use_b false, or whose k is past K, reads k = 0 of a valid
 // pointer and passes zero), so the loop has no divergent branches; two
-// accumulators over alternate k-steps keep two products in flight.
+// accumulators over alternate k-steps keep two products in flight, and the
+// next eight k-steps' operands are loaded while these are multiplied.
 __device__ __forceinline__ d4_t mfma_tile(const double* pa, int sa, bool use_a, const double* pb,
                                           int sb, bool use_b, int K, int l) {
   d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
   const int kl = l >> 4;
-  for (int k0 = 0; k0 < K; k0 += 8) {
+  // operands of the k-steps k0 + kl and k0 + kl + 4 (zero past K)
+  auto load = [&](int k0, double& a0, double& b0, double& a1, double& b1) {
     const int ka = k0 + kl, kb = ka + 4;
     const bool va = ka < K, vb = kb < K;
     const int ia = va ? ka : 0, ib = vb ? kb : 0;
-    const double a0 = pa[ia * sa], b0 = pb[ia * sb];
-    const double a1 = pa[ib * sa], b1 = pb[ib * sb];
-    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(use_a && va ? a0 : 0.0, use_b && va ? b0 : 0.0, d0,
-                                              0, 0, 0);
-    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(use_a && vb ? a1 : 0.0, use_b && vb ? b1 : 0.0, d1,
-                                              0, 0, 0);
+    a0 = pa[ia * sa];
+    b0 = pb[ia * sb];
+    a1 = pa[ib * sa];
+    b1 = pb[ib * sb];
+    a0 = use_a && va ? a0 : 0.0;
+    b0 = use_b && va ? b0 : 0.0;
+    a1 = use_a && vb ? a1 : 0.0;
+    b1 = use_b && vb ? b1 : 0.0;
+  };
+  double a0, b0, a1, b1;
+  load(0, a0, b0, a1, b1);
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    double na0, nb0, na1, nb1;
+    load(k0 + 8, na0, nb0, na1, nb1);      // the next k-steps' loads overlap these products
+    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, d1, 0, 0, 0);
+    a0 = na0;
+    b0 = nb0;
+    a1 = na1;
+    b1 = nb1;
   }
   return d0 + d1;
 }
@@ -737,7 +772,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __shared__ double p2[RMAX], pyr[RMAX], pyn[RMAX], wn[RMAX], sgn[RMAX], ssig[RMAX], pvec[RMAX];
   __shared__ SecShared sec;
   __shared__ double sC[RMAX * RMAX];
-  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX], qB[RMAX], eB[RMAX];
+  __shared__ double wk[RMAX], urk[RMAX], sw[RMAX], qB[RMAX], eB[RMAX], isg[RMAX];
   __shared__ int perm[MMAX + 1];
   __shared__ int flag;
   __shared__ double sc[8];
@@ -1078,6 +1113,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
         pyn[k] = s * inv;
         wn[k] = sV[pj * LDK + r];
         sgn[k] = sd[pj];
+        isg[k] = inv;                           // 1 / sigma'_k
         wk[k] = s * inv * inv;                  // p_y,k / sigma'_k
         urk[k] = sA[pj * LDK + r] * inv;        // U_k(r, k)
       }
@@ -1143,7 +1179,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
           const int cr = c0 + 4 * v + (l >> 4);
           double out = 0.0;
           if (kb < rn) {
-            const double inv = 1.0 / sd[pk];
+            const double inv = isg[kb];
             const double urr = sA[pk * LDK + r];
             if (cr < meff) out = (d[v] - irho * urr * red[cr]) * inv;
             else if (cr == meff && grow) out = urr * irho * inv;
@@ -1226,7 +1262,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
         const int i = i0 + 4 * v + (l >> 4);
         if (i < rn && jb < rn) {
           st->C[jb * RMAX + i] = d[v];
-          st->At[jb * RMAX + i] = (sgn[i] * d[v] + pyn[i] * wn[jb]) / sgn[jb];
+          st->At[jb * RMAX + i] = (sgn[i] * d[v] + pyn[i] * wn[jb]) * isg[jb];
         }
       }
     }
