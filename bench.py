@@ -328,6 +328,15 @@ def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 
         R = U64 - U @ (U.T @ U64)
         smax = float(torch.linalg.eigvalsh(R.T @ R).max().clamp(min=0.0)) ** 0.5
         out["subspace_angle_rad_vs_f64"][b] = float(f"{math.asin(min(1.0, smax)):.3e}")
+        # per FP64 direction: the angle between it and the model's span, worst
+        # over the directions with sigma >= 1e-2 sigma_1 (well above BF16's
+        # per-entry rounding, 2^-9) and over all principal ones
+        sines = torch.linalg.norm(R, dim=0).clamp(max=1.0).cpu().numpy()
+        lvl = {}
+        for name, cut in (("sigma_ge_1e-2", 1e-2), ("sigma_ge_1e-3", 1e-3)):
+            sel = sig[:kk] >= cut * sig[0]
+            lvl[name] = float(f"{math.asin(float(sines[sel].max())):.3e}")
+        out.setdefault("direction_angle_rad_vs_f64_worst", {})[b] = lvl
         del U, G, R
     del U64
     torch.cuda.empty_cache()
