@@ -200,7 +200,12 @@ odmd_status odmd_autotune(int64_t n, int32_t r_max, odmd_dtype basis, odmd_dtype
  * On a chained handle (odmd_create, odmd_create_ex) later pairs must
  * chain: x_k must equal, element for element, the x_k1 of the previous
  * accepted update; otherwise the update is skipped and ODMD_ESEQ is
- * latched.  A general-pair handle (odmd_create_general) takes any pair.
+ * latched.  The device checks two fingerprints, both summed in the same
+ * fixed order by every pass of the handle: x.x, and a weighted sum with
+ * weights in [1, 2) hashed from the row index (a sign flip or a
+ * permutation of x changes it); a different x that matches both bit for
+ * bit is not detected.  A general-pair handle (odmd_create_general) takes
+ * any pair.
  * Asynchronous.  It may be captured into a HIP graph (stream capture on the
  * handle's stream): the graph then reads the same x_k, x_k1 buffers at
  * every replay, and from the capture on the handle sizes its passes for

@@ -792,7 +792,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   //    a pair is then bit-equal to y.y of the pair before it).  A thread's
   //    records are read RU at a time, the first RU with Q and C, so that
   //    their latencies overlap.
-  const int pwc = 2 * c.rb + 4, pw2 = pwc / 2;
+  const int pwc = 2 * c.rb + 6, pw2 = pwc / 2;
   constexpr int nslot = CORE_THREADS / (PW / 2);
   constexpr int RU = 10;
   const bool rth = tid < nslot * pw2;
@@ -800,7 +800,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const double2* __restrict__ rec = reinterpret_cast<const double2*>(c.partials);
   double2 rv[RU];
   int64_t macc0 = 0;
-  double yyprev0 = 0.0, tol0 = 0.0;
+  double yyprev0 = 0.0, yhprev0 = 0.0, tol0 = 0.0;
   double ax = 0.0, ay = 0.0;
   // records rsl + (ch RU + i) nslot; past nblk a valid record is read and
   // not added
@@ -845,6 +845,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (tid == 0) {
       macc0 = st->m_acc;
       yyprev0 = st->yy_prev;
+      yhprev0 = st->yh_prev;
       tol0 = st->tol;
     }
     if (sth) {
@@ -958,11 +959,14 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     py2 = add_half_pair(add_row_pair(row_sum(py2)));
     if (tid == 0) {
       const double ee = tot[P_EE], xx = tot[P_XX], ey = tot[P_EY], yy = tot[P_YY];
+      const double xh = tot[P_XH], yh = tot[P_YH];
       int skip = 0;
       if (!(isfinite(ee) && isfinite(xx) && isfinite(ey) && isfinite(yy) && isfinite(pp) &&
             isfinite(py2))) {
         skip = ST_NONFINITE;
-      } else if (!GENERAL && macc0 > 0 && xx != yyprev0) {
+      } else if (!GENERAL && macc0 > 0 && (xx != yyprev0 || xh != yhprev0)) {
+        // x must be the previous pair's y: both fingerprints, summed in the
+        // same fixed order by every pass of this stream, agree bit for bit
         skip = ST_SEQ;
       }
       double rho = sqrt(fmax(ee - pp, 0.0));
@@ -971,6 +975,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       sc[0] = rho;
       sc[1] = grow ? (ey - py2) / rho : 0.0;   // q^T y
       sc[2] = yy;
+      sc[3] = yh;
       si[0] = skip;
       si[1] = grow;
     }
@@ -1089,6 +1094,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       st->refold = 0;
       st->m_acc += 1;
       st->yy_prev = sc[2];
+      st->yh_prev = sc[3];
       st->last_rho = rho;
       st->sweeps = sweeps;
       st->eig_valid = 0;
@@ -1279,6 +1285,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     st->refold = mnew >= fold_limit(c, rn);
     st->m_acc += 1;
     st->yy_prev = sc[2];
+    st->yh_prev = sc[3];
     st->last_rho = rho;
     st->sweeps = sweeps;
     st->eig_valid = 0;

@@ -23,7 +23,7 @@ constexpr int RMAX = 64;          // rank cap
 constexpr int MMAX = RMAX + 1;    // core size (r + 1)
 constexpr int CMAX = 72;          // stored columns per tile, at most
 constexpr int FOLD_SLACK = 16;    // pending stored columns (beyond r, or r_max for the capacity) before a refold
-constexpr int PW = 2 * CMAX + 4;  // partial-sum record per workgroup
+constexpr int PW = 2 * CMAX + 6;  // partial-sum record per workgroup
 // Streaming-pass launch shape of a stream, fixed at creation (the
 // partition sets the order of the pass's sums, so it never changes for a
 // handle, batched or not):
@@ -56,6 +56,8 @@ constexpr int P_EE = 2 * CMAX;       // e . e
 constexpr int P_EY = 2 * CMAX + 1;   // e . y
 constexpr int P_XX = 2 * CMAX + 2;   // x . x
 constexpr int P_YY = 2 * CMAX + 3;   // y . y
+constexpr int P_XH = 2 * CMAX + 4;   // h . x  (row-hashed weights, see row_weight)
+constexpr int P_YH = 2 * CMAX + 5;   // h . y
 
 // latched status bits
 constexpr int ST_NONFINITE = 1;
@@ -77,7 +79,8 @@ struct DevState {
   double tol;     // effective tolerance
   double yy_prev; // y.y of the last accepted pair (chaining fingerprint)
   double last_rho;
-  double pad_[4];
+  double yh_prev; // h.y of the last accepted pair (second fingerprint)
+  double pad_[3];
   // host-visible copy of `status` (a word of the handle's mapped pinned
   // memory), rewritten by every kernel that latches a bit, so that the host
   // can read the latched status of finished work without a device call
@@ -103,6 +106,17 @@ struct DevState {
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 #ifdef __HIPCC__
+// Weight of global row i in the chaining fingerprint h . x: a multiplicative
+// hash of the index mapped to [1, 2) with 20 random bits (exact in FP64), so
+// that a sign flip or a permutation of x changes h . x where x . x does not.
+__device__ __forceinline__ double row_weight(int64_t i) {
+  uint32_t k = (uint32_t)i * 2654435761u;
+  k ^= k >> 15;
+  k *= 2246822519u;
+  k ^= k >> 13;
+  return 1.0 + (double)(k >> 12) * 0x1p-20;
+}
+
 // Latch status bits (one thread) and mirror the result to the host word.
 __device__ inline void latch_status(DevState* st, int bits) {
   st->status |= bits;

@@ -10,7 +10,7 @@ struct PassArgs {
   void* Us;             // stored basis S: 64-row tiles, column-major inside a tile
   const void* x;        // snapshot x_k (io type)
   const void* y;        // snapshot x_k+1 (io type)
-  double* partials;     // nblk records (stride PW) of 2 rb + 4 values
+  double* partials;     // nblk records (stride PW) of 2 rb + 6 values
   const DevState* st;
   int64_t n;
   int64_t units;        // (unused by the kernels; kept for the host)

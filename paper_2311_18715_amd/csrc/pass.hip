@@ -96,7 +96,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, l16 = lane & 15;
 
-  double accE[KK], accY[KK], sEE = 0.0, sEY = 0.0, sXX = 0.0, sYY = 0.0;
+  double accE[KK], accY[KK], sEE = 0.0, sEY = 0.0, sXX = 0.0, sYY = 0.0, sXH = 0.0, sYH = 0.0;
 #pragma unroll
   for (int kk = 0; kk < KK; ++kk) accE[kk] = accY[kk] = 0.0;
 
@@ -230,10 +230,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     if (q == 0) {
 #pragma unroll
       for (int j = 0; j < RPL; ++j) {
+        const double hw = row_weight(row0 + j);
         sEE = __builtin_fma(ed[j], ed[j], sEE);
         sEY = __builtin_fma(ed[j], yv[j], sEY);
         sXX = __builtin_fma(xv[j], xv[j], sXX);
         sYY = __builtin_fma(yv[j], yv[j], sYY);
+        sXH = __builtin_fma(hw, xv[j], sXH);
+        sYH = __builtin_fma(hw, yv[j], sYH);
       }
     }
 
@@ -290,8 +293,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   sEY = row_sum(sEY);
   sXX = row_sum(sXX);
   sYY = row_sum(sYY);
-  // record: [S^T e (RB) | S^T y (RB) | e.e e.y x.x y.y]
-  __shared__ double red[NWAVE][2 * RB + 4];
+  sXH = row_sum(sXH);
+  sYH = row_sum(sYH);
+  // record: [S^T e (RB) | S^T y (RB) | e.e e.y x.x y.y h.x h.y]
+  __shared__ double red[NWAVE][2 * RB + 6];
   if (l16 == 0) {
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
@@ -304,10 +309,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
     red[wave][2 * RB + 1] = sEY;
     red[wave][2 * RB + 2] = sXX;
     red[wave][2 * RB + 3] = sYY;
+    red[wave][2 * RB + 4] = sXH;
+    red[wave][2 * RB + 5] = sYH;
   }
   __syncthreads();
   double* __restrict__ out = p.partials + (int64_t)blk * PW;
-  for (int idx = threadIdx.x; idx < 2 * RB + 4; idx += NTH) {
+  for (int idx = threadIdx.x; idx < 2 * RB + 6; idx += NTH) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < NWAVE; ++w) t += red[w][idx];

@@ -202,6 +202,20 @@ def test_nonfinite_and_unchained_are_skipped():
     with pytest.raises(OdmdError) as e:
         g.sync()
     assert e.value.name == "ESEQ"
+    # equal norms, not the previous y: sign-flipped, two entries swapped,
+    # the entries reversed (x.x unchanged; the hashed fingerprint differs)
+    flip = -Xd[20]
+    swap = Xd[20].clone()
+    swap[[3, 700]] = swap[[700, 3]]
+    rev = torch.flip(Xd[20], dims=[0])
+    for x in (flip, swap, rev):
+        nx, n20 = float(x @ x), float(Xd[20] @ Xd[20])
+        assert abs(nx - n20) <= 1e-13 * n20
+        g.update(x, Xd[21])
+        with pytest.raises(OdmdError) as e:
+            g.sync()
+        assert e.value.name == "ESEQ"
+    np.testing.assert_array_equal(before["sigma"], g.state()["sigma"])
     # the stream resumes where it was and matches an oracle that skipped both
     o = O.OnlineDMD(1000, 10, 1e-8)
     for k in range(25):
