@@ -131,8 +131,9 @@ size_t odmd_state_bytes_general(int64_t n, int32_t r_max, odmd_dtype basis, odmd
  * the order of the pass's sums, so a handle keeps its shape for life and
  * two handles fed the same pairs give bitwise equal results exactly when
  * their shapes give the same workgroup count and size (with the 512-thread
- * size, BF16 bases and FP32 bases of n >= 2^21 read two rows per lane,
- * also fixed per handle).  Results of any two shapes agree to rounding.
+ * size, BF16 bases and FP32 bases of n >= 1,482,911, about 2^20.5, read
+ * two rows per lane, also fixed per handle).  Results of any two shapes
+ * agree to rounding.
  *
  * odmd_default_shape: the shape odmd_create_ex / odmd_create_general use
  * for n (512 x 256 rows, at most 256 workgroups, for n >= 131072; else

@@ -105,11 +105,14 @@ int col_bucket(int cols) { return (cols + 7) / 8 * 8; }
 
 // Two rows per lane in the 512-thread pass: always for BF16 storage (half
 // lines instead of quarter lines per load), for FP32 storage only from
-// 2^21 rows on, where a single HBM-bound stream gains (whole lines) and the
+// about 2^20.5 rows on (1,482,911 = the first n whose nearest power of two
+// in log scale is 2^21, so that a tuned-shape bucket never mixes the two
+// variants), where a single HBM-bound stream gains (whole lines) and the
 // higher register count no longer costs batches of mid-size streams.
+constexpr int64_t F32_WIDE_ROWS_MIN_N = 1482911;
 int wide_rows(odmd_dtype basis, int threads, int64_t n) {
   if (threads != PASS_WIDE.threads) return 0;
-  return basis == ODMD_BF16 || (basis == ODMD_F32 && n >= (int64_t(1) << 21));
+  return basis == ODMD_BF16 || (basis == ODMD_F32 && n >= F32_WIDE_ROWS_MIN_N);
 }
 
 // Stored basis: 64-row tiles, column-major inside a tile, fold_capacity(r_max)

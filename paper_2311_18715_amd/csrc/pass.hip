@@ -156,8 +156,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& p, const int blk) {
   const int ca = threadIdx.x;
   const double a_c = (ca < 4 * KK && ca < m) ? st->a[ca] : 0.0;
   // (unconditional, as in the loop: a wave without a unit of its own
-  // re-reads the workgroup's first one, u0 < u1 since there are at least as
-  // many units as workgroups)
+  // re-reads unit u0, which is in range, u0 < units, for every workgroup,
+  // also one that gets no unit at all: with 32-row units there can be
+  // fewer units than workgroups, u0 == u1 there, and its loop is empty)
   int64_t u = u0 + __builtin_amdgcn_readfirstlane(wave);
   load_unit(u < u1 ? u : u0, A, xv, yv);
   if (ca < 4 * KK) sa[ca] = a_c;

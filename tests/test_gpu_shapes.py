@@ -113,3 +113,49 @@ def test_shape_by_objective_uses_the_shipped_table():
         info = g.info()
         assert (info.threads, info.nblocks) == (t, min(-(-n // rpb), cap))
         g.close()
+
+
+def test_fp32_two_rows_per_lane_matches_one_row():
+    """FP32 storage at a ragged n past the two-rows-per-lane threshold: the
+    512-thread shape (two rows per lane, whole 128-byte lines) against the
+    256-thread shape (one row per lane) on the same pairs.  Different sum
+    orders, so the two agree to FP32-storage rounding: equal rank, sigma
+    within 1e-6 sigma_1, eigenvalues within 2e-5 of each other and 1e-4 of
+    the planted ones (80 pairs: with 40, the FP64 oracle itself is 4e-3 off
+    on these FP32-rounded snapshots), rollouts within 1e-5.  A batch of two two-row handles equals their
+    own launches bit for bit."""
+    n, rank, r_max, steps = (1 << 21) + 17, 9, 16, 80
+    gen = synth.DevicePlanted(torch, n, rank, seed=2718, dtype=torch.float32)
+    X = gen.chunk(0, steps + 1)
+    two = ODMD(n, r_max, 1e-6, basis="f32")
+    one = ODMD(n, r_max, 1e-6, basis="f32", shape=(256, 512, 512))
+    assert two.info().threads == 512 and one.info().threads == 256
+    for k in range(steps):
+        two.update(X[k], X[k + 1])
+        one.update(X[k], X[k + 1])
+    st, so = two.state(), one.state()
+    assert st["r"] == so["r"] == rank
+    np.testing.assert_allclose(st["sigma"], so["sigma"], rtol=0, atol=1e-6 * so["sigma"][0])
+    lams = [g.eigs(vectors=False)[0] for g in (two, one)]
+    for lam in lams:
+        got = O.match_eigs(gen.planted, lam)
+        assert np.max(np.abs(got - gen.planted) / np.abs(gen.planted)) < 1e-4
+    d = np.abs(O.match_eigs(lams[1], lams[0]) - lams[1]) / np.abs(lams[1])
+    assert d.max() < 2e-5, d.max()
+    pt, po = two.predict(20), one.predict(20)
+    err = (torch.linalg.norm((pt - po).double(), dim=1) / torch.linalg.norm(po.double(), dim=1)).max()
+    assert float(err) < 1e-5, float(err)
+    # batched two-row launches equal the handles' own launches
+    A = [ODMD(n, r_max, 1e-6, basis="f32") for _ in range(2)]
+    C = [ODMD(n, r_max, 1e-6, basis="f32") for _ in range(2)]
+    for k in range(12):
+        update_batch(A, [X[k], X[k + 1]], [X[k + 1], X[k + 2]])
+        C[0].update(X[k], X[k + 1])
+        C[1].update(X[k + 1], X[k + 2])
+    for a, c in zip(A, C):
+        sa, sc = a.state(), c.state()
+        for key in ("sigma", "atilde", "p_y", "C", "w"):
+            assert np.array_equal(sa[key], sc[key]), key
+        assert torch.equal(a.basis_matrix(), c.basis_matrix())
+    for g in [two, one] + A + C:
+        g.close()
