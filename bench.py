@@ -79,23 +79,46 @@ def measured_traffic():
     return int(m_bytes.group(1))
 
 
-def cpu_baseline(X, seconds: float = 15.0, threads_limit=None):
+def host_info() -> dict:
+    """The host CPU model and the BLAS library NumPy calls (threadpoolctl)."""
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if libs:
+            blas = f"{libs[0].get('internal_api')} {libs[0].get('version')}"
+    except Exception:
+        pass
+    return {"cpu_model": cpu, "blas": blas, "numpy": np.__version__}
+
+
+def cpu_baseline(X, seconds: float = 15.0, threads_limit=None, r_max: int = R_MAX, tol: float = TOL,
+                 warm_max: int = 200):
     """The FP64 oracle on this host: warm up to the saturated rank, then time
     as many updates as fit in about `seconds` (at least 5).  threads_limit
     caps the BLAS threads (None: the library's default)."""
     if threads_limit is not None:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=threads_limit):
-            return cpu_baseline(X, seconds)
+            return cpu_baseline(X, seconds, None, r_max, tol, warm_max)
     from oracle import odmd_oracle as O
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    o = O.OnlineDMD(X.shape[0], R_MAX, TOL)
+    o = O.OnlineDMD(X.shape[0], r_max, tol)
     k = 0
-    while o.r < R_MAX and k < 200:
+    while o.r < r_max and k < warm_max:
         o.update(X[:, k], X[:, k + 1])
         k += 1
     k0, t0 = k, time.perf_counter()
@@ -106,8 +129,20 @@ def cpu_baseline(X, seconds: float = 15.0, threads_limit=None):
             break
     dt = time.perf_counter() - t0
     return {"value": (k - k0) / dt, "unit": "updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{k - k0} consecutive updates of the same n={X.shape[0]} stream at the "
-                      f"saturated rank {R_MAX} (after {k0} warm-up updates), FP64 NumPy/LAPACK"}
+            "sample": f"{k - k0} consecutive updates of the same n={X.shape[0]} stream at "
+                      f"rank {o.r} (r_max {r_max}, after {k0} warm-up updates), FP64 NumPy/LAPACK",
+            **host_info()}
+
+
+def cpu_baseline_configs() -> dict:
+    """Bounded oracle sample of the small single-stream workload: the
+    planted n = 4096 stream (rank 6, r_max 20; the n = 6,000,000 precision
+    stream's sample is taken in its own section, from the snapshots the
+    device generates there)."""
+    from paper_2311_18715_amd import synth
+    s = synth.planted_small()
+    X = s.snapshots(0, 400)
+    return {"planted_n4096": cpu_baseline(X, seconds=4.0, r_max=20, tol=1e-8, warm_max=20)}
 
 
 # (ii) S independent n = 160k streams through the batched update
@@ -248,7 +283,8 @@ def hybrid_section(torch):
                              "workload, context only"}
 
 
-def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 500):
+def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 500,
+                      cpu: bool = False):
     """The precision form at full size: the wake generator on a 3000 x 1000
     grid (n = 6,000,000; mean flow, 10 shedding harmonics, 10 transients:
     real rank 41), noise 1e-5, r_max = 64, 1000 snapshots, run with FP64,
@@ -364,6 +400,12 @@ def precision_section(torch, snaps: int = 1000, chunk: int = 50, rollout: int = 
     for g in models.values():
         g.close()
     torch.cuda.empty_cache()
+    if cpu:
+        # the oracle on the first snapshots of the same stream (copied from
+        # the device generator): a short warm-up, then a few timed updates
+        Xh = snapshots(0, 16).T.contiguous().cpu().numpy()
+        out["cpu_baseline_oracle"] = cpu_baseline(Xh, seconds=5.0, r_max=64, tol=1e-8, warm_max=8)
+        del Xh
     return out
 
 
@@ -971,7 +1013,7 @@ def main():
         torch.cuda.empty_cache()
         result["prediction_n585k"] = prediction_section(torch)
         torch.cuda.empty_cache()
-        result["precision_n6m"] = precision_section(torch)
+        result["precision_n6m"] = precision_section(torch, cpu=not args.no_cpu_baseline)
     if args.calibrate_copy > 0:
         a = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -982,6 +1024,7 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(X)
         result["cpu_baseline_1thread"] = cpu_baseline(X, seconds=8.0, threads_limit=1)
+        result["cpu_baseline_other_configs"] = cpu_baseline_configs()
     print(json.dumps(result), flush=True)
 
 
