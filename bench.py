@@ -56,7 +56,7 @@ def make_stream():
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_pass_f64_r40_wake_n160k.md")
-PASS_SOURCES = ("pass.hip", "pass.h", "odmd_internal.h", "storage.h", "xlane.h")
+PASS_SOURCES = ("pass.hip", "pass_body.h", "pass.h", "odmd_internal.h", "storage.h", "xlane.h")
 
 
 def measured_traffic():

@@ -269,10 +269,11 @@ odmd_status odmd_update_batch_noalloc(odmd_t* hs, const void* const* xs, const v
  *   device buffers between launches, keeping each pair chained (e.g. two
  *   plans over two buffers, used alternately: (A, B), then (B, A)).  The
  *   plan copies its descriptor tables to the device here (synchronous).
- *   Every pass of a plan is sized for the handle's full stored-column
- *   capacity, since a graph cannot follow the live count; from then on
- *   the handles size their other updates the same way (the host no longer
- *   knows the count either).  Results equal odmd_update_batch's bit for
+ *   A graph cannot follow the live stored-column count from the host, so
+ *   each workgroup of a plan's passes reads its stream's count on the
+ *   device and runs that count's live-column variant; from then on the
+ *   handles size their own updates for the full capacity (the host no
+ *   longer knows the count).  Results equal odmd_update_batch's bit for
  *   bit.  *plan is set to NULL on error; ODMD_EINVAL for invalid
  *   arguments, ODMD_ENOMEM if the tables or side streams cannot be made.
  * odmd_plan_launch: enqueue one step on the handles' stream (kernel

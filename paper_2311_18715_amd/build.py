@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libodmd.so")
-SOURCES = ["pass.hip", "gram.hip", "core.hip", "eig.hip", "combine.hip", "odmd_api.hip", "autotune.hip"]
+SOURCES = ["pass.hip", "pass_live.hip", "gram.hip", "core.hip", "eig.hip", "combine.hip", "odmd_api.hip", "autotune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -792,7 +792,11 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   //    a pair is then bit-equal to y.y of the pair before it).  A thread's
   //    records are read RU at a time, the first RU with Q and C, so that
   //    their latencies overlap.
-  const int pwc = 2 * c.rb + 6, pw2 = pwc / 2;
+  // the record length the pass wrote: its bucket, given by the launch or,
+  // for passes that chose it on the device (c.rb = -kb), the variant of the
+  // m the pass read (the pass leaves m as it found it)
+  const int rbk = c.rb > 0 ? c.rb : live_variant(m, -c.rb);
+  const int pwc = 2 * rbk + 6, pw2 = pwc / 2;
   constexpr int nslot = CORE_THREADS / (PW / 2);
   constexpr int RU = 10;
   const bool rth = tid < nslot * pw2;
@@ -876,7 +880,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     if (tid < pwc) {
       double t = 0.0;
       for (int sl = 0; sl < nslot; ++sl) t += sV[sl * pwc + tid];
-      const int rb = c.rb;
+      const int rb = rbk;
       const int at = tid < rb ? P_SUE + tid : (tid < 2 * rb ? P_SUY + (tid - rb) : P_EE + (tid - 2 * rb));
       tot[at] = t;
     }

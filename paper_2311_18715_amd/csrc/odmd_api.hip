@@ -1152,8 +1152,9 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
   if (!p) return ODMD_ENOMEM;
   p->device = hs[0]->device;
   p->stream = hs[0]->stream;
-  // the same grouping and order as a batched update, with every pass sized
-  // for the full stored-column capacity
+  // grouped like a batched update by (launch shape, rows per lane, storage
+  // type, capacity); each workgroup chooses its live-column variant on the
+  // device from the stream's m (the host cannot follow m across replays)
   std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> groups;
   for (int32_t i = 0; i < count; ++i)
     groups[{hs[i]->threads, hs[i]->rows2, (int)hs[i]->basis, hs[i]->ct}].push_back(i);
@@ -1199,7 +1200,7 @@ odmd_status odmd_plan_create(odmd_t* hs, const void* const* xs, const void* cons
     c.nblk = h->nblk;
     c.r_max = h->r_max;
     c.jacobi_only = h->jacobi_only;
-    c.rb = h->ct;
+    c.rb = -h->ct;        // the pass's variant follows m on the device
     c.ct = h->ct;
     c.fold_slack = fold_slack(h);
     c.grec = h->grec;
@@ -1233,14 +1234,15 @@ odmd_status odmd_plan_launch(odmd_plan_t p) {
   const PassDesc* dpd = static_cast<const PassDesc*>(p->dev);
   if (p->nside == 0) {
     const odmd_plan_s::Launch& L = p->launches[0];
-    HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb, p->stream));
+    HIP_OK(launch_pass_batch_live(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb,
+                                  p->stream));
   } else {
     HIP_OK(hipEventRecord(p->fork, p->stream));
     for (int i = 0; i < p->nside; ++i) HIP_OK(hipStreamWaitEvent(p->side[i], p->fork, 0));
     for (size_t i = 0; i < p->launches.size(); ++i) {
       const odmd_plan_s::Launch& L = p->launches[i];
-      HIP_OK(launch_pass_batch(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb,
-                               p->side[i % p->nside]));
+      HIP_OK(launch_pass_batch_live(dpd + L.first, L.nd, L.nblocks, L.threads, L.rows2, L.basis, L.rb,
+                                    p->side[i % p->nside]));
     }
     for (int i = 0; i < p->nside; ++i) {
       HIP_OK(hipEventRecord(p->join[i], p->side[i]));

@@ -124,6 +124,18 @@ __device__ inline void latch_status(DevState* st, int bits) {
 }
 #endif
 
+// The live-column bucket of m stored columns (the pass is compiled for
+// buckets 8, 16, ..., 72 and reads the first bucket >= m columns), as a
+// batched pass chooses it on the device for a stream of capacity kb >= m.
+inline
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+int live_variant(int m, int kb) {
+  const int b = m <= 8 ? 8 : (m + 7) / 8 * 8;
+  return b < kb ? b : kb;
+}
+
 // stored-column capacity of a stream with rank cap r_max (multiple of 8)
 inline int fold_capacity(int r_max) {
   const int c = (r_max + FOLD_SLACK + 7) / 8 * 8;

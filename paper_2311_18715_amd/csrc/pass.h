@@ -48,6 +48,11 @@ struct PassDesc {
 // threads: the launch shape's workgroup size, common to the streams of d
 hipError_t launch_pass_batch(const PassDesc* d, int nd, int nblocks, int threads, int rows2, int basis,
                              int rb, hipStream_t s);
+// The same, each workgroup running the live bucket of its stream's m, read
+// on the device (live_variant; plans and graphs): one kernel per capacity
+// kb of the streams of d; the core then takes rb = -kb.
+hipError_t launch_pass_batch_live(const PassDesc* d, int nd, int nblocks, int threads, int rows2,
+                                  int basis, int kb, hipStream_t s);
 
 // Gram matrix of a BF16 basis after a refold (gram.hip): per-workgroup
 // records of the 16x16 block pairs I <= J of the 64 columns
@@ -77,7 +82,8 @@ struct CoreArgs {
   int nblk;
   int r_max;
   int jacobi_only;      // skip the secular solver (diagnostics)
-  int rb;               // live-column bucket of the pass (compact partial records)
+  int rb;               // live-column bucket of the pass (compact partial records);
+                        // -kb: the pass chose it on the device, live_variant(m, kb)
   int ct;               // stored-column capacity of the stream
   int fold_slack;       // refold once the stored columns reach r' + fold_slack
                         // (or the capacity); 0: only at the capacity
