@@ -107,8 +107,12 @@ int col_bucket(int cols) { return (cols + 7) / 8 * 8; }
 // lines instead of quarter lines per load), for FP32 storage only from
 // about 2^20.5 rows on (1,482,911 = the first n whose nearest power of two
 // in log scale is 2^21, so that a tuned-shape bucket never mixes the two
-// variants), where a single HBM-bound stream gains (whole lines) and the
-// higher register count no longer costs batches of mid-size streams.
+// variants).  A single HBM-bound stream gains (whole lines: the n = 6M
+// FP32 update 521 -> 481 us), while the higher register count costs
+// batches: at n = 2^21, r_max 16, a 16-stream batch step went from 874 to
+// 941 us with the 512-thread shape (the tuned table picks each bucket's
+// shape with the variant in effect); below this size, where the batched
+// mixes live, one row per lane stays.
 constexpr int64_t F32_WIDE_ROWS_MIN_N = 1482911;
 int wide_rows(odmd_dtype basis, int threads, int64_t n) {
   if (threads != PASS_WIDE.threads) return 0;
