@@ -157,9 +157,10 @@ __device__ __forceinline__ double lam_minus_d(const SecShared& S, int i, double 
 }
 
 // Returns true on success; fills A (columns U_k * sigma'), V (V_k), column
-// order arbitrary (the caller sorts by column norm).
+// order arbitrary (the caller sorts by column norm), and the norms of A's
+// columns into sdo (norms_ok: no tied-pole rotation touched them after).
 __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* sig, const double* pv, double rho,
-                            int r, SecShared& S) {
+                            int r, SecShared& S, double* sdo, bool& norms_ok) {
   const int tid = threadIdx.x;
   const int n = r + 1;
 
@@ -432,6 +433,7 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
     const double fa = sqrt(S.rK[i] * S.rK[i] + S.mu[i]) / sqrt(sa);
     const double fv = 1.0 / sqrt(sv);
     bool bad = false;
+    double sn = 0.0;
 #pragma unroll
     for (int m = 0; m < SEC_TERMS; ++m) {
       const int jj = ql + 16 * m;
@@ -440,9 +442,12 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
         const double a = ea[m] * fa, v = ev[m] * fv;
         A[i * LDK + row] = a;
         V[i * LDK + row] = v;
+        sn = __builtin_fma(a, a, sn);
         bad = bad || !isfinite(a) || !isfinite(v);
       }
     }
+    sn = row_sum(sn);
+    if (ql == 0) sdo[i] = sqrt(sn);          // the column norm of what A holds
     for (int t = ql; t < S.ndef; t += 16) {
       A[i * LDK + S.dflist[t]] = 0.0;
       V[i * LDK + S.dflist[t]] = 0.0;
@@ -450,6 +455,7 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
     if (bad) S.fail = 1;
   }
   // deflated pairs: (d_j, e_j, e_j)
+  for (int t = tid; t < S.ndef; t += CORE_THREADS) sdo[nd + t] = fabs(sig[S.dflist[t]]);
   for (int idx = tid; idx < S.ndef * n; idx += CORE_THREADS) {
     const int t = idx / n, row = idx % n;
     const int j = S.dflist[t], col = nd + t;
@@ -457,7 +463,9 @@ __device__ __forceinline__ bool secular_svd(double* A, double* V, const double* 
     V[col * LDK + row] = row == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  // undo the tied-pole rotations on the rows of U_k and V_k
+  // undo the tied-pole rotations on the rows of U_k and V_k (the caller
+  // then takes the column norms again)
+  norms_ok = S.ngiv == 0;
   if (S.ngiv > 0) {
     if (tid < 2 * n) {
       double* M = tid < n ? A : V;
@@ -947,6 +955,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       const int c0 = idx / RMAX, j = idx % RMAX;
       sQ[c0 * LDQ + j] = (c0 == j && j < r) ? 1.0 : 0.0;
     }
+    __syncthreads();                   // step 3's phase reads Q
   }
   const int meff = refolded ? r : m;   // stored columns U is built from; e sits in column meff
   // a BF16 basis just refolded: carry the model over to the orthonormal
@@ -955,7 +964,23 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   if (gfix) gram_fix(c, r, sA, sV, sQ, pvec, p2, pyr);
 
   // 3. checks, residual norm, growth test (|p2|^2 and p2 . U^T y summed
-  //    across the first wavefront, one entry per lane)
+  //    across the first wavefront, one entry per lane); in the same phase
+  //    the second wavefront forms the core's p = p1 + p2 (step 4) and the
+  //    rest (Q p2)[c] for the rotation (step 8) into red, one quarter-wave
+  //    per row (a skipped update uses neither)
+  if (tid >= 64 && tid < 128) {
+    const int j = tid - 64;
+    if (j < r) pvec[j] += p2[j];           // sigma and p1 were staged with Q
+  } else if (tid >= 128) {
+    const int q0 = (tid - 128) >> 4, l16 = tid & 15;
+    for (int row = q0; row < CMAX; row += (CORE_THREADS - 128) / 16) {
+      double t = 0.0;
+      if (row < m || refolded)
+        for (int j = l16; j < r; j += 16) t += sQ[row * LDQ + j] * p2[j];
+      t = row_sum(t);
+      if (l16 == 0) red[row] = t;
+    }
+  }
   if (tid < 64) {
     double pp = tid < r ? p2[tid] * p2[tid] : 0.0;
     double py2 = tid < r ? p2[tid] * pyr[tid] : 0.0;
@@ -1024,10 +1049,9 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   const double rho = sc[0], qy = sc[1];
 
   // 4. core K = [[diag(sigma), p], [0, rho]], p = p1 + p2 with p1 the
-  //    cached p_y (chained pairs) or U^T x from the projection sweep
+  //    cached p_y (chained pairs) or U^T x from the projection sweep (p was
+  //    formed in the phase of step 3)
   const int M = r + 1;
-  if (tid < r) pvec[tid] += p2[tid];   // sigma and p1 were staged with Q
-  __syncthreads();
   // general pairs: q^T B = (e^T B - p2^T G) / rho with G = U^T B (in sC,
   // G(i, j) at sC[j * RMAX + i]), from the stored residual e = x - U p1
   // itself (no cancellation between x^T B and p^T G); zero when no
@@ -1040,6 +1064,7 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
 
   // 5. SVD of the core: secular equation, one-sided Jacobi if that fails
   int sweeps = 0;
+  bool have_norms = false;               // the secular solver left the column norms in sd
   if (gfix) {
     // K = [[M^1/2 diag(sigma), p], [0, rho]]: M^1/2 is in sA already
     for (int idx = tid; idx < M * M; idx += CORE_THREADS) {
@@ -1050,7 +1075,8 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
     __syncthreads();
     sweeps = jacobi_sweeps(sA, sV, sd, M, &flag);
-  } else if (c.jacobi_only || !secular_svd(sA, sV, ssig, pvec, rho, r, sec)) {
+  } else if (c.jacobi_only || !secular_svd(sA, sV, ssig, pvec, rho, r, sec, sd, have_norms)) {
+    have_norms = false;
     for (int idx = tid; idx < M * M; idx += CORE_THREADS) {
       const int i = idx % M, j = idx / M;
       double v;
@@ -1067,13 +1093,15 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   //    (one 16-lane quarter-wave per column for the norm and for the rank;
   //    M = r + 1 may exceed the 64 quarter-waves)
   const int qcl = tid & 15;
-  for (int col = tid >> 4; col < M; col += CORE_THREADS / 16) {
-    double s = 0.0;
-    for (int i = qcl; i < M; i += 16) s = __builtin_fma(sA[col * LDK + i], sA[col * LDK + i], s);
-    s = row_sum(s);
-    if (qcl == 0) sd[col] = sqrt(s);
+  if (!have_norms) {                       // uniform
+    for (int col = tid >> 4; col < M; col += CORE_THREADS / 16) {
+      double s = 0.0;
+      for (int i = qcl; i < M; i += 16) s = __builtin_fma(sA[col * LDK + i], sA[col * LDK + i], s);
+      s = row_sum(s);
+      if (qcl == 0) sd[col] = sqrt(s);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int col = tid >> 4; col < M; col += CORE_THREADS / 16) {
     const double me = sd[col];
     double rank = 0.0;
@@ -1140,28 +1168,20 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   //    with U'[i, k] = sA[perm[k] * LDK + i].
   const double irho = grow ? 1.0 / rho : 0.0;
   const int mnew = meff + grow;
-  // (Q p2)[c] into red, G p_y into pvec (pvec is free after the SVD; the
-  // next pass's a needs it): one 16-lane quarter-wave per entry
+  // G p_y into pvec (pvec is free after the SVD; the next pass's a needs
+  // it; (Q p2)[c] is in red since step 3): one 16-lane quarter-wave per entry
   const int qw = tid >> 4, ql = tid & 15;
   {
     double bs = 0.0;                       // g . p_y up to 1/rho: U_k(r, :) p_y
     for (int k = ql; k < rn; k += 16) bs += urk[k] * pyn[k];
     const double bsum = row_sum(bs);
-    for (int row = qw; row < CMAX + RMAX; row += CORE_THREADS / 16) {
+    for (int j = qw; j < RMAX; j += CORE_THREADS / 16) {
+      // (G p_y)_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
       double t = 0.0;
-      if (row < CMAX) {
-        if (row < m || refolded)
-          for (int j = ql; j < r; j += 16) t += sQ[row * LDQ + j] * p2[j];
-        t = row_sum(t);
-        if (ql == 0) red[row] = t;
-      } else {
-        // (G p_y)_j = sum_k U_k(j,k) p_y,k - (p2_j / rho) sum_k U_k(r,k) p_y,k
-        const int j = row - CMAX;
-        if (j < r)
-          for (int k = ql; k < rn; k += 16) t += sA[perm[k] * LDK + j] * wk[k];
-        t = row_sum(t);
-        if (ql == 0) pvec[j] = j < r ? t - p2[j] * irho * bsum : 0.0;
-      }
+      if (j < r)
+        for (int k = ql; k < rn; k += 16) t += sA[perm[k] * LDK + j] * wk[k];
+      t = row_sum(t);
+      if (ql == 0) pvec[j] = j < r ? t - p2[j] * irho * bsum : 0.0;
     }
   }
   __syncthreads();
@@ -1201,16 +1221,26 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
     }
   }
   // next first-projection coefficients a = Q' p_y (rows < meff: Q (G p_y);
-  // row meff: g . p_y), one quarter-wave per entry
-  for (int row = qw; row < CMAX; row += CORE_THREADS / 16) {
-    double t = 0.0;
-    if (row < meff) {
-      for (int j = ql; j < r; j += 16) t += sQ[row * LDQ + j] * pvec[j];
-    } else if (row == meff && grow) {
-      for (int k = ql; k < rn; k += 16) t += urk[k] * pyn[k];
+  // row meff: g . p_y), one quarter-wave per entry: by the wavefronts that
+  // hold no Q' tile, while the others run their matrix-core tiles, or by
+  // all of them after the tiles when every wavefront holds one
+  {
+    const int wv = tid >> 6;
+    const int idle = ntile < CORE_THREADS / 64 ? CORE_THREADS / 64 - ntile : 0;
+    const bool mine = idle > 0 ? wv >= ntile : true;
+    const int q0 = idle > 0 ? qw - 4 * ntile : qw, nq = idle > 0 ? 4 * idle : CORE_THREADS / 16;
+    if (mine) {
+      for (int row = q0; row < CMAX; row += nq) {
+        double t = 0.0;
+        if (row < meff) {
+          for (int j = ql; j < r; j += 16) t += sQ[row * LDQ + j] * pvec[j];
+        } else if (row == meff && grow) {
+          for (int k = ql; k < rn; k += 16) t += urk[k] * pyn[k];
+        }
+        t = row_sum(t);
+        if (ql == 0) st->a[row] = row == meff && grow ? t * irho : t;
+      }
     }
-    t = row_sum(t);
-    if (ql == 0) st->a[row] = row == meff && grow ? t * irho : t;
   }
   __syncthreads();   // every thread is done reading Q: write Q' in place
   {
