@@ -47,6 +47,11 @@ NX, NY, SNAPS, R_MAX, TOL, NOISE = 400, 200, 2000, 40, 1e-8, 1e-6
 ROLLOUT = 500
 PEAK_HBM_GBPS = 8000.0
 STEADY_FROM = 100          # updates after which the rank has saturated at r_max
+# timed updates carry timing events at this stride (coprime to the refold
+# period of 16 updates, so every phase of the refold cycle is sampled): a
+# pair of events around each of an update's two kernels costs about a fifth
+# of the update's time on this GPU
+PROFILE_STRIDE = 7
 
 
 def make_stream():
@@ -919,8 +924,9 @@ def main():
 
     def one_step(g, profile):
         for k in range(m):
-            if profile and k == STEADY_FROM:
-                g.profile(cap)
+            j = k - STEADY_FROM
+            if profile and j >= 0 and j % PROFILE_STRIDE < 2:
+                g.profile(cap if j % PROFILE_STRIDE == 0 else 0)
             g.update(Xd[k], Xd[k + 1])
         g.profile(0)
         g.eigs(vectors=False)           # synchronising
@@ -990,6 +996,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBPS, 4),
             "bytes_per_launch": bytes_upd,
             "launches_timed": int(pass_ms.size),
+            "launches_sampled": f"every {PROFILE_STRIDE}th update of the timed steps from update "
+                                f"{STEADY_FROM} on (HIP events on the update's stream)",
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },

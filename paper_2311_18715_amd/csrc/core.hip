@@ -504,8 +504,9 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // pointer and passes zero), so the loop has no divergent branches; two
 // accumulators over alternate k-steps keep two products in flight, and the
 // next eight k-steps' operands are loaded while these are multiplied.
-__device__ __forceinline__ d4_t mfma_tile(const double* pa, int sa, bool use_a, const double* pb,
-                                          int sb, bool use_b, int K, int l) {
+template <int NB>
+__device__ __forceinline__ d4_t mfma_tile_nb(const double* pa, int sa, bool use_a, const double* pb, int sb,
+                                             bool use_b, int K, int l) {
   d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
   const int kl = l >> 4;
   // operands of the k-steps k0 + kl and k0 + kl + 4 (zero past K)
@@ -524,9 +525,10 @@ __device__ __forceinline__ d4_t mfma_tile(const double* pa, int sa, bool use_a, 
   };
   double a0, b0, a1, b1;
   load(0, a0, b0, a1, b1);
-  for (int k0 = 0; k0 < K; k0 += 8) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
     double na0, nb0, na1, nb1;
-    load(k0 + 8, na0, nb0, na1, nb1);      // the next k-steps' loads overlap these products
+    load(8 * j + 8, na0, nb0, na1, nb1);   // the next k-steps' loads overlap these products
     d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, d0, 0, 0, 0);
     d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, d1, 0, 0, 0);
     a0 = na0;
@@ -535,6 +537,63 @@ __device__ __forceinline__ d4_t mfma_tile(const double* pa, int sa, bool use_a, 
     b1 = nb1;
   }
   return d0 + d1;
+}
+
+// The same product with a run-time loop over the blocks (fewer registers;
+// the BF16 Gram correction's rarely taken products)
+__device__ __forceinline__ d4_t mfma_tile_loop(const double* pa, int sa, bool use_a, const double* pb, int sb,
+                                               bool use_b, int K, int l) {
+  d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
+  const int kl = l >> 4;
+  auto load = [&](int k0, double& a0, double& b0, double& a1, double& b1) {
+    const int ka = k0 + kl, kb = ka + 4;
+    const bool va = ka < K, vb = kb < K;
+    const int ia = va ? ka : 0, ib = vb ? kb : 0;
+    a0 = pa[ia * sa];
+    b0 = pb[ia * sb];
+    a1 = pa[ib * sa];
+    b1 = pb[ib * sb];
+    a0 = use_a && va ? a0 : 0.0;
+    b0 = use_b && va ? b0 : 0.0;
+    a1 = use_a && vb ? a1 : 0.0;
+    b1 = use_b && vb ? b1 : 0.0;
+  };
+  double a0, b0, a1, b1;
+  load(0, a0, b0, a1, b1);
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    double na0, nb0, na1, nb1;
+    load(k0 + 8, na0, nb0, na1, nb1);
+    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, d1, 0, 0, 0);
+    a0 = na0;
+    b0 = nb0;
+    a1 = na1;
+    b1 = nb1;
+  }
+  return d0 + d1;
+}
+
+// The number of 8-step blocks is dispatched to a straight-line product (one
+// uniform branch): a loop over a run-time K took about three times the
+// matrix-core time of its products in isolation (2100 against 628 cycles for
+// K = 40 on one wavefront), its load waits and branches breaking the
+// pipelining.  The products and their order are those of the loop, bit for
+// bit.
+__device__ __forceinline__ d4_t mfma_tile(const double* pa, int sa, bool use_a, const double* pb,
+                                          int sb, bool use_b, int K, int l) {
+  static_assert(MMAX <= 72, "K of the core's products is at most 72");
+  switch ((K + 7) >> 3) {
+    case 1: return mfma_tile_nb<1>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 2: return mfma_tile_nb<2>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 3: return mfma_tile_nb<3>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 4: return mfma_tile_nb<4>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 5: return mfma_tile_nb<5>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 6: return mfma_tile_nb<6>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 7: return mfma_tile_nb<7>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 8: return mfma_tile_nb<8>(pa, sa, use_a, pb, sb, use_b, K, l);
+    case 9: return mfma_tile_nb<9>(pa, sa, use_a, pb, sb, use_b, K, l);
+    default: return d4_t{0.0, 0.0, 0.0, 0.0};   // K <= 0
+  }
 }
 
 // General pairs (B = Y W held as T R): the right-factor bookkeeping of one
@@ -708,7 +767,7 @@ __device__ void gram_fix(const CoreArgs& c, int r, double* sA, double* sV, doubl
   for (int it = 0; it < 12; ++it) {
     int far = 0;
     if (tile_live) {
-      const d4_t d = mfma_tile(sV + (ra < r ? ra : 0), LDK, ra < r, sA + (cb < r ? cb : 0) * LDK, 1,
+      const d4_t d = mfma_tile_loop(sV + (ra < r ? ra : 0), LDK, ra < r, sA + (cb < r ? cb : 0) * LDK, 1,
                                cb < r, r, l);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -723,8 +782,8 @@ __device__ void gram_fix(const CoreArgs& c, int r, double* sA, double* sV, doubl
     const int more = __syncthreads_or(far);
     d4_t yt = {0.0, 0.0, 0.0, 0.0}, tz = yt;
     if (tile_live) {
-      yt = mfma_tile(sA + (ra < r ? ra : 0), LDK, ra < r, sQ + (cb < r ? cb : 0) * LDQ, 1, cb < r, r, l);
-      tz = mfma_tile(sQ + (ra < r ? ra : 0), LDQ, ra < r, sV + (cb < r ? cb : 0) * LDK, 1, cb < r, r, l);
+      yt = mfma_tile_loop(sA + (ra < r ? ra : 0), LDK, ra < r, sQ + (cb < r ? cb : 0) * LDQ, 1, cb < r, r, l);
+      tz = mfma_tile_loop(sQ + (ra < r ? ra : 0), LDQ, ra < r, sV + (cb < r ? cb : 0) * LDK, 1, cb < r, r, l);
     }
     __syncthreads();
     if (tile_live) {
