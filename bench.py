@@ -48,10 +48,13 @@ ROLLOUT = 500
 PEAK_HBM_GBPS = 8000.0
 STEADY_FROM = 100          # updates after which the rank has saturated at r_max
 # timed updates carry timing events at this stride (coprime to the refold
-# period of 16 updates, so every phase of the refold cycle is sampled): a
-# pair of events around each of an update's two kernels costs about a fifth
-# of the update's time on this GPU
-PROFILE_STRIDE = 7
+# period of 16 updates, so every phase of the refold cycle is sampled): an
+# event between the pass and the core delays the core by several
+# microseconds on this GPU, so kernel durations come from the updates at
+# offset 0 of the stride (events around each kernel) and the latency from
+# those at LATENCY_OFFSET (one event before the pass, one after the core)
+PROFILE_STRIDE = 13
+LATENCY_OFFSET = 6
 
 
 def make_stream():
@@ -925,8 +928,13 @@ def main():
     def one_step(g, profile):
         for k in range(m):
             j = k - STEADY_FROM
-            if profile and j >= 0 and j % PROFILE_STRIDE < 2:
-                g.profile(cap if j % PROFILE_STRIDE == 0 else 0)
+            if profile and j >= 0:
+                ph = j % PROFILE_STRIDE
+                if ph in (0, LATENCY_OFFSET):
+                    g.profile_latency(ph == LATENCY_OFFSET)
+                    g.profile(cap)
+                elif ph in (1, LATENCY_OFFSET + 1):
+                    g.profile(0)
             g.update(Xd[k], Xd[k + 1])
         g.profile(0)
         g.eigs(vectors=False)           # synchronising
@@ -949,6 +957,9 @@ def main():
         core_ms.append(b)
         upd_ms.append(u)
     pass_ms, core_ms, upd_ms = np.concatenate(pass_ms), np.concatenate(core_ms), np.concatenate(upd_ms)
+    kern = ~np.isnan(pass_ms)                # kernel-timed samples; the rest are latency samples
+    lat_ms = upd_ms[~kern]
+    pass_ms, core_ms = pass_ms[kern], core_ms[kern]
     for g in models:
         g.sync()
     infos = [g.info() for g in models]
@@ -959,7 +970,7 @@ def main():
     bytes_upd = n * (R_MAX + R_MAX) * 8 + 2 * n * 8      # read U, write U', read x, y
     pass_avg_s = float(np.mean(pass_ms)) * 1e-3
     achieved = bytes_upd / pass_avg_s / 1e9
-    lat = upd_ms * 1e3
+    lat = lat_ms * 1e3
     result = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -997,7 +1008,9 @@ def main():
             "bytes_per_launch": bytes_upd,
             "launches_timed": int(pass_ms.size),
             "launches_sampled": f"every {PROFILE_STRIDE}th update of the timed steps from update "
-                                f"{STEADY_FROM} on (HIP events on the update's stream)",
+                                f"{STEADY_FROM} on (HIP events on the update's stream); latency from "
+                                f"the updates {LATENCY_OFFSET} later in each stride (no event between "
+                                f"the two kernels)",
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },

@@ -403,6 +403,15 @@ odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_
 odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double* core_ms,
                                  double* update_ms, int64_t* count);
 
+/* Latency-only timing (a measurement aid, not a passage of the method):
+ * while on != 0, a timed update records only its pass's start and its
+ * small-SVD kernel's end, so that no event sits between the two kernels (an
+ * event there delays the second launch by several microseconds on MI355X).
+ * Such an update's pass_ms and core_ms samples read as NaN and
+ * odmd_profile_read leaves it out of its sums and count; update_ms is its
+ * latency.  EINVAL for a NULL handle. */
+odmd_status odmd_profile_latency(odmd_t h, int32_t on);
+
 #ifdef __cplusplus
 }
 #endif

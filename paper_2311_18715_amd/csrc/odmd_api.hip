@@ -56,6 +56,8 @@ struct odmd_s {
   bool jacobi_only = false;     // ODMD_CORE_SVD=jacobi at create time
   std::vector<hipEvent_t> ev;   // per update: pass start, pass end, core start, core end
   size_t ev_used = 0;
+  bool prof_lat = false;        // timed updates record the pass start and the core end only
+  std::vector<unsigned char> ev_lat;   // per timed update: recorded with prof_lat
   // Feedback: the core writes (seq << 8) | m (stored columns in use) into
   // this pinned host word after every update; seq counts the updates issued
   // on the handle.
@@ -266,7 +268,9 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
     }
     ev = &h->ev[h->ev_used];
     h->ev_used += EV_PER_UPDATE;
+    h->ev_lat.push_back(h->prof_lat ? 1 : 0);
   }
+  const bool lat = ev && h->prof_lat;   // no events between the two kernels
   PassArgs p{};
   p.Us = h->Us;
   p.x = x;
@@ -294,7 +298,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
     HIP_OK(launch_coef(ca, h->stream));
     p.eout = h->eout;
   }
-  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+  HIP_OK(launch_pass(p, (int)h->basis, kb, h->stream, ev ? ev[0] : nullptr, ev && !lat ? ev[1] : nullptr));
   if (h->general) {
     // the T sweep: appends y to T (refolding T when it is full) with zero
     // coefficients; its records carry T^T e
@@ -325,7 +329,7 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   c.tst = h->general ? h->tst : nullptr;
   c.pt = h->general ? h->pt : nullptr;
   c.rbt = h->ct;
-  HIP_OK(launch_core(c, h->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr));
+  HIP_OK(launch_core(c, h->stream, ev && !lat ? ev[2] : nullptr, ev ? ev[3] : nullptr));
   return ODMD_OK;
 }
 
@@ -1079,11 +1083,16 @@ odmd_status odmd_profile(odmd_t h, int32_t capacity) {
   return ODMD_OK;
 }
 
-// durations of timed update k: pass, core, and pass start to core end
+// durations of timed update k: pass, core (NaN for a latency-only update),
+// and pass start to core end
 static odmd_status update_times(odmd_t h, size_t k, float* t) {
   const hipEvent_t* e = &h->ev[EV_PER_UPDATE * k];
-  HIP_OK(hipEventElapsedTime(&t[0], e[0], e[1]));
-  HIP_OK(hipEventElapsedTime(&t[1], e[2], e[3]));
+  if (k < h->ev_lat.size() && h->ev_lat[k]) {
+    t[0] = t[1] = NAN;
+  } else {
+    HIP_OK(hipEventElapsedTime(&t[0], e[0], e[1]));
+    HIP_OK(hipEventElapsedTime(&t[1], e[2], e[3]));
+  }
   HIP_OK(hipEventElapsedTime(&t[2], e[0], e[3]));
   return ODMD_OK;
 }
@@ -1094,17 +1103,28 @@ odmd_status odmd_profile_read(odmd_t h, double* pass_ms, double* core_ms, int64_
   HIP_OK(hipStreamSynchronize(h->stream));
   const size_t n = h->ev_used / EV_PER_UPDATE;
   double a = 0.0, b = 0.0;
+  int64_t nk = 0;
   for (size_t k = 0; k < n; ++k) {
     float t[3];
     const odmd_status st = update_times(h, k, t);
     if (st != ODMD_OK) return st;
-    a += t[0];
-    b += t[1];
+    if (t[0] == t[0]) {
+      a += t[0];
+      b += t[1];
+      ++nk;
+    }
   }
   *pass_ms = a;
   *core_ms = b;
-  *count = (int64_t)n;
+  *count = nk;
   h->ev_used = 0;
+  h->ev_lat.clear();
+  return ODMD_OK;
+}
+
+odmd_status odmd_profile_latency(odmd_t h, int32_t on) {
+  if (!h) return ODMD_EINVAL;
+  h->prof_lat = on != 0;
   return ODMD_OK;
 }
 
@@ -1124,6 +1144,7 @@ odmd_status odmd_profile_samples(odmd_t h, int64_t cap, double* pass_ms, double*
   }
   *count = n;
   h->ev_used = 0;
+  h->ev_lat.clear();
   return ODMD_OK;
 }
 

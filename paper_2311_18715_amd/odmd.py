@@ -24,7 +24,7 @@ EXPORTS = [
     "odmd_create", "odmd_create_ex", "odmd_state_bytes", "odmd_update", "odmd_update_batch",
     "odmd_eigs", "odmd_predict", "odmd_predict_batch", "odmd_sync", "odmd_destroy", "odmd_status_str",
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
-    "odmd_profile_samples", "odmd_create_general", "odmd_state_bytes_general",
+    "odmd_profile_samples", "odmd_profile_latency", "odmd_create_general", "odmd_state_bytes_general",
     "odmd_default_shape", "odmd_create_shaped", "odmd_state_bytes_shaped", "odmd_autotune",
     "odmd_plan_create", "odmd_plan_launch", "odmd_plan_destroy", "odmd_update_batch_noalloc",
     "odmd_peek_status",
@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
             "odmd_profile": ([vp, i32], ctypes.c_int),
             "odmd_profile_read": ([vp, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
             "odmd_profile_samples": ([vp, i64, pd, pd, pd, ctypes.POINTER(i64)], ctypes.c_int),
+            "odmd_profile_latency": ([vp, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -261,6 +262,11 @@ class ODMD:
     def profile(self, capacity: int) -> None:
         """Record per-update events (capacity > 0 reserves them now); 0 stops."""
         _check(lib().odmd_profile(self._h, int(capacity)), "odmd_profile")
+
+    def profile_latency(self, on: bool) -> None:
+        """While on, timed updates record only the pass start and the core
+        end (their kernel samples read as NaN; update_ms is their latency)."""
+        _check(lib().odmd_profile_latency(self._h, 1 if on else 0), "odmd_profile_latency")
 
     def profile_read(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()

@@ -93,6 +93,7 @@ def test_null_arguments_are_rejected():
     assert L.odmd_eigs(None, 4, ctypes.byref(r), None, None, None, None) == 1
     assert L.odmd_get_info(None, None) == 1
     assert L.odmd_profile(None, 1) == 1
+    assert L.odmd_profile_latency(None, 1) == 1
 
 
 @needs_lib

@@ -159,3 +159,33 @@ def test_fp32_two_rows_per_lane_matches_one_row():
         assert torch.equal(a.basis_matrix(), c.basis_matrix())
     for g in [two, one] + A + C:
         g.close()
+
+
+def test_profile_kernel_and_latency_samples():
+    """Timed updates: events around each kernel give pass and core
+    durations; latency-only updates give NaN for those and their pass start
+    to core end; timing changes no result."""
+    X, Xd = _stream(20011, 8, 40, seed=77)
+    g, h = ODMD(20011, 16, 1e-8), ODMD(20011, 16, 1e-8)
+    g.profile(64)
+    g.profile(0)
+    for k in range(40):
+        if k == 10:
+            g.profile_latency(False)
+            g.profile(64)
+        elif k == 20:
+            g.profile_latency(True)
+        elif k == 30:
+            g.profile(0)
+        g.update(Xd[k], Xd[k + 1])
+        h.update(Xd[k], Xd[k + 1])
+    a, b, u = g.profile_samples()
+    assert len(a) == 20
+    assert np.all(a[:10] > 0) and np.all(b[:10] > 0)
+    assert np.all(u[:10] >= np.maximum(a[:10], b[:10]))
+    assert np.all(np.isnan(a[10:])) and np.all(np.isnan(b[10:]))
+    assert np.all(u[10:] > 0) and np.all(np.isfinite(u))
+    lam_g, lam_h = g.eigs(vectors=False)[0], h.eigs(vectors=False)[0]
+    assert np.array_equal(lam_g, lam_h)
+    g.close()
+    h.close()
