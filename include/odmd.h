@@ -344,9 +344,22 @@ odmd_status odmd_sync(odmd_t h);
  */
 odmd_status odmd_peek_status(odmd_t h, odmd_status* status);
 
-/* Free the handle and (unless caller-owned) its device memory; ODMD_EINVAL
- * while a plan holds it. */
+/* Free the handle and (unless caller-owned) its device memory, after
+ * waiting for its stream; ODMD_EINVAL while a plan holds it. */
 odmd_status odmd_destroy(odmd_t h);
+
+/* Free the handle without waiting for its stream (a request loop that closes
+ * many streams while others keep running; not a passage of the method).
+ * A handle whose device memory the library allocated is destroyed as by
+ * odmd_destroy (freeing device memory waits).  For a caller-owned
+ * workspace the caller keeps the buffer until the work queued on the
+ * handle's stream has finished: releasing it to an allocator that orders
+ * reuse on that same stream (torch's caching allocator, for a handle made
+ * on torch's current stream) is enough.  The handle's pinned host word
+ * goes back to a pool once that work has finished (an event on the stream).
+ * Errors of the queued work are not reported here.  ODMD_EINVAL for NULL or
+ * while a plan holds the handle. */
+odmd_status odmd_release(odmd_t h);
 
 const char* odmd_status_str(odmd_status s);
 

@@ -684,6 +684,95 @@ odmd_status launch_rollout(odmd_t h, int32_t steps, void* out) {
   return ODMD_OK;
 }
 
+// ---- pinned feedback words: a per-device pool ----
+// Each handle holds one 64-byte slot of mapped, coherent pinned host memory
+// (the rank feedback and the status mirror).  Allocating and freeing pinned
+// memory synchronises the device, so slots come from chunks that live until
+// the process ends.  A slot given back while the handle's work may still
+// write it waits behind an event recorded on the handle's stream.
+struct FbPool {
+  std::mutex mu;
+  std::vector<std::pair<unsigned*, unsigned*>> free;                 // (host, device)
+  std::vector<std::tuple<hipEvent_t, unsigned*, unsigned*>> waiting;
+};
+constexpr int FB_SLOT_WORDS = 16;     // 64 bytes
+constexpr int FB_CHUNK_SLOTS = 1024;
+
+FbPool& fb_pool(int device) {
+  static std::mutex mu;
+  static std::map<int, std::unique_ptr<FbPool>> pools;
+  std::lock_guard<std::mutex> lk(mu);
+  std::unique_ptr<FbPool>& p = pools[device];
+  if (!p) p.reset(new FbPool);
+  return *p;
+}
+
+// a zeroed slot of the current device, or false
+bool fb_acquire(int device, unsigned** host, unsigned** dev) {
+  FbPool& P = fb_pool(device);
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (size_t i = 0; i < P.waiting.size();) {
+    hipEvent_t e = std::get<0>(P.waiting[i]);
+    if (hipEventQuery(e) == hipSuccess) {
+      (void)hipEventDestroy(e);
+      P.free.emplace_back(std::get<1>(P.waiting[i]), std::get<2>(P.waiting[i]));
+      P.waiting[i] = P.waiting.back();
+      P.waiting.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  (void)hipGetLastError();            // hipEventQuery's not-ready status
+  if (P.free.empty()) {
+    unsigned* h = nullptr;
+    unsigned* d = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&h), (size_t)FB_CHUNK_SLOTS * FB_SLOT_WORDS * sizeof(unsigned),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&d), h, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      if (h) (void)hipHostFree(h);
+      return false;
+    }
+    for (int k = FB_CHUNK_SLOTS - 1; k >= 0; --k)
+      P.free.emplace_back(h + k * FB_SLOT_WORDS, d + k * FB_SLOT_WORDS);
+  }
+  *host = P.free.back().first;
+  *dev = P.free.back().second;
+  P.free.pop_back();
+  std::memset(*host, 0, FB_SLOT_WORDS * sizeof(unsigned));
+  return true;
+}
+
+// give a slot back: at once if no queued work can still write it (wait =
+// false), else behind an event on the stream (a synchronisation if the
+// event cannot be made)
+void fb_release(int device, unsigned* host, unsigned* dev, hipStream_t stream, bool pending) {
+  FbPool& P = fb_pool(device);
+  hipEvent_t e = nullptr;
+  if (pending) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(e, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+      (void)hipStreamSynchronize(stream);
+    }
+  }
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (e) P.waiting.emplace_back(e, host, dev);
+  else P.free.emplace_back(host, dev);
+}
+
+// the state's non-zero initial fields, after the memset (no host staging,
+// so creating a handle does not wait for the stream)
+__global__ void k_init_state(DevState* st, double tol, unsigned* mirror, int general) {
+  if (threadIdx.x == 0) {
+    st->tol = tol;
+    st->smirror = mirror;
+    st->general = general;
+  }
+}
+
 }  // namespace
 
 // ---- plans: a fixed batched step, launchable without host staging ----
@@ -802,22 +891,17 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
     delete s;
     return ODMD_EDEVICE;
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->fb_host), 64,
-                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-      hipHostGetDevicePointer(reinterpret_cast<void**>(&s->fb_dev), s->fb_host, 0) != hipSuccess) {
-    (void)hipGetLastError();
-    if (s->fb_host) (void)hipHostFree(s->fb_host);
+  // word 0: the rank feedback, word 1: host-visible copy of the latched status
+  if (!fb_acquire(s->device, &s->fb_host, &s->fb_dev)) {
     delete s;
     return ODMD_ENOMEM;
   }
-  s->fb_host[0] = 0;
-  s->fb_host[1] = 0;            // host-visible copy of the latched status
   if (workspace) {
     s->mem = static_cast<char*>(workspace);
   } else {
     if (hipMalloc(&s->mem, L.total) != hipSuccess) {
       (void)hipGetLastError();
-      (void)hipHostFree(s->fb_host);
+      fb_release(s->device, s->fb_host, s->fb_dev, s->stream, false);
       delete s;
       return ODMD_ENOMEM;
     }
@@ -839,20 +923,22 @@ static odmd_status create_impl(int64_t n, int32_t r_max, double tol, odmd_dtype 
     s->Ts = s->mem + L.Ts;
     s->eout = s->mem + L.eout;
   }
-  const double tol_eff = s->tol_eff;
-  const int gflag = general ? 1 : 0;
-  unsigned* const mirror = s->fb_dev + 1;
-  if (hipMemsetAsync(s->mem, 0, L.total, s->stream) != hipSuccess ||
-      hipMemcpyAsync(&s->st->tol, &tol_eff, sizeof(double), hipMemcpyHostToDevice, s->stream) !=
-          hipSuccess ||
-      hipMemcpyAsync(&s->st->smirror, &mirror, sizeof(mirror), hipMemcpyHostToDevice, s->stream) !=
-          hipSuccess ||
-      hipMemcpyAsync(&s->st->general, &gflag, sizeof(int), hipMemcpyHostToDevice, s->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(s->stream) != hipSuccess) {
+  // zero state, then its non-zero fields, in the stream's order: the first
+  // update on the stream sees them; nothing here waits for the stream
+  if (hipMemsetAsync(s->mem, 0, L.total, s->stream) != hipSuccess) {
     (void)hipGetLastError();
+    (void)hipStreamSynchronize(s->stream);
     if (s->own) (void)hipFree(s->mem);
-    (void)hipHostFree(s->fb_host);
+    fb_release(s->device, s->fb_host, s->fb_dev, s->stream, false);
+    delete s;
+    return ODMD_EDEVICE;
+  }
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s->stream, s->st, s->tol_eff, s->fb_dev + 1,
+                     general ? 1 : 0);
+  if (hipGetLastError() != hipSuccess) {
+    (void)hipStreamSynchronize(s->stream);
+    if (s->own) (void)hipFree(s->mem);
+    fb_release(s->device, s->fb_host, s->fb_dev, s->stream, false);
     delete s;
     return ODMD_EDEVICE;
   }
@@ -1155,7 +1241,19 @@ odmd_status odmd_destroy(odmd_t h) {
     s = ODMD_EDEVICE;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->own && hipFree(h->mem) != hipSuccess) s = ODMD_EDEVICE;
-  if (h->fb_host && hipHostFree(h->fb_host) != hipSuccess) s = ODMD_EDEVICE;
+  fb_release(h->device, h->fb_host, h->fb_dev, h->stream, false);
+  (void)hipGetLastError();
+  delete h;
+  return s;
+}
+
+odmd_status odmd_release(odmd_t h) {
+  if (!h || h->plans > 0) return ODMD_EINVAL;
+  if (h->own) return odmd_destroy(h);     // freeing its memory waits anyway
+  odmd_status s = ODMD_OK;
+  if (hipSetDevice(h->device) != hipSuccess) s = ODMD_EDEVICE;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  fb_release(h->device, h->fb_host, h->fb_dev, h->stream, true);
   (void)hipGetLastError();
   delete h;
   return s;

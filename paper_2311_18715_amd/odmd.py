@@ -22,7 +22,8 @@ STATUS = {
 }
 EXPORTS = [
     "odmd_create", "odmd_create_ex", "odmd_state_bytes", "odmd_update", "odmd_update_batch",
-    "odmd_eigs", "odmd_predict", "odmd_predict_batch", "odmd_sync", "odmd_destroy", "odmd_status_str",
+    "odmd_eigs", "odmd_predict", "odmd_predict_batch", "odmd_sync", "odmd_destroy", "odmd_release",
+    "odmd_status_str",
     "odmd_get_info", "odmd_get_state", "odmd_get_basis", "odmd_profile", "odmd_profile_read",
     "odmd_profile_samples", "odmd_profile_latency", "odmd_create_general", "odmd_state_bytes_general",
     "odmd_default_shape", "odmd_create_shaped", "odmd_state_bytes_shaped", "odmd_autotune",
@@ -96,6 +97,7 @@ def lib() -> ctypes.CDLL:
             "odmd_sync": ([vp], ctypes.c_int),
             "odmd_peek_status": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "odmd_destroy": ([vp], ctypes.c_int),
+            "odmd_release": ([vp], ctypes.c_int),
             "odmd_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "odmd_get_info": ([vp, ctypes.POINTER(Info)], ctypes.c_int),
             "odmd_get_state": ([vp, i32, pd, pd, pd, pd, pd], ctypes.c_int),
@@ -284,12 +286,17 @@ class ODMD:
         k = min(cap, c.value)
         return a[:k].copy(), b[:k].copy(), u[:k].copy()
 
-    def close(self) -> None:
+    def close(self, wait: bool = True) -> None:
+        """Free the handle: after its stream's work (odmd_destroy), or, with
+        wait=False, at once (odmd_release; a caller-owned workspace must then
+        outlive the queued work, as torch's allocator on the handle's stream
+        ensures)."""
         if getattr(self, "_h", None):
-            code = lib().odmd_destroy(self._h)
+            name = "odmd_destroy" if wait else "odmd_release"
+            code = getattr(lib(), name)(self._h)
             if code != 1:            # EINVAL: a live plan holds the handle, which stays valid
                 self._h = None
-            _check(code, "odmd_destroy")
+            _check(code, name)
 
     def __del__(self):
         try:

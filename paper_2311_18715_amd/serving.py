@@ -150,7 +150,9 @@ class Server:
                 self.active[st.sid] = st
 
     def _release(self, st: _Stream) -> None:
-        st.model.close()
+        # no wait: the workspace goes back to torch's allocator on the
+        # handles' stream, which orders its reuse after the queued work
+        st.model.close(wait=False)
         st.model = None
         st.workspace = None
         self.used -= st.bytes

@@ -86,6 +86,7 @@ def test_null_arguments_are_rejected():
     assert L.odmd_update(None, None, None) == 1
     assert L.odmd_sync(None) == 1
     assert L.odmd_destroy(None) == 1
+    assert L.odmd_release(None) == 1
     assert L.odmd_predict(None, 5, None) == 1
     assert L.odmd_update_batch(None, None, None, 1) == 1
     assert L.odmd_update_batch_noalloc(None, None, None, 1) == 1

@@ -130,3 +130,42 @@ def test_device_errors_reach_the_requests_of_their_stream():
         g.sync()
     assert g.peek_status() == 0
     g.close()
+
+
+def test_release_without_waiting_reuses_memory_safely():
+    """Handles on caller workspaces released without waiting (odmd_release)
+    while their updates are still queued; their workspaces go back to
+    torch's allocator at once and their pinned words to the library's pool.
+    Handles made right after (reusing both) match a handle made on a quiet
+    device bit for bit."""
+    n, rank, rmax, m = 20011, 8, 16, 30
+    s = synth.random_planted(n, rank, seed=4321, noise=1e-7)
+    Xd = torch.from_numpy(np.ascontiguousarray(s.snapshots(0, m + 1).T)).cuda()
+    ref = ODMD(n, rmax, 1e-8)
+    for k in range(m):
+        ref.update(Xd[k], Xd[k + 1])
+    lam_ref = ref.eigs(vectors=False)[0]
+    sig_ref = ref.state()["sigma"]
+    ref.close()
+    nbytes = ODMD.state_bytes(n, rmax, "f64")
+    for _ in range(3):
+        hs = []
+        for i in range(40):
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            g = ODMD(n, rmax, 1e-8, workspace=ws)
+            for k in range(6):
+                g.update(Xd[k], Xd[k + 1])
+            hs.append(g)
+        for g in hs:
+            g.close(wait=False)               # their updates are still queued
+        del hs, g, ws
+        outs = []
+        for i in range(4):
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            g = ODMD(n, rmax, 1e-8, workspace=ws)
+            for k in range(m):
+                g.update(Xd[k], Xd[k + 1])
+            outs.append((g.eigs(vectors=False)[0], g.state()["sigma"]))
+            g.close(wait=False)
+        for lam, sig in outs:
+            assert np.array_equal(lam, lam_ref) and np.array_equal(sig, sig_ref)

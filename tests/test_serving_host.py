@@ -75,7 +75,7 @@ class FakeBackend:
                 B.log.append(("sync", self.id))
                 B.errors.pop(self.id, None)
 
-            def close(self):
+            def close(self, wait=True):
                 B.live.discard(self.id)
 
         self.models = {}
