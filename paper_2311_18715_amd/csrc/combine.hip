@@ -7,11 +7,11 @@
 // write per predicted state).
 //
 // As a product it is Out (K x n) = Coef (K x m) S^T (m x n) with a short
-// contraction (m <= 72): 2 K n m flops against K n output writes.  At the
-// FP64 matrix-core rate this GPU reaches in practice (about 45 TFLOP/s, a
-// 16x16x4 product every ~100 cycles per SIMD) the flops take longer than
-// the writes: it is bound by the matrix cores.  It runs on
-// the FP64 matrix cores (16x16x4): a wavefront takes 16 rows of one tile in
+// contraction (m <= 72): 2 K n m flops against K n output writes.  For
+// FP64 states the writes bound it (a 500-state read-out at n = 160,000 moves
+// 889 MB, 178 us at the device-copy rate, against 98 us of FP64
+// matrix-core time); for FP32 states and wide bases the two are close.  It
+// runs on the FP64 matrix cores (16x16x4): a wavefront takes 16 rows of one tile in
 // the streaming pass's operand layout (lane l holds row l%16 of stored
 // columns 4 kk + l/16, so one column of the unit is a 128-byte line for
 // FP64) and multiplies them by 16-step blocks of coefficients staged in LDS
