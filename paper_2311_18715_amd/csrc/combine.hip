@@ -20,9 +20,15 @@
 // stores: the states are not read again here).  The
 // stored values convert exactly to FP64, the coefficients are FP64 and so
 // are the sums; the output is rounded once, to its type.  A workgroup covers
-// RPW rows and 16 NS states; its stored columns are read once per 16 NS
-// states.
+// a contiguous share of the rows (about CB_RPW or more: the grid holds no more
+// workgroups than the GPU runs at once) and 16 NS states; the stored
+// columns are read once per 16 NS states.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "odmd_internal.h"
 #include "pass.h"
@@ -33,7 +39,7 @@ namespace odmd {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int CB_THREADS = 256;          // four wavefronts
-constexpr int CB_RPW = 512;              // rows per workgroup (8 tiles)
+constexpr int CB_RPW = 512;              // rows per workgroup, at least
 
 // NS 16-state blocks per workgroup (the host picks NS from the number of
 // states, so that a short rollout computes no more than 16 states in vain)
@@ -59,9 +65,14 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(CombineArgs c) {
 
   const TS* __restrict__ Us = static_cast<const TS*>(c.Us);
   TO* __restrict__ out = static_cast<TO*>(c.out);
-  const int64_t r0 = (int64_t)blockIdx.x * CB_RPW;
-  const int64_t rend = r0 + CB_RPW < c.n ? r0 + CB_RPW : c.n;
-  const int nunit = (int)((rend - r0 + 15) / 16);
+  // the workgroup's rows: a contiguous share of the 16-row units (the
+  // launch sizes the grid to the workgroups the GPU holds at once, so the
+  // last round of workgroups does not run the chip part empty)
+  const int64_t units = (c.n + 15) / 16;
+  const int64_t ub = (int64_t)blockIdx.x * units / gridDim.x;
+  const int64_t ue = (int64_t)(blockIdx.x + 1) * units / gridDim.x;
+  const int64_t r0 = 16 * ub;
+  const int nunit = (int)(ue - ub);
   const int kmax = (m + 3) / 4;              // live k-steps (uniform)
   // the unit's stored values stay in their storage type until used; the next
   // unit's loads are in flight while the current one is multiplied
@@ -134,13 +145,44 @@ __global__ __launch_bounds__(256) void k_combine_rows(CombineArgs c) {
   }
 }
 
+// Workgroups of kernel f the GPU holds at once (its occupancy per CU times
+// the CUs of the current device), cached per kernel and device.
+static int resident_blocks(const void* f) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({f, dev});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, CB_THREADS, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cache[{f, dev}] = per_cu * cus;
+}
+
+// Row workgroups: one per CB_RPW rows at most, and no more than the GPU holds
+// at once together with the launch's other state blocks (then every
+// workgroup gets a larger, equal share of the rows).
+template <typename K>
+static dim3 combine_grid(K f, const CombineArgs& c, int NS) {
+  const unsigned ys = (unsigned)((c.K + 16 * NS - 1) / (16 * NS));
+  int64_t g = (c.n + CB_RPW - 1) / CB_RPW;
+  const int res = resident_blocks(reinterpret_cast<const void*>(f));
+  if (res > 0) g = std::min<int64_t>(g, std::max<int64_t>(1, res / (int64_t)ys));
+  return dim3((unsigned)g, ys);
+}
+
 template <typename TS, typename TO, int NS>
 static hipError_t launch_ns(const CombineArgs& c, int rb, hipStream_t s) {
-  const dim3 grid((unsigned)((c.n + CB_RPW - 1) / CB_RPW), (unsigned)((c.K + 16 * NS - 1) / (16 * NS)));
   const dim3 block(CB_THREADS);
   switch (rb) {
 #define ODMD_CASE(RB) \
-  case RB: hipLaunchKernelGGL((k_combine<TS, TO, RB, NS>), grid, block, 0, s, c); break;
+  case RB: hipLaunchKernelGGL((k_combine<TS, TO, RB, NS>), combine_grid(k_combine<TS, TO, RB, NS>, c, NS), \
+                              block, 0, s, c); break;
     ODMD_CASE(8) ODMD_CASE(16) ODMD_CASE(24) ODMD_CASE(32) ODMD_CASE(40) ODMD_CASE(48)
     ODMD_CASE(56) ODMD_CASE(64) ODMD_CASE(72)
 #undef ODMD_CASE
