@@ -91,7 +91,11 @@ odmd_status odmd_create(int64_t n, int32_t r_max, double tol, odmd_t* h);
  *          aligned, owned by the caller and kept alive until odmd_destroy.
  *   Either way the handle also holds 64 bytes of pinned host memory, into
  *   which the device reports the rank after each update; the host sizes the
- *   next launches from it (work follows the live rank, not r_max).
+ *   next launches from it (work follows the live rank, not r_max).  Those
+ *   words come from a per-device pool that lives until the process ends.
+ *   The state is initialised by work queued on hip_stream (a memset and a
+ *   one-thread kernel): creating a handle does not wait for the stream, and
+ *   a device error of that work is reported by a later call.
  */
 odmd_status odmd_create_ex(int64_t n, int32_t r_max, double tol, odmd_dtype basis,
                            odmd_dtype io, void* hip_stream, void* workspace,
