@@ -84,6 +84,23 @@ def test_planted_small_every_step(core_svd):
     assert np.max(np.abs(Pg - Po)) < 1e-10 * np.max(np.abs(Po))
 
 
+@pytest.mark.parametrize("steps", [1, 4, 5, 16, 17, 129, 1100])
+def test_rollout_lengths_against_the_oracle(steps):
+    """Rollouts of every length class of the read-out: a few states (one
+    row per lane), one to eight 16-state blocks, several 128-state blocks,
+    and more states than one coefficient chunk (512): each state within
+    1e-9 of the oracle's, relative to the largest state (the planted modes
+    decay: the last of 1100 states is 1e-9 of the first), on a ragged n."""
+    s = synth.random_planted(3001, 6, seed=913, noise=1e-9)
+    X = s.snapshots(0, 61)
+    g, o = run_both(X, 12, 1e-8)
+    pg = g.predict(steps).cpu().numpy()
+    po = o.predict(steps)
+    assert pg.shape == po.shape == (steps, 3001)
+    err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1).max()
+    assert err.max() < 1e-9
+
+
 def test_planted_small_rollout():
     s = synth.planted_small()
     X = s.snapshots(0, 400)
