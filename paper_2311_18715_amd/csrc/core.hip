@@ -1346,7 +1346,11 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
   __syncthreads();
 
   // 10. C <- V_k[:, kept]^T T (rn x rn, K = M) on the matrix cores; sigma,
-  //     w, p_y and A~_ij = (sigma_i C_ij + p_y,i w_j) / sigma_j
+  //     w, p_y and A~_ij = (sigma_i C_ij + p_y,i w_j) / sigma_j.  Each tile
+  //     is formed transposed (T's columns as the first operand, the same
+  //     products in the same order), so that lane l holds rows i0 + l%16 of
+  //     columns j0 + 4 v + l/16: a store then writes 16 consecutive rows of
+  //     a column (four 128-byte pieces instead of sixteen 32-byte ones)
   {
     const int wv = tid >> 6, l = tid & 63;
     const int nt = (rn + 15) / 16;
@@ -1354,14 +1358,14 @@ __device__ __forceinline__ void core_update(const CoreArgs& c) {
       const int i0 = 16 * (tile % nt), j0 = 16 * (tile / nt);
       const int ia = i0 + (l & 15), jb = j0 + (l & 15);
       const int pa = ia < rn ? perm[ia] : 0;
-      const d4_t d = mfma_tile(sV + pa * LDK, 1, ia < rn, sA + (jb < rn ? jb : 0) * LDK, 1, jb < rn,
+      const d4_t d = mfma_tile(sA + (jb < rn ? jb : 0) * LDK, 1, jb < rn, sV + pa * LDK, 1, ia < rn,
                                M, l);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + 4 * v + (l >> 4);
-        if (i < rn && jb < rn) {
-          st->C[jb * RMAX + i] = d[v];
-          st->At[jb * RMAX + i] = (sgn[i] * d[v] + pyn[i] * wn[jb]) * isg[jb];
+        const int j = j0 + 4 * v + (l >> 4);
+        if (ia < rn && j < rn) {
+          st->C[j * RMAX + ia] = d[v];
+          st->At[j * RMAX + ia] = (sgn[ia] * d[v] + pyn[ia] * wn[j]) * isg[j];
         }
       }
     }
