@@ -679,22 +679,24 @@ __device__ __forceinline__ void general_tail(const CoreArgs& c, int r, int rn, i
     rt[h] = d;
   }
   __syncthreads();
-  // G' = U_k^T (E V_k) (rn x rn, K = M) and A~ = G' diag(sigma')^-1
+  // G' = U_k^T (E V_k) (rn x rn, K = M) and A~ = G' diag(sigma')^-1, each
+  // tile formed transposed (as for C in the chained update: lane l holds
+  // rows i0 + l%16, so the stores write 128-byte pieces)
   {
     const int nt = (rn + 15) / 16;
     for (int tile = wv; tile < nt * nt; tile += CORE_THREADS / 64) {
       const int i0 = 16 * (tile % nt), j0 = 16 * (tile / nt);
       const int ia = i0 + (l & 15), jb = j0 + (l & 15);
       const int pa = ia < rn ? perm[ia] : 0;
-      const d4_t d = mfma_tile(sA + pa * LDK, 1, ia < rn, sQ + (jb < rn ? jb : 0) * MMAX, 1, jb < rn,
+      const d4_t d = mfma_tile(sQ + (jb < rn ? jb : 0) * MMAX, 1, jb < rn, sA + pa * LDK, 1, ia < rn,
                                M, l);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + 4 * v + (l >> 4);
-        if (i < rn && jb < rn) {
-          const double g = d[v] / sd[perm[i]];
-          st->C[jb * RMAX + i] = g;
-          st->At[jb * RMAX + i] = g / sgn[jb];
+        const int j = j0 + 4 * v + (l >> 4);
+        if (ia < rn && j < rn) {
+          const double g = d[v] / sd[pa];
+          st->C[j * RMAX + ia] = g;
+          st->At[j * RMAX + ia] = g / sgn[j];
         }
       }
     }
