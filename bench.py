@@ -217,9 +217,9 @@ def prediction_section(torch):
     only timing of this path, one time step of a converged DMD model, is
     quoted at): a planted stream (Gaussian modes, rank 20, generated on the
     device), r_max = 40, 121 updates, then odmd_predict of one state: the
-    first call after an update (the eigendecomposition of A~ included) and
-    the following ones (eigenpairs reused), and a 100-state rollout.  Device time between
-    events on the handle's stream."""
+    first call after an update and the following ones (the states are formed
+    from powers of A~, so no call needs the eigendecomposition), and a
+    100-state rollout.  Device time between events on the handle's stream."""
     from paper_2311_18715_amd import synth
     from paper_2311_18715_amd.odmd import ODMD
     gen = synth.DevicePlanted(torch, PRED_N, PRED_RANK, 231118715 + 9)
@@ -230,7 +230,7 @@ def prediction_section(torch):
     for k in range(PRED_UPDATES):
         g.update(X[k], X[k + 1])
     g.predict(1, out=out1)             # every kernel of the path launched once
-    g.update(X[PRED_UPDATES], X[PRED_UPDATES + 1])   # new A~: the next call solves again
+    g.update(X[PRED_UPDATES], X[PRED_UPDATES + 1])   # a new A~ for the first timed call
     torch.cuda.synchronize()
 
     def timed(fn, reps):

@@ -312,17 +312,20 @@ odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double*
 /*
  * Predicted states x_{a+1} .. x_{a+steps} where a is the time index of the
  * last x_k1 (Sec. 2.3, u(t) = Phi Lambda^(t/dt) Phi^+ u(0), anchored at the
- * last snapshot: Phi^+ u(0) = V^-1 U^T x_a).  out: device, steps x n, row
- * k-1 holds state a+k, io type, row-major (row stride n).  steps >= 1.
- * Asynchronous (the eigendecomposition it may need runs on the device);
- * kernel launches only, so it may be captured into a HIP graph.
+ * last snapshot: Phi^+ u(0) = V^-1 U^T x_a).  At integer steps this is
+ * U V Lambda^k V^-1 U^T x_a = U A~^k U^T x_a, which is how it is formed
+ * (powers of A~, no eigendecomposition; the same states wherever A~ has a
+ * full set of eigenvectors, and defined where it has not).  out: device,
+ * steps x n, row k-1 holds state a+k, io type, row-major (row stride n).
+ * steps >= 1.  Asynchronous; kernel launches only, so it may be captured
+ * into a HIP graph.
  */
 odmd_status odmd_predict(odmd_t h, int32_t steps, void* out);
 
 /*
- * odmd_predict for several streams at once: the eigendecompositions they
- * need run in one launch (one workgroup per stream), then each stream's
- * states are written as by odmd_predict.  hs[i] distinct handles sharing one
+ * odmd_predict for several streams at once: the coefficients of every
+ * stream's first chunk of states are formed in one launch (one workgroup
+ * per stream), then each stream's states are written as by odmd_predict.  hs[i] distinct handles sharing one
  * device and HIP stream, steps[i] >= 1, outs[i] as odmd_predict's out (host
  * arrays of count entries, read during the call).  Asynchronous; results
  * equal those of odmd_predict bit for bit.  ODMD_EINVAL for a NULL entry,

@@ -1,21 +1,19 @@
 // Eigendecomposition of the reduced operator and prediction coefficients.
 //
-// Sec. 2.3: A~ = V Lambda V^-1, Phi = U V, and the prediction
-// u(t) = Phi Lambda^(t/dt) Phi^+ u(0).  With U orthonormal and the anchor
-// u(0) = x_a (the last snapshot), Phi^+ u(0) = V^-1 U^T x_a = V^-1 p_y =: b~,
-// so the state k steps ahead is U c_k with c_k = Re(V (Lambda^k b~)).
+// Sec. 2.3: A~ = V Lambda V^-1 and Phi = U V (the projected DMD modes), and
+// the prediction u(t) = Phi Lambda^(t/dt) Phi^+ u(0).
 //
-// k_eig (one 64-lane wavefront, FP64):
+// k_eig (one 64-lane wavefront, FP64), on demand for the eigenpairs:
 //   1. Householder reduction of A~ to upper Hessenberg form H = Q^T A~ Q;
 //   2. Francis double-shift QR iteration to the real Schur form T = Z^T A~ Z
 //      (1x1 and standardised 2x2 diagonal blocks), accumulating Z;
 //   3. eigenvectors of T by back-substitution (complex arithmetic), one lane
 //      per eigenvalue, then V = Z X, unit 2-norm, largest entry real > 0;
-//   4. order by |lambda| descending, then Im descending;
-//   5. b~ = V^-1 p_y = G^-1 X^-1 Z^T p_y (V = Z X G, G the normalising
-//      factors): block back-substitution.
-// k_predict_coef: c_k for a chunk of steps, folded with the basis
-// coefficients (U = S[:, :m] Q, so U c = S (Q c)).
+//   4. order by |lambda| descending, then Im descending.
+// k_power_coef: the prediction's coefficients for a chunk of steps, as
+// powers of A~ applied to U^T x_a (equal to the eigenvector form at integer
+// steps, see below), folded with the basis coefficients (U = S[:, :m] Q,
+// so U c = S (Q c)).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -185,8 +183,6 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   __shared__ double Xr[(RMAX + 1) * LDH];
   __shared__ double Xi[(RMAX + 1) * LDH];
   __shared__ double wr[RMAX], wi[RMAX], hv[RMAX];
-  __shared__ double gr[RMAX], gi[RMAX], cr[RMAX], ci[RMAX];
-  __shared__ int srank[RMAX];
   __shared__ double dum[64 * 9];           // slots of lanes outside a role of a bulge step
   __shared__ int sfail;
   const int t = threadIdx.x;
@@ -497,7 +493,6 @@ __device__ __forceinline__ void eig_body(DevState* st) {
       const double mj = hv[j];
       rank += (mj > ml) || (mj == ml && (wi[j] > wi[t] || (wi[j] == wi[t] && j < t)));
     }
-    srank[t] = rank;
     double* __restrict__ vr = st->V_re + rank * RMAX;
     double* __restrict__ vi = st->V_im + rank * RMAX;
     // entries i0 .. i0+3 of Z X[:, t]: one load of x_j serves four rows of
@@ -545,8 +540,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
     // conj(v_ib) / (|v_ib| ||v||)
     const double m = sqrt(best), f = 1.0 / sqrt(nrm2);
     const double pr = vbr / m * f, pi = -vbi / m * f;
-    gr[t] = pr;                              // V[:, rank] = (Z X[:, t]) (pr + i pi)
-    gi[t] = pi;
+                                             // V[:, rank] = (Z X[:, t]) (pr + i pi)
     for (int i0 = 0; i0 < n; i0 += 4) {
       double ar[4], ai[4];
       zx4(i0, ar, ai);
@@ -565,64 +559,6 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   __threadfence();
   __syncthreads();
 
-  // 5. b~ = V^-1 p_y.  V is Z X G with its columns reordered (G the
-  //    diagonal of the normalising factors), Z orthogonal and X block upper
-  //    triangular (a 2 x 2 diagonal block per complex pair), so
-  //    b~ = G^-1 X^-1 Z^T p_y: one matrix-vector product, then a block
-  //    back-substitution with one lane per entry of the right-hand side.
-  if (!sfail) {
-    if (t < n) {
-      double a = 0.0;
-      for (int i = 0; i < n; ++i) a += Zm(i, t) * st->py[i];
-      cr[t] = a;
-      ci[t] = 0.0;
-    }
-    __syncthreads();
-    for (int i = n - 1; i >= 0;) {
-      const bool pair = i > 0 && wi[i] < 0.0;     // (i - 1, i): a complex pair
-      if (!pair) {
-        const cplx b = cdiv({cr[i], ci[i]}, {Xr[i * LDH + i], Xi[i * LDH + i]});
-        if (t < i) {
-          const cplx u = cmul({Xr[i * LDH + t], Xi[i * LDH + t]}, b);
-          cr[t] -= u.re;
-          ci[t] -= u.im;
-        }
-        if (t == i) {                              // c[i] is spent: it now holds b'[i]
-          cr[i] = b.re;
-          ci[i] = b.im;
-        }
-        __syncthreads();
-        i -= 1;
-      } else {
-        const int p = i - 1, q = i;
-        const cplx xpp = {Xr[p * LDH + p], Xi[p * LDH + p]}, xpq = {Xr[q * LDH + p], Xi[q * LDH + p]};
-        const cplx xqp = {Xr[p * LDH + q], Xi[p * LDH + q]}, xqq = {Xr[q * LDH + q], Xi[q * LDH + q]};
-        const cplx cp = {cr[p], ci[p]}, cq = {cr[q], ci[q]};
-        const cplx det = csub(cmul(xpp, xqq), cmul(xpq, xqp));
-        const cplx bp = cdiv(csub(cmul(cp, xqq), cmul(xpq, cq)), det);
-        const cplx bq = cdiv(csub(cmul(xpp, cq), cmul(xqp, cp)), det);
-        if (t < p) {
-          const cplx u = cadd(cmul({Xr[p * LDH + t], Xi[p * LDH + t]}, bp),
-                              cmul({Xr[q * LDH + t], Xi[q * LDH + t]}, bq));
-          cr[t] -= u.re;
-          ci[t] -= u.im;
-        }
-        if (t == p) {
-          cr[p] = bp.re;
-          ci[p] = bp.im;
-          cr[q] = bq.re;
-          ci[q] = bq.im;
-        }
-        __syncthreads();
-        i -= 2;
-      }
-    }
-    if (t < n) {
-      const cplx b = cdiv({cr[t], ci[t]}, {gr[t], gi[t]});
-      st->bt_re[srank[t]] = b.re;
-      st->bt_im[srank[t]] = b.im;
-    }
-  }
   if (t == 0) {
     st->eig_status = sfail;
     if (sfail) latch_status(st, ST_NOCONV);
@@ -630,43 +566,228 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   }
 }
 
-// Coefficients of one chunk of predicted states: column kk (state
-// a+k0+kk+1) of coefA is Q c_k, so that the state is S[:, :m] Q c_k.
-__global__ __launch_bounds__(256) void k_predict_coef(DevState* st, int k0, int K) {
-  __shared__ double zr[4][RMAX], zi[4][RMAX], cc[4][RMAX];
-  const int col = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int kk = blockIdx.x * 4 + col;
-  const int n = st->r, m = st->m;
-  const bool live = kk < K && n > 0 && st->eig_status == 0;
-  const double kstep = (double)(k0 + kk + 1);
-  if (live && l < n) {
-    const double lr = st->lam_re[l], li = st->lam_im[l];
-    const double mag = pow(hypot(lr, li), kstep);
-    const double ang = kstep * atan2(li, lr);
-    double sn, cs;
-    sincos(ang, &sn, &cs);
-    const cplx p = {mag * cs, mag * sn};
-    const cplx z = cmul(p, {st->bt_re[l], st->bt_im[l]});
-    zr[col][l] = z.re;
-    zi[col][l] = z.im;
+// Prediction coefficients by powers of A~ (Sec. 2.3).  With U orthonormal,
+// Phi = U V and the anchor x_a (Phi^+ x_a = V^-1 U^T x_a = V^-1 p_y), the
+// state k steps ahead Phi Lambda^k Phi^+ x_a = U V Lambda^k V^-1 p_y equals
+// U A~^k p_y: the same states without the eigendecomposition (and defined
+// also where A~ has no full set of eigenvectors).  One workgroup forms
+// c_k = A~^k p_y for one chunk of steps k0+1 .. k0+K by doubling: c_{k0+1}
+// = A~ c_{k0}; with columns 1 .. w known and P = A~^w, columns w+1 .. 2w
+// are P times columns 1 .. w, then P <- P^2.  The columns stay in LDS
+// (leading dimension r | 1; the host sizes chunks by coef_chunk(r_max)),
+// and are written out as Q c_k, the coefficients of the stored columns
+// (U = S[:, :m] Q).  c_{k0+K} is kept in cfwd, where the next chunk starts.
+// Products are 16 x 16 FP64 matrix-core tiles (16x16x4 operand layout:
+// lane l supplies row or column l % 16 at k-step offset l / 16; element v
+// of lane l's result is row 4 v + l / 16, column l % 16).
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int LP = RMAX + 1;            // leading dimension of the LDS matrices
+constexpr int PC_THREADS = 256;
+constexpr int PC_NWV = PC_THREADS / 64;
+constexpr int PC_NA = RMAX * RMAX / PC_THREADS;                    // A~ entries per thread
+constexpr int PC_NQ = (CMAX * LP + PC_THREADS - 1) / PC_THREADS;   // Q entries per thread
+
+struct PowerLds {
+  double M[2 * RMAX * LP];              // A~^w and its square; then Q
+  double col[PC_LCOL];                  // c_k of this chunk, column kk at kk * ldc
+  double sv[RMAX];
+};
+static_assert(CMAX * LP <= 2 * RMAX * LP, "Q fits the power buffers");
+
+// One 16 x 16 tile: sum over the k-steps s < 4 NT of A(s) B(s), where a(s)
+// and b(s) give this lane's operands; two accumulators over alternate
+// k-steps.  NT 16-row tiles cover the rank (entries past it are zero).
+template <int NT, class FA, class FB>
+__device__ __forceinline__ d4_t tile_sum(FA a, FB b) {
+  d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
+#pragma unroll
+  for (int s = 0; s < 4 * NT; s += 2) {
+    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a(s), b(s), d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a(s + 1), b(s + 1), d1, 0, 0, 0);
+  }
+  return d0 + d1;
+}
+
+template <int NT>
+__device__ __forceinline__ void power_body(DevState* st, PowerLds& S, int k0, int K, int n, int m) {
+  const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+  const int lr = l & 15, lk = l >> 4;                // operand row/column, k-step offset
+  const int ldc = n | 1;
+  double* const out = st->coefA;                     // column kk at out + kk * CMAX
+  // every load of A~, Q and the start vector in flight at once
+  double ra[PC_NA], rq[PC_NQ];
+#pragma unroll
+  for (int u = 0; u < PC_NA; ++u) {
+    const int idx = t + u * PC_THREADS, i = idx % RMAX, j = idx / RMAX;
+    const bool ok = i < n && j < n;
+    const double x = st->At[ok ? j * RMAX + i : 0];
+    ra[u] = ok ? x : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < PC_NQ; ++u) {
+    const int idx = t + u * PC_THREADS, k = idx % LP, c = idx / LP;
+    const bool ok = c < m && k < n;
+    const double x = st->Q[ok ? c * RMAX + k : 0];
+    rq[u] = ok ? x : 0.0;
+  }
+  const double s0 = t < n ? (k0 == 0 ? st->py[t] : st->cfwd[t]) : 0.0;
+  double* P = S.M;
+  double* P2 = S.M + RMAX * LP;
+#pragma unroll
+  for (int u = 0; u < PC_NA; ++u) {
+    const int idx = t + u * PC_THREADS;
+    P[(idx / RMAX) * LP + idx % RMAX] = ra[u];
+  }
+  // c_{k0+1} = A~ c_{k0}, then c_{k0+2} .. c_{k0+16} one at a time by
+  // wave 0 (from a copy of A~ at the end of the column store, which the
+  // doubling overwrites later); for longer chunks the other waves meanwhile
+  // square A~ four times, so that the doubling starts at w = 16 with
+  // P = A~^16.  Wave 0 forms columns [0, 2) in round 0 and [2^q, 2^(q+1))
+  // in round q (column kk holds c_{k0+kk+1}).
+  double* const A1 = S.col + (PC_LCOL - RMAX * LP);
+#pragma unroll
+  for (int u = 0; u < PC_NA; ++u) {
+    const int idx = t + u * PC_THREADS;
+    A1[(idx / RMAX) * LP + idx % RMAX] = ra[u];
+  }
+  if (t < RMAX) S.sv[t] = s0;
+  __syncthreads();
+  const bool dbl = K > 16;
+  const int K0 = min(K, 16);
+  for (int q = 0; q < (dbl ? 4 : 1); ++q) {
+    if (wv == 0) {
+      const int kb = dbl ? (q == 0 ? 0 : 1 << q) : 0, ke = dbl ? 2 << q : K0;   // columns kb .. ke-1
+      for (int kk = kb; kk < ke; ++kk) {
+        const double* const src = kk == 0 ? S.sv : S.col + (kk - 1) * ldc;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 16 * NT; ++j) {
+          const double x = src[j < n ? j : 0];
+          a[j & 3] = __builtin_fma(A1[j * LP + l], j < n ? x : 0.0, a[j & 3]);
+        }
+        if (l < n) S.col[kk * ldc + l] = (a[0] + a[1]) + (a[2] + a[3]);
+      }
+    } else if (dbl) {
+      for (int j = wv - 1; j < NT * NT; j += PC_NWV - 1) {
+        const int it = j % NT, jt = j / NT;
+        const d4_t d = tile_sum<NT>([&](int s) { return P[(4 * s + lk) * LP + it * 16 + lr]; },
+                                    [&](int s) { return P[(jt * 16 + lr) * LP + 4 * s + lk]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P2[(jt * 16 + lr) * LP + it * 16 + 4 * v + lk] = d[v];
+      }
+    }
+    if (dbl) {
+      double* const tmp = P;
+      P = P2;
+      P2 = tmp;
+    }
+    __syncthreads();
+  }
+  for (int w = 16; w < K; w *= 2) {
+    // jobs: columns w .. w+cnt-1 = P (= A~^w) times columns 0 .. cnt-1, as
+    // (16 columns, 16 rows) tiles; then, unless this is the last doubling,
+    // the tiles of P2 = P P (= A~^2w)
+    const int cnt = min(w, K - w);
+    const int jp = (cnt + 15) / 16 * NT;
+    const int js = 2 * w < K ? NT * NT : 0;
+    for (int j = wv; j < jp + js; j += PC_NWV) {
+      if (j < jp) {
+        const int ct = j / NT, it = j % NT;
+        const int c = ct * 16 + lr;
+        const bool cv = c < cnt;
+        const d4_t d = tile_sum<NT>(
+            [&](int s) {
+              const int k = 4 * s + lk;
+              const bool ok = cv && k < n;
+              const double x = S.col[ok ? c * ldc + k : 0];
+              return ok ? x : 0.0;
+            },
+            [&](int s) { return P[(4 * s + lk) * LP + it * 16 + lr]; });
+        const int i = it * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cc = ct * 16 + 4 * v + lk;
+          if (cc < cnt && i < n) S.col[(w + cc) * ldc + i] = d[v];
+        }
+      } else {
+        const int it = (j - jp) % NT, jt = (j - jp) / NT;
+        const d4_t d = tile_sum<NT>([&](int s) { return P[(4 * s + lk) * LP + it * 16 + lr]; },
+                                    [&](int s) { return P[(jt * 16 + lr) * LP + 4 * s + lk]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P2[(jt * 16 + lr) * LP + it * 16 + 4 * v + lk] = d[v];
+      }
+    }
+    if (js) {
+      double* const tmp = P;
+      P = P2;
+      P2 = tmp;
+    }
+    __syncthreads();
+  }
+  if (t < n) st->cfwd[t] = S.col[(K - 1) * ldc + t];
+  double* const sQ = S.M;                            // the powers are done
+#pragma unroll
+  for (int u = 0; u < PC_NQ; ++u) {
+    const int idx = t + u * PC_THREADS;
+    if (idx < CMAX * LP) sQ[idx] = rq[u];
   }
   __syncthreads();
-  if (live && l < n) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += st->V_re[j * RMAX + l] * zr[col][j] - st->V_im[j * RMAX + l] * zi[col][j];
-    cc[col][l] = s;
-  }
-  __syncthreads();
-  if (kk < K) {
-    for (int c = l; c < CMAX; c += 64) {
-      double v = 0.0;
-      if (live && c < m)
-        for (int k = 0; k < n; ++k) v += st->Q[c * RMAX + k] * cc[col][k];
-      st->coefA[kk * CMAX + c] = v;
+  // out column kk = Q c_kk, as (16 columns, 16 rows c) tiles over the rows
+  // c < m (rounded up to 16); the rows above are zero
+  const int CT = (m + 15) / 16;
+  const int jf = (K + 15) / 16 * CT;
+  for (int j = wv; j < jf; j += PC_NWV) {
+    const int ct = j / CT, jt = j % CT;
+    const int kk = ct * 16 + lr;
+    const bool kv = kk < K;
+    const int cq = jt * 16 + lr;
+    const bool qv = cq < CMAX;
+    const d4_t d = tile_sum<NT>(
+        [&](int s) {
+          const int k = 4 * s + lk;
+          const bool ok = kv && k < n;
+          const double x = S.col[ok ? kk * ldc + k : 0];
+          return ok ? x : 0.0;
+        },
+        [&](int s) {
+          const double q = sQ[(qv ? cq : 0) * LP + 4 * s + lk];
+          return qv ? q : 0.0;
+        });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int kc = ct * 16 + 4 * v + lk;
+      if (kc < K && qv) out[kc * CMAX + cq] = d[v];
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (n == 0 || st->eig_status != 0))
-    latch_status(st, n == 0 ? ST_EMPTY : ST_NOCONV);
+  const int c0 = 16 * CT;
+  if (c0 < CMAX)
+    for (int idx = t; idx < K * (CMAX - c0); idx += PC_THREADS)
+      out[(idx / (CMAX - c0)) * CMAX + c0 + idx % (CMAX - c0)] = 0.0;
+}
+
+__device__ __forceinline__ void power_entry(DevState* st, int k0, int K) {
+  __shared__ PowerLds S;
+  const int n = st->r, m = st->m;
+  if (n == 0 || K > coef_chunk(n)) {                // (the host never sends a larger chunk)
+    for (int idx = threadIdx.x; idx < K * CMAX; idx += PC_THREADS) st->coefA[idx] = 0.0;
+    if (threadIdx.x == 0) latch_status(st, n == 0 ? ST_EMPTY : ST_NOCONV);
+    return;
+  }
+  switch ((n + 15) / 16) {
+    case 1: power_body<1>(st, S, k0, K, n, m); break;
+    case 2: power_body<2>(st, S, k0, K, n, m); break;
+    case 3: power_body<3>(st, S, k0, K, n, m); break;
+    default: power_body<4>(st, S, k0, K, n, m); break;
+  }
+}
+
+__global__ __launch_bounds__(PC_THREADS) void k_power_coef(DevState* st, int k0, int K) { power_entry(st, k0, K); }
+
+// The first chunk (k0 = 0) of several streams: one workgroup per entry of a
+// device-resident table of states and step counts.
+__global__ __launch_bounds__(PC_THREADS) void k_power_coef_batch(DevState* const* __restrict__ sts,
+                                                                 const int* __restrict__ Ks) {
+  power_entry(sts[blockIdx.x], 0, Ks[blockIdx.x]);
 }
 
 // Coefficients that materialise the basis: column k of U is S[:, :m] Q[:, k].
@@ -680,23 +801,18 @@ __global__ __launch_bounds__(256) void k_basis_coef(DevState* st) {
 
 __global__ __launch_bounds__(64) void k_eig(DevState* st) { eig_body(st); }
 
-// One workgroup per stream of a device-resident table of states.
-__global__ __launch_bounds__(64) void k_eig_batch(DevState* const* __restrict__ sts) {
-  eig_body(sts[blockIdx.x]);
-}
-
 hipError_t launch_eig(DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_eig, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 
-hipError_t launch_eig_batch(DevState* const* sts, int count, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig_batch, dim3(count), dim3(64), 0, s, sts);
+hipError_t launch_power_coef(DevState* st, int k0, int steps, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_coef, dim3(1), dim3(PC_THREADS), 0, s, st, k0, steps);
   return hipGetLastError();
 }
 
-hipError_t launch_predict_coef(DevState* st, int k0, int steps, hipStream_t s) {
-  hipLaunchKernelGGL(k_predict_coef, dim3((steps + 3) / 4), dim3(256), 0, s, st, k0, steps);
+hipError_t launch_power_coef_batch(DevState* const* sts, const int* steps, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_coef_batch, dim3(count), dim3(PC_THREADS), 0, s, sts, steps);
   return hipGetLastError();
 }
 

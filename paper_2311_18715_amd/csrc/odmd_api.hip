@@ -670,13 +670,15 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   return ODMD_OK;
 }
 
-// Coefficients and read-out of predicted states a+1 .. a+steps (the
-// eigendecomposition has been queued before).
-odmd_status launch_rollout(odmd_t h, int32_t steps, void* out) {
+// Coefficients and read-out of predicted states a+1 .. a+steps, a chunk of
+// coef_chunk(r_max) states at a time (first_done: the first chunk's
+// coefficients are already queued, by a batched launch).
+odmd_status launch_rollout(odmd_t h, int32_t steps, void* out, bool first_done = false) {
   const int es = elem_bytes(h->io);
-  for (int k0 = 0; k0 < steps; k0 += COEF_CHUNK) {
-    const int K = std::min(COEF_CHUNK, steps - k0);
-    HIP_OK(launch_predict_coef(h->st, k0, K, h->stream));
+  const int ch = coef_chunk(h->r_max);
+  for (int k0 = 0; k0 < steps; k0 += ch) {
+    const int K = std::min(ch, steps - k0);
+    if (k0 > 0 || !first_done) HIP_OK(launch_power_coef(h->st, k0, K, h->stream));
     char* o = static_cast<char*>(out) + (int64_t)k0 * h->n * es;
     const odmd_status s = launch_combine_cols(h, o, h->n, K, h->io == ODMD_F32);
     if (s != ODMD_OK) return s;
@@ -1067,7 +1069,6 @@ odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double*
 odmd_status odmd_predict(odmd_t h, int32_t steps, void* out) {
   if (!h || !out || steps < 1) return ODMD_EINVAL;
   HIP_OK(hipSetDevice(h->device));
-  HIP_OK(launch_eig(h->st, h->stream));
   return launch_rollout(h, steps, out);
 }
 
@@ -1085,18 +1086,26 @@ odmd_status odmd_predict_batch(odmd_t* hs, const int32_t* steps, void* const* ou
   {
     std::unique_lock<std::mutex> lk;
     BatchSlot* sl = nullptr;
-    const odmd_status s = acquire_slot(hs[0]->device, (size_t)count * sizeof(DevState*), lk, sl);
+    // the states' table, then the first chunk's step counts
+    const size_t tb = round_up((int64_t)count * sizeof(DevState*), 16);
+    const odmd_status s = acquire_slot(hs[0]->device, tb + (size_t)count * sizeof(int), lk, sl);
     if (s != ODMD_OK) return s;
     DevState** tab = static_cast<DevState**>(sl->host);
-    for (int32_t i = 0; i < count; ++i) tab[i] = hs[i]->st;
-    HIP_OK(hipMemcpyAsync(sl->dev, sl->host, (size_t)count * sizeof(DevState*), hipMemcpyHostToDevice,
+    int* ks = reinterpret_cast<int*>(static_cast<char*>(sl->host) + tb);
+    for (int32_t i = 0; i < count; ++i) {
+      tab[i] = hs[i]->st;
+      ks[i] = std::min(coef_chunk(hs[i]->r_max), (int)steps[i]);
+    }
+    HIP_OK(hipMemcpyAsync(sl->dev, sl->host, tb + (size_t)count * sizeof(int), hipMemcpyHostToDevice,
                           hs[0]->stream));
-    HIP_OK(launch_eig_batch(static_cast<DevState* const*>(sl->dev), count, hs[0]->stream));
+    HIP_OK(launch_power_coef_batch(static_cast<DevState* const*>(sl->dev),
+                                   reinterpret_cast<const int*>(static_cast<char*>(sl->dev) + tb), count,
+                                   hs[0]->stream));
     HIP_OK(hipEventRecord(sl->done, hs[0]->stream));
     sl->used = true;
   }
   for (int32_t i = 0; i < count; ++i) {
-    const odmd_status s = launch_rollout(hs[i], steps[i], outs[i]);
+    const odmd_status s = launch_rollout(hs[i], steps[i], outs[i], true);
     if (s != ODMD_OK) return s;
   }
   return ODMD_OK;

@@ -47,7 +47,20 @@ inline bool valid_shape(const PassShape& sh) {
          sh.max_blocks >= 1 && sh.max_blocks <= 65536;
 }
 constexpr int CORE_THREADS = 1024;
-constexpr int COEF_CHUNK = 512;   // prediction steps per coefficient chunk
+constexpr int COEF_CHUNK = 512;   // prediction steps per coefficient chunk, at most
+// The prediction's power-form coefficients c_k (rank r) of one chunk are
+// kept in LDS with leading dimension r | 1: PC_LCOL doubles hold
+// PC_LCOL / (r | 1) of them; the chunk size for that rank is that count
+// rounded down to whole 16-state blocks of the read-out.
+constexpr int PC_LCOL = 11264;
+inline
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+int coef_chunk(int r) {
+  const int c = PC_LCOL / (r | 1) / 16 * 16;
+  return c < COEF_CHUNK ? c : COEF_CHUNK;
+}
 
 // reduced partial-sum record layout (doubles)
 constexpr int P_SUE = 0;             // S^T e         [0, CMAX)
@@ -100,7 +113,7 @@ struct DevState {
   double V_re[RMAX * RMAX], V_im[RMAX * RMAX];
   // read-out coefficients of one chunk: rows j < m, column k at coefA + k*CMAX
   double coefA[CMAX * COEF_CHUNK];
-  double bt_re[RMAX], bt_im[RMAX];   // b~ = V^-1 p_y
+  double cfwd[RMAX];    // A~^k p_y at the end of the last prediction chunk
 };
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

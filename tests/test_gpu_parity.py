@@ -88,7 +88,8 @@ def test_planted_small_every_step(core_svd):
 def test_rollout_lengths_against_the_oracle(steps):
     """Rollouts of every length class of the read-out: a few states (one
     row per lane), one to eight 16-state blocks, several 128-state blocks,
-    and more states than one coefficient chunk (512): each state within
+    and more states than one coefficient chunk (512 at this rank cap), with
+    the coefficients' serial start (up to 16 steps) and doubling: each state within
     1e-9 of the oracle's, relative to the largest state (the planted modes
     decay: the last of 1100 states is 1e-9 of the first), on a ragged n."""
     s = synth.random_planted(3001, 6, seed=913, noise=1e-9)
@@ -97,6 +98,24 @@ def test_rollout_lengths_against_the_oracle(steps):
     pg = g.predict(steps).cpu().numpy()
     po = o.predict(steps)
     assert pg.shape == po.shape == (steps, 3001)
+    err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1).max()
+    assert err.max() < 1e-9
+
+
+@pytest.mark.parametrize("r_max,steps", [(24, 50), (40, 600), (64, 400)])
+def test_rollout_chunks_of_higher_ranks_against_the_oracle(r_max, steps):
+    """The prediction's coefficients are formed as powers of A~ applied to
+    U^T x_a, a chunk of steps at a time whose length falls with the rank cap
+    (r_max 40: 272 steps, 64: 160): a noisy wake stream at ranks 24, 40 and
+    64 (two to four 16-row tiles), rollouts across two and three chunks,
+    each state within 1e-9 of the oracle's eigenvector-form rollout relative
+    to the largest state, on a ragged n."""
+    s = synth.wake(nx=61, ny=39, noise=1e-6)
+    X = s.snapshots(0, 200)
+    g, o = run_both(X, r_max, 1e-8)
+    assert g.info().r == o.r == r_max
+    pg = g.predict(steps).cpu().numpy()
+    po = o.predict(steps)
     err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1).max()
     assert err.max() < 1e-9
 
