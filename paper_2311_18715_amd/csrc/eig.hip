@@ -597,23 +597,33 @@ static_assert(CMAX * LP <= 2 * RMAX * LP, "Q fits the power buffers");
 // One 16 x 16 tile: sum over the k-steps s < 4 NT of A(s) B(s), where a(s)
 // and b(s) give this lane's operands; two accumulators over alternate
 // k-steps.  NT 16-row tiles cover the rank (entries past it are zero).
+// Every operand is loaded before the first product (the scheduling barrier
+// keeps the compiler from spreading the loads between the products, where
+// each pair of products waited for the next loads).
 template <int NT, class FA, class FB>
 __device__ __forceinline__ d4_t tile_sum(FA a, FB b) {
+  double av[4 * NT], bv[4 * NT];
+#pragma unroll
+  for (int s = 0; s < 4 * NT; ++s) {
+    av[s] = a(s);
+    bv[s] = b(s);
+  }
+  __builtin_amdgcn_sched_barrier(0);
   d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
 #pragma unroll
   for (int s = 0; s < 4 * NT; s += 2) {
-    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a(s), b(s), d0, 0, 0, 0);
-    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a(s + 1), b(s + 1), d1, 0, 0, 0);
+    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], d1, 0, 0, 0);
   }
   return d0 + d1;
 }
 
 template <int NT>
-__device__ __forceinline__ void power_body(DevState* st, PowerLds& S, int k0, int K, int n, int m) {
+__device__ __forceinline__ void power_body(DevState* st, PowerLds& S, int k0, int K, int koff, int n, int m) {
   const int t = threadIdx.x, l = t & 63, wv = t >> 6;
   const int lr = l & 15, lk = l >> 4;                // operand row/column, k-step offset
   const int ldc = n | 1;
-  double* const out = st->coefA;                     // column kk at out + kk * CMAX
+  double* const out = st->coefA + koff * CMAX;       // column kk at out + kk * CMAX
   // every load of A~, Q and the start vector in flight at once
   double ra[PC_NA], rq[PC_NQ];
 #pragma unroll
@@ -638,52 +648,16 @@ __device__ __forceinline__ void power_body(DevState* st, PowerLds& S, int k0, in
     const int idx = t + u * PC_THREADS;
     P[(idx / RMAX) * LP + idx % RMAX] = ra[u];
   }
-  // c_{k0+1} = A~ c_{k0}, then c_{k0+2} .. c_{k0+16} one at a time by
-  // wave 0 (from a copy of A~ at the end of the column store, which the
-  // doubling overwrites later); for longer chunks the other waves meanwhile
-  // square A~ four times, so that the doubling starts at w = 16 with
-  // P = A~^16.  Wave 0 forms columns [0, 2) in round 0 and [2^q, 2^(q+1))
-  // in round q (column kk holds c_{k0+kk+1}).
-  double* const A1 = S.col + (PC_LCOL - RMAX * LP);
-#pragma unroll
-  for (int u = 0; u < PC_NA; ++u) {
-    const int idx = t + u * PC_THREADS;
-    A1[(idx / RMAX) * LP + idx % RMAX] = ra[u];
-  }
   if (t < RMAX) S.sv[t] = s0;
   __syncthreads();
-  const bool dbl = K > 16;
-  const int K0 = min(K, 16);
-  for (int q = 0; q < (dbl ? 4 : 1); ++q) {
-    if (wv == 0) {
-      const int kb = dbl ? (q == 0 ? 0 : 1 << q) : 0, ke = dbl ? 2 << q : K0;   // columns kb .. ke-1
-      for (int kk = kb; kk < ke; ++kk) {
-        const double* const src = kk == 0 ? S.sv : S.col + (kk - 1) * ldc;
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < n) {                                       // c_{k0+1} = A~ c_{k0}
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < 16 * NT; ++j) {
-          const double x = src[j < n ? j : 0];
-          a[j & 3] = __builtin_fma(A1[j * LP + l], j < n ? x : 0.0, a[j & 3]);
-        }
-        if (l < n) S.col[kk * ldc + l] = (a[0] + a[1]) + (a[2] + a[3]);
-      }
-    } else if (dbl) {
-      for (int j = wv - 1; j < NT * NT; j += PC_NWV - 1) {
-        const int it = j % NT, jt = j / NT;
-        const d4_t d = tile_sum<NT>([&](int s) { return P[(4 * s + lk) * LP + it * 16 + lr]; },
-                                    [&](int s) { return P[(jt * 16 + lr) * LP + 4 * s + lk]; });
-#pragma unroll
-        for (int v = 0; v < 4; ++v) P2[(jt * 16 + lr) * LP + it * 16 + 4 * v + lk] = d[v];
-      }
-    }
-    if (dbl) {
-      double* const tmp = P;
-      P = P2;
-      P2 = tmp;
-    }
-    __syncthreads();
+    for (int j = 0; j < 16 * NT; ++j) a[j & 3] = __builtin_fma(P[j * LP + t], S.sv[j], a[j & 3]);
+    S.col[t] = (a[0] + a[1]) + (a[2] + a[3]);
   }
-  for (int w = 16; w < K; w *= 2) {
+  __syncthreads();
+  for (int w = 1; w < K; w *= 2) {
     // jobs: columns w .. w+cnt-1 = P (= A~^w) times columns 0 .. cnt-1, as
     // (16 columns, 16 rows) tiles; then, unless this is the last doubling,
     // the tiles of P2 = P P (= A~^2w)
@@ -765,29 +739,32 @@ __device__ __forceinline__ void power_body(DevState* st, PowerLds& S, int k0, in
       out[(idx / (CMAX - c0)) * CMAX + c0 + idx % (CMAX - c0)] = 0.0;
 }
 
-__device__ __forceinline__ void power_entry(DevState* st, int k0, int K) {
+__device__ __forceinline__ void power_entry(DevState* st, int k0, int K, int koff) {
   __shared__ PowerLds S;
   const int n = st->r, m = st->m;
-  if (n == 0 || K > coef_chunk(n)) {                // (the host never sends a larger chunk)
-    for (int idx = threadIdx.x; idx < K * CMAX; idx += PC_THREADS) st->coefA[idx] = 0.0;
+  if (n == 0 || K > coef_chunk(n) || koff + K > COEF_CHUNK) {   // (the host sends neither)
+    for (int idx = threadIdx.x; idx < K * CMAX && koff + idx / CMAX < COEF_CHUNK; idx += PC_THREADS)
+      st->coefA[koff * CMAX + idx] = 0.0;
     if (threadIdx.x == 0) latch_status(st, n == 0 ? ST_EMPTY : ST_NOCONV);
     return;
   }
   switch ((n + 15) / 16) {
-    case 1: power_body<1>(st, S, k0, K, n, m); break;
-    case 2: power_body<2>(st, S, k0, K, n, m); break;
-    case 3: power_body<3>(st, S, k0, K, n, m); break;
-    default: power_body<4>(st, S, k0, K, n, m); break;
+    case 1: power_body<1>(st, S, k0, K, koff, n, m); break;
+    case 2: power_body<2>(st, S, k0, K, koff, n, m); break;
+    case 3: power_body<3>(st, S, k0, K, koff, n, m); break;
+    default: power_body<4>(st, S, k0, K, koff, n, m); break;
   }
 }
 
-__global__ __launch_bounds__(PC_THREADS) void k_power_coef(DevState* st, int k0, int K) { power_entry(st, k0, K); }
+__global__ __launch_bounds__(PC_THREADS) void k_power_coef(DevState* st, int k0, int K, int koff) {
+  power_entry(st, k0, K, koff);
+}
 
 // The first chunk (k0 = 0) of several streams: one workgroup per entry of a
 // device-resident table of states and step counts.
 __global__ __launch_bounds__(PC_THREADS) void k_power_coef_batch(DevState* const* __restrict__ sts,
                                                                  const int* __restrict__ Ks) {
-  power_entry(sts[blockIdx.x], 0, Ks[blockIdx.x]);
+  power_entry(sts[blockIdx.x], 0, Ks[blockIdx.x], 0);
 }
 
 // Coefficients that materialise the basis: column k of U is S[:, :m] Q[:, k].
@@ -806,8 +783,8 @@ hipError_t launch_eig(DevState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_power_coef(DevState* st, int k0, int steps, hipStream_t s) {
-  hipLaunchKernelGGL(k_power_coef, dim3(1), dim3(PC_THREADS), 0, s, st, k0, steps);
+hipError_t launch_power_coef(DevState* st, int k0, int steps, int koff, hipStream_t s) {
+  hipLaunchKernelGGL(k_power_coef, dim3(1), dim3(PC_THREADS), 0, s, st, k0, steps, koff);
   return hipGetLastError();
 }
 

@@ -670,15 +670,17 @@ odmd_status launch_combine_cols(odmd_t h, void* out, int64_t ldo, int K, bool ou
   return ODMD_OK;
 }
 
-// Coefficients and read-out of predicted states a+1 .. a+steps, a chunk of
-// coef_chunk(r_max) states at a time (first_done: the first chunk's
-// coefficients are already queued, by a batched launch).
+// Coefficients and read-out of predicted states a+1 .. a+steps, COEF_CHUNK
+// states per read-out launch; their coefficients in launches of
+// coef_chunk(r_max) states, each starting where the last one ended
+// (first_done: the first of them is already queued, by a batched launch).
 odmd_status launch_rollout(odmd_t h, int32_t steps, void* out, bool first_done = false) {
   const int es = elem_bytes(h->io);
   const int ch = coef_chunk(h->r_max);
-  for (int k0 = 0; k0 < steps; k0 += ch) {
-    const int K = std::min(ch, steps - k0);
-    if (k0 > 0 || !first_done) HIP_OK(launch_power_coef(h->st, k0, K, h->stream));
+  for (int k0 = 0; k0 < steps; k0 += COEF_CHUNK) {
+    const int K = std::min(COEF_CHUNK, steps - k0);
+    for (int j = 0; j < K; j += ch)
+      if (k0 + j > 0 || !first_done) HIP_OK(launch_power_coef(h->st, k0 + j, std::min(ch, K - j), j, h->stream));
     char* o = static_cast<char*>(out) + (int64_t)k0 * h->n * es;
     const odmd_status s = launch_combine_cols(h, o, h->n, K, h->io == ODMD_F32);
     if (s != ODMD_OK) return s;

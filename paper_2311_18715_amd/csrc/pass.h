@@ -125,7 +125,8 @@ hipError_t launch_combine(const CombineArgs& c, int basis, int out_f32, int rb, 
 hipError_t launch_basis_coef(DevState* st, hipStream_t s);
 hipError_t launch_eig(DevState* st, hipStream_t s);
 // prediction coefficients of steps k0+1 .. k0+steps (steps <= coef_chunk(r_max))
-hipError_t launch_power_coef(DevState* st, int k0, int steps, hipStream_t s);
+// into columns koff .. koff+steps-1 of the read-out coefficients
+hipError_t launch_power_coef(DevState* st, int k0, int steps, int koff, hipStream_t s);
 // the first chunk of several streams: one workgroup per entry of
 // device-resident tables of states and step counts
 hipError_t launch_power_coef_batch(DevState* const* sts, const int* steps, int count, hipStream_t s);
