@@ -364,9 +364,9 @@ class Plan:
 
 
 def predict_batch(models, steps):
-    """odmd_predict_batch: predicted states of several streams, their
-    eigendecompositions in one launch.  Returns one (steps_i, n_i) device
-    tensor per model."""
+    """odmd_predict_batch: predicted states of several streams, the
+    coefficients of every stream's first chunk of states in one launch.
+    Returns one (steps_i, n_i) device tensor per model."""
     import torch
     n = len(models)
     steps = [int(s) for s in steps]

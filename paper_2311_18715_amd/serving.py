@@ -179,8 +179,8 @@ class Server:
         leading updates (at most max_layers of them) and, if one follows, a
         prediction.  The k-th updates of the streams form layer k (one
         batched launch per layer); the predictions go last, in one batched
-        launch (one eigendecomposition launch for all), each after its own
-        stream's updates.  Predictions past pred_bytes of output in the
+        call (one coefficient launch for all), each after its own stream's
+        updates.  Predictions past pred_bytes of output in the
         round wait for the next one.  Returns the number of requests
         launched."""
         self.poll()

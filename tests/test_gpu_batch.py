@@ -78,8 +78,13 @@ def test_predict_batch_equals_individual():
     A = [ODMD(n, rmax, 1e-10, basis=b) for (n, _, rmax, b) in SPECS]
     for k in range(steps):
         update_batch(A, [Xd[k] for _, Xd in data], [Xd[k + 1] for _, Xd in data])
-    one = [g.predict(17 + i) for i, g in enumerate(A)]
-    many = predict_batch(A, [17 + i for i in range(len(A))])
+    # 17 + i states, and a long rollout for every third stream: more states
+    # than one coefficient launch holds at its rank cap (the batched launch
+    # forms the first chunk, the rest follow per stream) and than one
+    # read-out launch (512)
+    ks = [17 + i if i % 3 else 600 + 7 * i for i in range(len(A))]
+    one = [g.predict(k) for g, k in zip(A, ks)]
+    many = predict_batch(A, ks)
     for a, b in zip(one, many):
         assert torch.equal(a, b)
     with pytest.raises(Exception):
