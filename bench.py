@@ -751,8 +751,9 @@ def serving_section(torch):
     random admitted, unfinished stream: 90 % its next update, 10 % a
     100-state prediction (of a stream with at least one update).  Reports
     the achieved rates, p50/p99 latency of updates and predictions
-    (submission to observed completion), requests per round, and, for a
-    20 GB budget that holds only part of the streams, the admission waits.
+    (submission to observed completion), requests per round, the host time
+    of the round loop and of the library calls in it, and, for a 20 GB
+    budget that holds only part of the streams, the admission waits.
     Snapshots are formed on the device beforehand (device Gaussian modes,
     FP32); prediction outputs are freed as their rounds complete."""
     from paper_2311_18715_amd import synth
@@ -841,7 +842,8 @@ def serving_section(torch):
             "mean_update_batch": round(float(np.mean(S.batch_sizes)), 1),
             "requests_per_round": round(n_req / max(1, S.rounds), 1),
             "errors": errors,
-            "peak_state_bytes": S.peak_used}
+            "peak_state_bytes": S.peak_used,
+            "host_s": {"run": round(dt, 3), **{k: round(v, 3) for k, v in S.host_s.items()}}}
         print(f"serving budget {budget >> 30} GB, rate {rate:g}: {res}", file=sys.stderr, flush=True)
         del S
         torch.cuda.empty_cache()

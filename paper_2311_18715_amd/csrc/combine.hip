@@ -22,10 +22,13 @@
 // are the sums; the output is rounded once, to its type.  A workgroup covers
 // a contiguous share of the rows (about CB_RPW or more: the grid holds no more
 // workgroups than the GPU runs at once) and 16 NS states; the stored
-// columns are read once per 16 NS states.
+// columns are read once per 16 NS states.  FP32 states from FP32 or BF16
+// stored columns take k_combine32 instead (FP32 matrix cores, 128-byte
+// stores); a few states (K <= 4) take k_combine_rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -37,6 +40,9 @@
 namespace odmd {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float to_float_value(float v) { return v; }
+__device__ __forceinline__ float to_float_value(bf16 v) { return __uint_as_float((uint32_t)v.bits << 16); }
 
 constexpr int CB_THREADS = 256;          // four wavefronts
 constexpr int CB_RPW = 512;              // rows per workgroup, at least
@@ -118,6 +124,86 @@ __global__ __launch_bounds__(CB_THREADS) void k_combine(CombineArgs c) {
   }
 }
 
+// FP32 states from FP32 or BF16 stored columns: the same product on the
+// FP32 matrix cores (32x32x2, twice the FP64 rate), which also writes
+// whole 128-byte lines: a wavefront takes 32 consecutive rows of one tile
+// (lane l supplies row l%32 of stored column 2 kk + l/32; 32 lanes read a
+// 128-byte line of a column), and register r of lane l holds state
+// 8 (r/4) + 4 (l/32) + r%4 of a 32-state block at row l%32, so 32 lanes
+// write 32 consecutive rows of one state.  The stored values are exact in
+// FP32; the coefficients are rounded to FP32 and the sums are FP32 (about
+// m FP32 roundings per state against one for the FP64 path: the output is
+// FP32 either way).  NS 32-state blocks per workgroup; with one block the
+// k-steps alternate between two accumulators, so that two product chains
+// are in flight.
+template <typename TS, int RB, int NS>
+__global__ __launch_bounds__(CB_THREADS, 2) void k_combine32(CombineArgs c) {
+  constexpr int KK = RB / 2;                 // k-steps over the stored columns
+  constexpr int NA = NS == 1 ? 2 : 1;        // accumulators per block
+  constexpr int NW = CB_THREADS / 64;
+  typedef float f16v __attribute__((ext_vector_type(16)));
+  const DevState* __restrict__ st = c.st;
+  const int m = st->m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int k0 = blockIdx.y * (32 * NS);
+
+  // sC[s][kk][lane] = coef(state k0 + 32 s + lane%32, column 2 kk + lane/32)
+  __shared__ float sC[NS][KK][64];
+  for (int idx = threadIdx.x; idx < NS * KK * 64; idx += CB_THREADS) {
+    const int ln = idx & 63, kk = (idx >> 6) % KK, s = (idx >> 6) / KK;
+    const int k = k0 + 32 * s + (ln & 31), col = 2 * kk + (ln >> 5);
+    sC[s][kk][ln] = (k < c.K && col < m) ? (float)st->coefA[k * CMAX + col] : 0.f;
+  }
+
+  const TS* __restrict__ Us = static_cast<const TS*>(c.Us);
+  float* __restrict__ out = static_cast<float*>(c.out);
+  const int64_t units = (c.n + 31) / 32;     // 32-row units (two per 64-row tile)
+  const int64_t ub = (int64_t)blockIdx.x * units / gridDim.x;
+  const int64_t ue = (int64_t)(blockIdx.x + 1) * units / gridDim.x;
+  const int64_t r0 = 32 * ub;
+  const int nunit = (int)(ue - ub);
+  const int kmax = (m + 1) / 2;              // live k-steps (uniform)
+  auto load = [&](int u, float (&B)[KK]) {
+    const int64_t row0 = r0 + 32 * u;
+    const TS* __restrict__ T = Us + (row0 >> 6) * (int64_t)c.ct * 64 + (row0 & 63);
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+      if (kk < kmax) B[kk] = to_float_value(T[(2 * kk + h) * 64 + l32]);
+  };
+  float B[KK];
+  __syncthreads();
+  for (int u = wave; u < nunit; u += NW) {
+    load(u, B);                              // two waves per SIMD hide the loads
+    f16v d[NS][NA];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) d[s][a] = f16v{};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      if (kk < kmax) {                       // uniform
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          d[s][kk % NA] = __builtin_amdgcn_mfma_f32_32x32x2f32(sC[s][kk][lane], B[kk], d[s][kk % NA], 0, 0, 0);
+      }
+    }
+    const int64_t row = r0 + 32 * u + l32;
+    if (row < c.n) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        f16v e = d[s][0];
+        if (NA == 2) e += d[s][NA - 1];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int k = k0 + 32 * s + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (k < c.K) __builtin_nontemporal_store(e[r], out + (int64_t)k * c.ldo + row);
+        }
+      }
+    }
+  }
+}
+
 // A few states (a one-step prediction, Sec. 2.3's u(t + dt)): bound by the
 // read of the stored columns, not by the flops.  One row per lane (a wave
 // reads 64 consecutive rows of a column, one 64-row tile), the coefficients
@@ -196,6 +282,21 @@ static hipError_t launch_ns(const CombineArgs& c, int rb, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename TS, int NS>
+static hipError_t launch_ns32(const CombineArgs& c, int rb, hipStream_t s) {
+  const dim3 block(CB_THREADS);
+  switch (rb) {
+#define ODMD_CASE(RB) \
+  case RB: hipLaunchKernelGGL((k_combine32<TS, RB, NS>), combine_grid(k_combine32<TS, RB, NS>, c, 2 * NS), \
+                              block, 0, s, c); break;
+    ODMD_CASE(8) ODMD_CASE(16) ODMD_CASE(24) ODMD_CASE(32) ODMD_CASE(40) ODMD_CASE(48)
+    ODMD_CASE(56) ODMD_CASE(64) ODMD_CASE(72)
+#undef ODMD_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename TS, typename TO>
 static hipError_t launch_rows(const CombineArgs& c, int rb, hipStream_t s) {
   const dim3 grid((unsigned)((c.n + 255) / 256)), block(256);
@@ -213,6 +314,11 @@ static hipError_t launch_rows(const CombineArgs& c, int rb, hipStream_t s) {
 template <typename TS, typename TO>
 static hipError_t launch_t(const CombineArgs& c, int rb, hipStream_t s) {
   if (c.K <= CR_KMAX) return launch_rows<TS, TO>(c, rb, s);
+  if constexpr (std::is_same<TO, float>::value && !std::is_same<TS, double>::value) {
+    if (c.K <= 32) return launch_ns32<TS, 1>(c, rb, s);
+    if (c.K <= 64) return launch_ns32<TS, 2>(c, rb, s);
+    return launch_ns32<TS, 4>(c, rb, s);
+  }
   // more 16-state blocks per workgroup: more independent accumulator
   // chains per wave (the FP64 matrix-core chains are latency-bound: 500
   // states at n = 160,000 and 56 columns took 182 us of matrix-core time

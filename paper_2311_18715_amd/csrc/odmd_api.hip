@@ -333,9 +333,13 @@ odmd_status launch_update(odmd_t h, const void* x, const void* y) {
   return ODMD_OK;
 }
 
-// Descriptor tables of batched launches: a small ring of pinned host / device
-// buffer pairs per device; a slot is reused only after the copy recorded on
-// it has completed.
+// Descriptor tables of batched launches: a ring of pinned host / device
+// buffer pairs per device; a slot is reused only after the kernels that read
+// its table have run.  The ring's depth bounds how many batched calls the
+// host can queue ahead of the device: with four slots a request loop whose
+// rounds issue eight batched updates and a batched prediction waited on
+// the device every few calls, and the device drained while the host
+// assembled the next round.
 struct BatchSlot {
   void* host = nullptr;
   void* dev = nullptr;
@@ -344,9 +348,10 @@ struct BatchSlot {
   bool used = false;
 };
 constexpr int NSIDE = 4;   // side streams for the pass launches of one batch
+constexpr int NSLOT = 32;  // staging slots per device
 struct BatchRing {
   std::mutex mu;
-  BatchSlot slot[4];
+  BatchSlot slot[NSLOT];
   int next = 0;
   // The pass launches of a batch's groups are independent: they go to side
   // streams (default priority) so that one launch's tail overlaps the next
@@ -381,7 +386,7 @@ odmd_status acquire_slot(int device, size_t bytes, std::unique_lock<std::mutex>&
     *ring_out = ring;
   }
   BatchSlot& sl = ring->slot[ring->next];
-  ring->next = (ring->next + 1) % 4;
+  ring->next = (ring->next + 1) % NSLOT;
   if (sl.used) HIP_OK(hipEventSynchronize(sl.done));
   if (sl.cap < bytes) {
     if (sl.host) (void)hipHostFree(sl.host);

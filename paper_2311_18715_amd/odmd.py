@@ -363,14 +363,21 @@ class Plan:
             pass
 
 
-def predict_batch(models, steps):
+def predict_batch(models, steps, outs=None):
     """odmd_predict_batch: predicted states of several streams, the
     coefficients of every stream's first chunk of states in one launch.
-    Returns one (steps_i, n_i) device tensor per model."""
+    Returns one (steps_i, n_i) device tensor per model: outs (contiguous
+    tensors of those shapes and the models' output types) or new ones."""
     import torch
     n = len(models)
     steps = [int(s) for s in steps]
-    outs = [torch.empty((s, m.n), dtype=m.dtype, device="cuda") for m, s in zip(models, steps)]
+    if outs is None:
+        outs = [torch.empty((s, m.n), dtype=m.dtype, device="cuda") for m, s in zip(models, steps)]
+    else:
+        outs = list(outs)
+        if len(outs) != n or any(tuple(o.shape) != (s, m.n) or o.dtype != m.dtype or not o.is_contiguous()
+                                 for o, m, s in zip(outs, models, steps)):
+            raise ValueError("predict_batch: outs must match the models' shapes and types")
     H = (ctypes.c_void_p * n)(*[m.handle for m in models])
     S = (ctypes.c_int32 * n)(*steps)
     O = (ctypes.c_void_p * n)(*[_dptr(o) for o in outs])

@@ -96,6 +96,11 @@ class Server:
         self.max_inflight = max(1, int(max_inflight))
         self.keep_outputs = bool(keep_outputs)
         self.pred_bytes = int(pred_bytes)    # prediction output per round (FP64 bound)
+        # keep_outputs=False: a round's prediction outputs are views of one
+        # of max_inflight + 1 arenas of pred_bytes (a round reuses the arena
+        # of a round that has finished), instead of an allocation each,
+        # which under memory churn made the allocator synchronise
+        self._arenas: List = []
         self.active: Dict[int, _Stream] = {}    # admitted streams with queued work or closing
         self.budget = int(budget_bytes)
         self.used = 0
@@ -106,6 +111,10 @@ class Server:
         self.completed: List[Request] = []
         self.rounds = 0
         self.batch_sizes: List[int] = []
+        # host seconds spent in pump() and, inside it, in the library's
+        # batched update and prediction calls (which also wait when their
+        # staging buffers are still in use by queued device work)
+        self.host_s = {"pump": 0.0, "update_batch": 0.0, "predict_batch": 0.0}
 
     # ---- streams -------------------------------------------------------
     def open(self, sid: int, n: int, r_max: int, tol: float, basis: str = "f32",
@@ -183,6 +192,7 @@ class Server:
         updates.  Predictions past pred_bytes of output in the
         round wait for the next one.  Returns the number of requests
         launched."""
+        t_pump = self.clock()
         self.poll()
         while len(self.inflight) >= self.max_inflight:
             self.inflight[0][0].synchronize()
@@ -221,17 +231,22 @@ class Server:
             H = self.B.handle_array([st.model for st, _ in ups])
             xp = np.fromiter((r.x.data_ptr() for _, r in ups), dtype=np.uint64, count=len(ups))
             yp = np.fromiter((r.y.data_ptr() for _, r in ups), dtype=np.uint64, count=len(ups))
+            t = self.clock()
             self.B.update_batch_ptrs(H, xp, yp)
+            self.host_s["update_batch"] += self.clock() - t
             launched.extend(r for _, r in ups)
             self.batch_sizes.append(len(ups))
         if preds:
+            t = self.clock()
             try:
                 outs = self.B.predict_batch([st.model for st, _ in preds],
-                                            [r.steps for _, r in preds])
+                                            [r.steps for _, r in preds],
+                                            **self._arena_outs(preds))
             except Exception as e:
                 outs = [None] * len(preds)
                 for _, r in preds:
                     r.error = str(e)
+            self.host_s["predict_batch"] += self.clock() - t
             for (_, r), o in zip(preds, outs):
                 r.out = o
             launched.extend(r for _, r in preds)
@@ -244,7 +259,27 @@ class Server:
             ev.record()
             self.inflight.append((ev, launched, members))
             self.rounds += 1
+        self.host_s["pump"] += self.clock() - t_pump
         return len(launched)
+
+    def _arena_outs(self, preds) -> dict:
+        """outs= for predict_batch from this round's arena, or {} (new
+        tensors) when outputs are kept or the round's outputs exceed it."""
+        if self.keep_outputs:
+            return {}
+        sizes = [(r.steps, st.n, st.model.dtype) for st, r in preds]
+        nbytes = [s * n * (8 if dt == self.torch.float64 else 4) for s, n, dt in sizes]
+        offs, o = [], 0
+        for b in nbytes:
+            offs.append(o)
+            o += (b + 255) // 256 * 256
+        if o > self.pred_bytes:
+            return {}
+        k = self.rounds % (self.max_inflight + 1)
+        while len(self._arenas) <= k:
+            self._arenas.append(self.torch.empty(self.pred_bytes, dtype=self.torch.uint8, device="cuda"))
+        a = self._arenas[k]
+        return {"outs": [a[o:o + b].view(dt).view(s, n) for o, b, (s, n, dt) in zip(offs, nbytes, sizes)]}
 
     def poll(self) -> None:
         """Mark the requests of finished rounds done, with the errors their

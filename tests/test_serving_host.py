@@ -86,7 +86,7 @@ class FakeBackend:
     def status_name(code):
         return {4: "ENONFINITE", 6: "ESEQ"}.get(code, str(code))
 
-    def predict_batch(self, models, steps):
+    def predict_batch(self, models, steps, outs=None):
         return [m.predict(s) for m, s in zip(models, steps)]
 
     def handle_array(self, models):
