@@ -101,6 +101,9 @@ class Server:
         # of a round that has finished), instead of an allocation each,
         # which under memory churn made the allocator synchronise
         self._arenas: List = []
+        if not self.keep_outputs:            # allocated up front, not inside the request loop
+            self._arenas = [self.torch.empty(self.pred_bytes, dtype=self.torch.uint8, device="cuda")
+                            for _ in range(self.max_inflight + 1)]
         self.active: Dict[int, _Stream] = {}    # admitted streams with queued work or closing
         self.budget = int(budget_bytes)
         self.used = 0
