@@ -169,3 +169,55 @@ def test_release_without_waiting_reuses_memory_safely():
             g.close(wait=False)
         for lam, sig in outs:
             assert np.array_equal(lam, lam_ref) and np.array_equal(sig, sig_ref)
+
+
+def test_prediction_arenas_hold_the_same_states():
+    """keep_outputs=False: a round's predictions are written into views of
+    one of the server's preallocated arenas (rotated over max_inflight + 1
+    rounds).  Taken right after their round, they equal the predictions of
+    the same streams run alone, bit for bit, round after round (every arena
+    reused several times); a prediction larger than an arena gets its own
+    tensor."""
+    import types
+    from paper_2311_18715_amd import odmd as B
+    data = streams()[:4]
+    calls = []
+
+    def predict_batch(models, steps, outs=None):
+        res = B.predict_batch(models, steps, outs=outs)
+        calls.append((outs is not None, list(models), res))
+        return res
+
+    proxy = types.SimpleNamespace(**{k: getattr(B, k) for k in dir(B) if not k.startswith("__")})
+    proxy.predict_batch = predict_batch
+    # arenas of 4 MB: the four streams' 9-state predictions (about 1.3 MB)
+    # fit; a 64-state prediction of the n = 20000 stream (5.1 MB) does not
+    S = Server(10 ** 10, backend=proxy, keep_outputs=False, max_inflight=2, pred_bytes=4 << 20)
+    twins = []
+    for i in range(4):
+        n, _, rmax, basis, _ = SPECS[i]
+        S.open(i, n, rmax, 1e-8, basis)
+        twins.append(ODMD(n, rmax, 1e-8, basis=basis))
+    for k in range(12):
+        for i in range(4):
+            S.submit_update(i, data[i][k], data[i][k + 1])
+            S.submit_predict(i, STEPS)
+            twins[i].update(data[i][k], data[i][k + 1])
+        before = len(calls)
+        S.pump()
+        torch.cuda.synchronize()
+        assert len(calls) == before + 1
+        used_arena, models, outs = calls[-1]
+        assert used_arena and len(outs) == 4
+        got = [o.clone() for o in outs]
+        for i, g in enumerate(got):
+            assert torch.equal(g, twins[i].predict(STEPS)), f"round {k}, stream {i}"
+    S.submit_predict(2, 64)
+    S.pump()
+    torch.cuda.synchronize()
+    used_arena, models, outs = calls[-1]
+    assert not used_arena and torch.equal(outs[0], twins[2].predict(64))
+    S.drain()
+    assert all(r.done and r.error is None and r.out is None for r in S.completed)
+    for t in twins:
+        t.close()
