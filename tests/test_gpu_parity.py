@@ -401,3 +401,21 @@ def test_full_size_wake_all_updates():
     err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1)
     print(f"rollout over 500 states: max relative difference {err.max():.2e}", flush=True)
     assert err.max() < 1e-9
+
+
+def test_prediction_on_a_defective_operator():
+    """A stream whose operator has a Jordan block (A~ without a full set of
+    eigenvectors: cond(V) about 2e8).  The GPU forms the prediction from
+    powers of A~, so it stays the exact continuation of the linear data:
+    60 states within 1e-10 of the true future (relative to the largest
+    state) and of the oracle's power-form rollout, where the eigenvector
+    form of the oracle is off by about 2e-9."""
+    from test_oracle_pins import _jordan_stream
+    X, fut = _jordan_stream()
+    g, o = run_both(X, 8, 1e-10)
+    assert g.info().r == o.r == 4
+    pg = g.predict(60).cpu().numpy()
+    scale = np.linalg.norm(fut, axis=0).max()
+    assert np.linalg.norm(pg - fut.T, axis=1).max() < 1e-10 * scale
+    pw = O.rollout_power(o.U, o.atilde(), o.p_y, 60)
+    assert np.linalg.norm(pg - pw, axis=1).max() < 1e-10 * scale

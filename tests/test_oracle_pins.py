@@ -517,3 +517,36 @@ def test_subspace_angle_planted_mistakes_are_caught(monkeypatch):
             failed |= abs(O.subspace_angle(A, B) - max(thetas)) > 1e-12 * max(thetas) + 1e-14
         monkeypatch.undo()
         assert failed, bad
+
+
+def _jordan_stream(n=1500, steps=41, seed=29):
+    """x_k = P M^k c with M = diag(J, 0.99 R(0.3)), J = [[0.97, 1], [0, 0.97]]
+    (a Jordan block: the operator on span P has no full set of
+    eigenvectors)."""
+    g = np.random.default_rng(seed)
+    P = g.standard_normal((n, 4)) / np.sqrt(n)
+    M = np.zeros((4, 4))
+    M[:2, :2] = [[0.97, 1.0], [0.0, 0.97]]
+    c, s = np.cos(0.3), np.sin(0.3)
+    M[2:, 2:] = 0.99 * np.array([[c, -s], [s, c]])
+    z = np.array([1.0, 1.0, 1.0, 0.5])
+    X = np.empty((n, steps + 60))
+    for k in range(steps + 60):
+        X[:, k] = P @ z
+        z = M @ z
+    return X[:, :steps], X[:, steps:]
+
+
+def test_power_rollout_on_a_defective_operator():
+    """Where A~ has no full set of eigenvectors the eigenvector form of the
+    prediction loses accuracy (V nearly singular), while U A~^k U^T x_a is
+    still the exact continuation of linear data: rollout_power matches the
+    true future states to 1e-10."""
+    X, fut = _jordan_stream()
+    o = run_online(X, 8, 1e-10)
+    assert o.r == 4
+    _, V = np.linalg.eig(o.atilde())
+    assert np.linalg.cond(V) > 1e5                     # numerically defective
+    pw = O.rollout_power(o.U, o.atilde(), o.p_y, 60)
+    err = np.linalg.norm(pw - fut.T, axis=1) / np.linalg.norm(fut, axis=0).max()
+    assert err.max() < 1e-10
