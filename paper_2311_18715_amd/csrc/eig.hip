@@ -582,7 +582,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
 // of lane l's result is row 4 v + l / 16, column l % 16).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int LP = RMAX + 1;            // leading dimension of the LDS matrices
-constexpr int PC_THREADS = 256;
+constexpr int PC_THREADS = 1024;
 constexpr int PC_NWV = PC_THREADS / 64;
 constexpr int PC_NA = RMAX * RMAX / PC_THREADS;                    // A~ entries per thread
 constexpr int PC_NQ = (CMAX * LP + PC_THREADS - 1) / PC_THREADS;   // Q entries per thread
@@ -602,18 +602,23 @@ static_assert(CMAX * LP <= 2 * RMAX * LP, "Q fits the power buffers");
 // each pair of products waited for the next loads).
 template <int NT, class FA, class FB>
 __device__ __forceinline__ d4_t tile_sum(FA a, FB b) {
-  double av[4 * NT], bv[4 * NT];
-#pragma unroll
-  for (int s = 0; s < 4 * NT; ++s) {
-    av[s] = a(s);
-    bv[s] = b(s);
-  }
-  __builtin_amdgcn_sched_barrier(0);
+  constexpr int NH = NT > 2 ? 2 : 1;        // halves of the k-steps (fewer live operands)
+  constexpr int KH = 4 * NT / NH;
   d4_t d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
 #pragma unroll
-  for (int s = 0; s < 4 * NT; s += 2) {
-    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], d0, 0, 0, 0);
-    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], d1, 0, 0, 0);
+  for (int hf = 0; hf < NH; ++hf) {
+    double av[KH], bv[KH];
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      av[s] = a(hf * KH + s);
+      bv[s] = b(hf * KH + s);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < KH; s += 2) {
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], d1, 0, 0, 0);
+    }
   }
   return d0 + d1;
 }
