@@ -419,3 +419,17 @@ def test_prediction_on_a_defective_operator():
     assert np.linalg.norm(pg - fut.T, axis=1).max() < 1e-10 * scale
     pw = O.rollout_power(o.U, o.atilde(), o.p_y, 60)
     assert np.linalg.norm(pg - pw, axis=1).max() < 1e-10 * scale
+
+
+def test_rank_one_stream_rollout_across_chunks():
+    """x_k = 0.9^k v: rank 1 (one 16-row tile, a 1 x 1 A~), 1100 predicted
+    states (three read-out launches, coefficient launches of 512) equal
+    0.9^(a+k) v to 1e-12 of the largest state."""
+    n = 2048 + 37
+    v = np.random.default_rng(5).standard_normal(n)
+    X = np.stack([0.9 ** k * v for k in range(12)], axis=1)
+    g, o = run_both(X, 4, 1e-10)
+    assert g.info().r == o.r == 1
+    pg = g.predict(1100).cpu().numpy()
+    fut = np.stack([0.9 ** (11 + k) * v for k in range(1, 1101)])
+    assert np.abs(pg - fut).max() < 1e-12 * np.abs(fut).max()
