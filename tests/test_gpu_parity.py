@@ -433,3 +433,18 @@ def test_rank_one_stream_rollout_across_chunks():
     pg = g.predict(1100).cpu().numpy()
     fut = np.stack([0.9 ** (11 + k) * v for k in range(1, 1101)])
     assert np.abs(pg - fut).max() < 1e-12 * np.abs(fut).max()
+
+
+@pytest.mark.parametrize("steps", [271, 272, 273, 512, 513, 784])
+def test_rollout_at_chunk_boundaries(steps):
+    """Rank cap 40: coefficient launches of 272 steps, read-out launches of
+    512 states.  Rollouts that end just before, on and just after each
+    boundary match the oracle's state by state (1e-9 of the largest state)."""
+    s = synth.wake(nx=61, ny=39, noise=1e-6)
+    X = s.snapshots(0, 120)
+    g, o = run_both(X, 40, 1e-8)
+    assert g.info().r == o.r == 40
+    pg = g.predict(steps).cpu().numpy()
+    po = o.predict(steps)
+    err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1).max()
+    assert err.max() < 1e-9
