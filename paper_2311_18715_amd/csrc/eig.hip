@@ -579,7 +579,9 @@ __device__ __forceinline__ void eig_body(DevState* st) {
 // (U = S[:, :m] Q).  c_{k0+K} is kept in cfwd, where the next chunk starts.
 // Products are 16 x 16 FP64 matrix-core tiles (16x16x4 operand layout:
 // lane l supplies row or column l % 16 at k-step offset l / 16; element v
-// of lane l's result is row 4 v + l / 16, column l % 16).
+// of lane l's result is row 4 v + l / 16, column l % 16), spread over the
+// workgroup's 16 wavefronts: a doubling's products and its squaring are
+// one list of tiles.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int LP = RMAX + 1;            // leading dimension of the LDS matrices
 constexpr int PC_THREADS = 1024;
@@ -597,9 +599,11 @@ static_assert(CMAX * LP <= 2 * RMAX * LP, "Q fits the power buffers");
 // One 16 x 16 tile: sum over the k-steps s < 4 NT of A(s) B(s), where a(s)
 // and b(s) give this lane's operands; two accumulators over alternate
 // k-steps.  NT 16-row tiles cover the rank (entries past it are zero).
-// Every operand is loaded before the first product (the scheduling barrier
-// keeps the compiler from spreading the loads between the products, where
-// each pair of products waited for the next loads).
+// The operands of a half of the k-steps (all of them for one or two
+// tiles) are loaded before its products (the scheduling barrier keeps the
+// compiler from spreading the loads between the products, where each pair
+// of products waited for the next loads); halves keep a 1024-thread
+// workgroup within 128 registers.
 template <int NT, class FA, class FB>
 __device__ __forceinline__ d4_t tile_sum(FA a, FB b) {
   constexpr int NH = NT > 2 ? 2 : 1;        // halves of the k-steps (fewer live operands)
