@@ -74,8 +74,10 @@ class Server:
     """Request loop with HBM-budget admission and continuous batching.
 
     budget_bytes bounds the sum of the admitted streams' device state
-    (odmd_state_bytes); prediction outputs are allocated per request and
-    are not part of it.  ``backend`` is the module that provides ODMD,
+    (odmd_state_bytes); prediction outputs are not part of it: with
+    keep_outputs (the default) they are allocated per request, without it
+    they are views of max_inflight + 1 arenas of pred_bytes each, allocated
+    when the server starts (40 GB with the defaults).  ``backend`` is the module that provides ODMD,
     handle_array and update_batch_ptrs (the library binding; a stand-in can
     be passed for host-only tests of the scheduling logic)."""
 
