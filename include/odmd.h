@@ -303,7 +303,9 @@ odmd_status odmd_plan_destroy(odmd_plan_t plan);
  *   lam_re/im eigenvalues, |lambda| descending, then Im descending;
  *   v_re/v_im nullable; column j (r doubles, leading dimension r) is the
  *             eigenvector of lambda_j with unit 2-norm, scaled so that its
- *             largest-modulus entry is real and positive.
+ *             largest-modulus entry is real and positive.  Without them the
+ *             device computes the eigenvalues only (no Schur vectors or
+ *             eigenvectors; the same eigenvalues bit for bit).
  * Returns ODMD_EEMPTY at rank 0, ODMD_EINVAL if cap < r.
  */
 odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double* lam_im,

@@ -107,7 +107,7 @@ __device__ __forceinline__ bool make_reflector(double x, double y, double z, dou
 // twice.  A lane outside a role reads and writes its own slots of dum
 // instead (straight-line code, no divergent branches).  Returns this lane's
 // new H(t, k) (rows <= r1), from which the next step's (x, y, z) are taken.
-template <bool THREE>
+template <bool THREE, bool VECS>
 __device__ __forceinline__ double bulge_step(double* H, double* Z, double* dum, int n, int l, int hi,
                                              int k, double x, double y, double z) {
   constexpr int nb = THREE ? 3 : 2;
@@ -133,7 +133,7 @@ __device__ __forceinline__ double bulge_step(double* H, double* Z, double* dum, 
   }
   double cv0 = pc[0], cv1 = pc[1], cv2 = THREE ? pc[2] : 0.0;
   double rv0 = *pr0, rv1 = *pr1, rv2 = THREE ? *pr2 : 0.0;
-  double zv0 = *pz0, zv1 = *pz1, zv2 = THREE ? *pz2 : 0.0;
+  double zv0 = VECS ? *pz0 : 0.0, zv1 = VECS ? *pz1 : 0.0, zv2 = VECS && THREE ? *pz2 : 0.0;
   double tau, v1, v2 = 0.0, al;
   if (!make_reflector(x, y, THREE ? z : 0.0, tau, v1, v2, al)) return rv0;   // uniform
   // column t, rows k .. k+2 (the bulge column k - 1 becomes (alpha, 0, 0))
@@ -160,24 +160,31 @@ __device__ __forceinline__ double bulge_step(double* H, double* Z, double* dum, 
   rv0 -= sr;
   rv1 -= sr * v1;
   rv2 -= sr * v2;
-  const double sz = tau * (zv0 + v1 * zv1 + v2 * zv2);
-  zv0 -= sz;
-  zv1 -= sz * v1;
-  zv2 -= sz * v2;
+  if (VECS) {
+    const double sz = tau * (zv0 + v1 * zv1 + v2 * zv2);
+    zv0 -= sz;
+    zv1 -= sz * v1;
+    zv2 -= sz * v2;
+  }
   pc[0] = cv0;
   pc[1] = cv1;
   if (THREE) pc[2] = cv2;
   *pr0 = rv0;
   *pr1 = rv1;
   if (THREE) *pr2 = rv2;
-  *pz0 = zv0;
-  *pz1 = zv1;
-  if (THREE) *pz2 = zv2;
+  if (VECS) {
+    *pz0 = zv0;
+    *pz1 = zv1;
+    if (THREE) *pz2 = zv2;
+  }
   return rv0;
 }
 
+// VECS false: eigenvalues only (no Z, eigenvectors or V); the cache level
+// eig_valid is 1 after such a call and 2 after a call with vectors.
+template <bool VECS>
 __device__ __forceinline__ void eig_body(DevState* st) {
-  if (st->eig_valid) return;
+  if (st->eig_valid >= (VECS ? 2 : 1)) return;
   __shared__ double H[RMAX * LDH];
   __shared__ double Z[RMAX * LDH];
   __shared__ double Xr[(RMAX + 1) * LDH];
@@ -189,7 +196,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   const int n = st->r;
   if (n == 0) {
     if (t == 0) {
-      st->eig_valid = 1;
+      st->eig_valid = 2;
       st->eig_status = 0;
     }
     return;
@@ -197,7 +204,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   for (int idx = t; idx < n * n; idx += 64) {
     const int i = idx % n, j = idx / n;
     Hm(i, j) = st->At[j * RMAX + i];
-    Zm(i, j) = (i == j) ? 1.0 : 0.0;
+    if (VECS) Zm(i, j) = (i == j) ? 1.0 : 0.0;
   }
   if (t == 0) sfail = 0;
   __syncthreads();
@@ -239,20 +246,22 @@ __device__ __forceinline__ void eig_body(DevState* st) {
 #pragma unroll 4
       for (; j + 1 < n; j += 2) {
         s = __builtin_fma(Hm(t, j), hv[j], s);
-        sz = __builtin_fma(Zm(t, j), hv[j], sz);
         s2 = __builtin_fma(Hm(t, j + 1), hv[j + 1], s2);
-        sz2 = __builtin_fma(Zm(t, j + 1), hv[j + 1], sz2);
+        if (VECS) {
+          sz = __builtin_fma(Zm(t, j), hv[j], sz);
+          sz2 = __builtin_fma(Zm(t, j + 1), hv[j + 1], sz2);
+        }
       }
       if (j < n) {
         s = __builtin_fma(Hm(t, j), hv[j], s);
-        sz = __builtin_fma(Zm(t, j), hv[j], sz);
+        if (VECS) sz = __builtin_fma(Zm(t, j), hv[j], sz);
       }
       s = (s + s2) * beta;
       sz = (sz + sz2) * beta;
 #pragma unroll 8
       for (int j = k + 1; j < n; ++j) {
         Hm(t, j) -= s * hv[j];
-        Zm(t, j) -= sz * hv[j];
+        if (VECS) Zm(t, j) -= sz * hv[j];
       }
     }
     __syncthreads();
@@ -318,7 +327,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
             Hm(t, p) = cs * u + sn * v;
             Hm(t, q) = -sn * u + cs * v;
           }
-          if (t < n) {
+          if (VECS && t < n) {
             const double u = Zm(t, p), v = Zm(t, q);
             Zm(t, p) = cs * u + sn * v;
             Zm(t, q) = -sn * u + cs * v;
@@ -368,20 +377,20 @@ __device__ __forceinline__ void eig_body(DevState* st) {
     // Bulge chase: one barrier per step; the next step's (x, y, z), the new
     // H(k+1 .. k+3, k), come from the registers of the lanes of those rows.
     for (int k = l; k < hi - 1; ++k) {
-      const double colk = bulge_step<true>(H, Z, dum, n, l, hi, k, x, y, z);
+      const double colk = bulge_step<true, VECS>(H, Z, dum, n, l, hi, k, x, y, z);
       x = readlane_d(colk, k + 1);
       y = readlane_d(colk, k + 2);
       z = (k + 3 <= hi) ? readlane_d(colk, k + 3) : 0.0;
       __syncthreads();
     }
-    bulge_step<false>(H, Z, dum, n, l, hi, hi - 1, x, y, 0.0);
+    bulge_step<false, VECS>(H, Z, dum, n, l, hi, hi - 1, x, y, 0.0);
     __syncthreads();
   }
   __syncthreads();
 
   // 3. eigenvectors of the quasi-triangular T by back-substitution
   const double smin = fmax(EPS * hn, 1e-300);
-  if (t < n && !sfail) {
+  if (VECS && t < n && !sfail) {
     const cplx lam = {wr[t], wi[t]};
     for (int i = 0; i < n; ++i) {
       Xr[t * LDH + i] = 0.0;
@@ -483,7 +492,8 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   }
   __syncthreads();
 
-  // V = Z X, normalised, stored at its rank in the output order
+  // the eigenvalues at their rank in the output order; with vectors,
+  // V = Z X normalised, at the same rank
   if (t < n) hv[t] = hypot(wr[t], wi[t]);    // |lambda| (hv is free after the reduction)
   __syncthreads();
   if (t < n && !sfail) {
@@ -493,68 +503,70 @@ __device__ __forceinline__ void eig_body(DevState* st) {
       const double mj = hv[j];
       rank += (mj > ml) || (mj == ml && (wi[j] > wi[t] || (wi[j] == wi[t] && j < t)));
     }
-    double* __restrict__ vr = st->V_re + rank * RMAX;
-    double* __restrict__ vi = st->V_im + rank * RMAX;
-    // entries i0 .. i0+3 of Z X[:, t]: one load of x_j serves four rows of
-    // Z (rows past n read row 0 and are not used)
-    auto zx4 = [&](int i0, double (&ar)[4], double (&ai)[4]) {
-      int ir[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ar[u] = 0.0;
-        ai[u] = 0.0;
-        ir[u] = i0 + u < n ? i0 + u : 0;
-      }
-      for (int j = 0; j < n; ++j) {
-        const double xr = Xr[t * LDH + j], xi = Xi[t * LDH + j];
+    st->lam_re[rank] = wr[t];
+    st->lam_im[rank] = wi[t];
+    if (VECS) {
+      double* __restrict__ vr = st->V_re + rank * RMAX;
+      double* __restrict__ vi = st->V_im + rank * RMAX;
+      // entries i0 .. i0+3 of Z X[:, t]: one load of x_j serves four rows of
+      // Z (rows past n read row 0 and are not used)
+      auto zx4 = [&](int i0, double (&ar)[4], double (&ai)[4]) {
+        int ir[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const double z = Zm(ir[u], j);
-          ar[u] = __builtin_fma(z, xr, ar[u]);
-          ai[u] = __builtin_fma(z, xi, ai[u]);
+          ar[u] = 0.0;
+          ai[u] = 0.0;
+          ir[u] = i0 + u < n ? i0 + u : 0;
+        }
+        for (int j = 0; j < n; ++j) {
+          const double xr = Xr[t * LDH + j], xi = Xi[t * LDH + j];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double z = Zm(ir[u], j);
+            ar[u] = __builtin_fma(z, xr, ar[u]);
+            ai[u] = __builtin_fma(z, xi, ai[u]);
+          }
+        }
+      };
+      // first pass: the norm and the largest-modulus entry; the second forms
+      // the entries again (bit for bit) and writes them normalised
+      double nrm2 = 0.0, best = -1.0, vbr = 0.0, vbi = 0.0;
+      int ib = 0;
+      for (int i0 = 0; i0 < n; i0 += 4) {
+        double ar[4], ai[4];
+        zx4(i0, ar, ai);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (i0 + u < n) {
+            const double m2 = ar[u] * ar[u] + ai[u] * ai[u];
+            nrm2 += m2;
+            if (m2 > best) {
+              best = m2;
+              ib = i0 + u;
+              vbr = ar[u];
+              vbi = ai[u];
+            }
+          }
         }
       }
-    };
-    // first pass: the norm and the largest-modulus entry; the second forms
-    // the entries again (bit for bit) and writes them normalised
-    double nrm2 = 0.0, best = -1.0, vbr = 0.0, vbi = 0.0;
-    int ib = 0;
-    for (int i0 = 0; i0 < n; i0 += 4) {
-      double ar[4], ai[4];
-      zx4(i0, ar, ai);
+      // unit norm, largest-modulus entry real and positive: multiply by
+      // conj(v_ib) / (|v_ib| ||v||)
+      const double m = sqrt(best), f = 1.0 / sqrt(nrm2);
+      const double pr = vbr / m * f, pi = -vbi / m * f;
+                                               // V[:, rank] = (Z X[:, t]) (pr + i pi)
+      for (int i0 = 0; i0 < n; i0 += 4) {
+        double ar[4], ai[4];
+        zx4(i0, ar, ai);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (i0 + u < n) {
-          const double m2 = ar[u] * ar[u] + ai[u] * ai[u];
-          nrm2 += m2;
-          if (m2 > best) {
-            best = m2;
-            ib = i0 + u;
-            vbr = ar[u];
-            vbi = ai[u];
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u;
+          if (i < n) {
+            vr[i] = ar[u] * pr - ai[u] * pi;
+            vi[i] = i == ib ? 0.0 : ar[u] * pi + ai[u] * pr;
           }
         }
       }
     }
-    // unit norm, largest-modulus entry real and positive: multiply by
-    // conj(v_ib) / (|v_ib| ||v||)
-    const double m = sqrt(best), f = 1.0 / sqrt(nrm2);
-    const double pr = vbr / m * f, pi = -vbi / m * f;
-                                             // V[:, rank] = (Z X[:, t]) (pr + i pi)
-    for (int i0 = 0; i0 < n; i0 += 4) {
-      double ar[4], ai[4];
-      zx4(i0, ar, ai);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u;
-        if (i < n) {
-          vr[i] = ar[u] * pr - ai[u] * pi;
-          vi[i] = i == ib ? 0.0 : ar[u] * pi + ai[u] * pr;
-        }
-      }
-    }
-    st->lam_re[rank] = wr[t];
-    st->lam_im[rank] = wi[t];
   }
   __threadfence();
   __syncthreads();
@@ -562,7 +574,7 @@ __device__ __forceinline__ void eig_body(DevState* st) {
   if (t == 0) {
     st->eig_status = sfail;
     if (sfail) latch_status(st, ST_NOCONV);
-    st->eig_valid = 1;
+    st->eig_valid = VECS ? 2 : 1;
   }
 }
 
@@ -785,10 +797,12 @@ __global__ __launch_bounds__(256) void k_basis_coef(DevState* st) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_eig(DevState* st) { eig_body(st); }
+template <bool VECS>
+__global__ __launch_bounds__(64) void k_eig(DevState* st) { eig_body<VECS>(st); }
 
-hipError_t launch_eig(DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_eig(DevState* st, bool vectors, hipStream_t s) {
+  if (vectors) hipLaunchKernelGGL(k_eig<true>, dim3(1), dim3(64), 0, s, st);
+  else hipLaunchKernelGGL(k_eig<false>, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

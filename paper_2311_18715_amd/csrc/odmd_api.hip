@@ -1039,7 +1039,7 @@ odmd_status odmd_eigs(odmd_t h, int32_t cap, int32_t* r, double* lam_re, double*
   if (!h || !r || !lam_re || !lam_im || cap < 0) return ODMD_EINVAL;
   if ((v_re == nullptr) != (v_im == nullptr)) return ODMD_EINVAL;
   HIP_OK(hipSetDevice(h->device));
-  HIP_OK(launch_eig(h->st, h->stream));
+  HIP_OK(launch_eig(h->st, v_re != nullptr, h->stream));
   int rr = 0;
   std::vector<double> lr(RMAX), li(RMAX), vr, vi;
   odmd_status s;

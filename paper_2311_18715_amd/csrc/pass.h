@@ -123,7 +123,8 @@ struct CombineArgs {
 hipError_t launch_combine(const CombineArgs& c, int basis, int out_f32, int rb, hipStream_t s);
 
 hipError_t launch_basis_coef(DevState* st, hipStream_t s);
-hipError_t launch_eig(DevState* st, hipStream_t s);
+// eigenvalues, and with vectors the unit eigenvectors V (cached per model)
+hipError_t launch_eig(DevState* st, bool vectors, hipStream_t s);
 // prediction coefficients of steps k0+1 .. k0+steps (steps <= coef_chunk(r_max))
 // into columns koff .. koff+steps-1 of the read-out coefficients
 hipError_t launch_power_coef(DevState* st, int k0, int steps, int koff, hipStream_t s);

@@ -448,3 +448,25 @@ def test_rollout_at_chunk_boundaries(steps):
     po = o.predict(steps)
     err = np.linalg.norm(pg - po, axis=1) / np.linalg.norm(po, axis=1).max()
     assert err.max() < 1e-9
+
+
+def test_eigenvalues_alone_equal_those_with_vectors():
+    """odmd_eigs without vectors runs the eigensolver without Z, the
+    eigenvectors and V: its eigenvalues equal those of a call with vectors
+    bit for bit (Z does not enter H's iteration), a call with vectors after
+    a values-only call recomputes, a values-only call after it reuses the
+    cache, and an update invalidates both."""
+    s = synth.wake(nx=61, ny=39, noise=1e-6)
+    X = s.snapshots(0, 122)
+    g, o = run_both(X, 40, 1e-8, steps=120)
+    lam1 = g.eigs(vectors=False)[0]
+    lam2, V = g.eigs(vectors=True)
+    assert np.array_equal(lam1, lam2)
+    assert np.array_equal(g.eigs(vectors=False)[0], lam2)
+    A = g.state()["atilde"]
+    assert np.linalg.norm(A @ V - V * lam2[None, :]) < 1e-10 * np.linalg.norm(A)
+    Xd = dev(X, torch.float64)
+    g.update(Xd[120], Xd[121])
+    lam3 = g.eigs(vectors=False)[0]
+    lam4, _ = g.eigs(vectors=True)
+    assert np.array_equal(lam3, lam4) and not np.array_equal(lam3, lam1)
